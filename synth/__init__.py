@@ -1,0 +1,247 @@
+"""Seeded synthetic inputs for DG-CheFSI workloads.
+
+This module only *draws* inputs: periodic element grids, per-element ALB
+counts J_K, the stored nonzero blocks H_{K;K'} of a symmetric block-sparse
+DG-shaped Hamiltonian, start blocks X and Lanczos start vectors.  It holds
+none of the method's arithmetic (no filter, no orthonormalisation, no
+Rayleigh-Ritz); both the CPU oracle and the GPU library consume what it makes.
+
+Problem shape (Sec. II A of the paper, eqs. for the block structure of H^DG):
+  * the domain is a periodic nx x ny x nz grid of elements, element id
+    K = ix + nx*(iy + ny*iz);
+  * element K carries J_K basis functions, its rows of any multivector are
+    contiguous (element-major row order), N = sum_K J_K;
+  * H_{K;K'} (J_K x J_K') is nonzero only for face neighbours K' of K.
+
+Stored-block convention ("slot" order): every element stores one block per
+stencil direction, in the order self, -x, +x, -y, +y, -z, +z (7-point
+stencil) or self, -x, +x, -y, +y (5-point, in-plane sheets).  A periodic
+dimension of length 2 reaches the same neighbour through two slots and a
+length-1 dimension reaches the element itself; such blocks *add* when the
+dense matrix is formed.  Element K owns its +x/+y/+z faces: the +d block is
+drawn as G and the -d block of the neighbour is G^T, which makes the dense
+matrix exactly (bitwise) symmetric.
+
+Value distributions: diagonal blocks Q diag(lambda) Q^T with lambda ~ U[lo, hi]
+and Q Haar-random (QR of a Gaussian matrix with the signs of diag(R) folded
+in, Mezzadri 2007), symmetrised; off-diagonal blocks i.i.d. N(0, sigma^2).
+
+Packed ("block-list") layout handed to the library: for K = 0..M-1, for each
+slot s, the J_K x J_{K'_s} block in row-major order, back to back, float64.
+
+Random streams: numpy SeedSequence(base_seed, spawn_key=(purpose, K)), so any
+element's data can be regenerated on its own.  Purposes: 0 eigenvalues,
+1 Haar Q, 2 off-diagonal blocks, 3 start block X, 4 Lanczos start vector,
+5 mixed J_K draw, 6 finite-difference entry choice.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+BASE_SEED = 1606
+
+# slot order: self, -x, +x, -y, +y, -z, +z
+SLOT_DIRS = ((0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1))
+
+PURPOSE_EIG, PURPOSE_HAAR, PURPOSE_OFFDIAG, PURPOSE_X0, PURPOSE_LANCZOS, PURPOSE_JDRAW, PURPOSE_FD = range(7)
+
+
+def rng_for(purpose: int, key: int = 0, base_seed: int = BASE_SEED) -> np.random.Generator:
+    ss = np.random.SeedSequence(base_seed, spawn_key=(int(purpose), int(key)))
+    return np.random.Generator(np.random.PCG64(ss))
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One synthetic workload shape (grid, stencil, ALB counts, states, degree)."""
+    name: str
+    grid: Tuple[int, int, int]
+    stencil: int
+    nb: Optional[int]                 # uniform ALBs per element, or None for a mixed draw
+    nb_choices: Optional[Tuple[int, ...]] = None
+    ns: int = 48
+    m: int = 10
+    sweeps: int = 1
+    lanczos_steps: int = 20
+    lam_lo: float = -0.5
+    lam_hi: float = 4.0
+    sigma_off: float = 0.05
+
+    @property
+    def M(self) -> int:
+        return self.grid[0] * self.grid[1] * self.grid[2]
+
+
+# The five workload shapes of the build (tiny, differentiation, bulk 3D,
+# bulk 3D mixed precision, 2D sheet with uneven ALB counts).
+TINY = Workload("tiny_2x2x2_nb32", (2, 2, 2), 7, 32, ns=48, m=10, sweeps=5)
+DIFF = Workload("diff_6x6x6_nb48", (6, 6, 6), 7, 48, ns=512, m=12, sweeps=1)
+BULK = Workload("bulk_12x12x12_nb64", (12, 12, 12), 7, 64, ns=4096, m=16, sweeps=4)
+SHEET = Workload("sheet_48x40x1_nb64-128", (48, 40, 1), 5, None,
+                 nb_choices=tuple(range(64, 129, 8)), ns=8192, m=20, sweeps=4)
+WORKLOADS = {w.name: w for w in (TINY, DIFF, BULK, SHEET)}
+
+
+def element_id(ix: int, iy: int, iz: int, grid: Sequence[int]) -> int:
+    nx, ny, nz = grid
+    return (ix % nx) + nx * ((iy % ny) + ny * (iz % nz))
+
+
+def element_coords(K: int, grid: Sequence[int]) -> Tuple[int, int, int]:
+    nx, ny, _ = grid
+    return K % nx, (K // nx) % ny, K // (nx * ny)
+
+
+def slot_neighbour(K: int, s: int, grid: Sequence[int]) -> int:
+    ix, iy, iz = element_coords(K, grid)
+    dx, dy, dz = SLOT_DIRS[s]
+    return element_id(ix + dx, iy + dy, iz + dz, grid)
+
+
+def draw_alb_counts(w: Workload, base_seed: int = BASE_SEED) -> np.ndarray:
+    if w.nb is not None:
+        return np.full(w.M, w.nb, dtype=np.int32)
+    choices = np.asarray(w.nb_choices, dtype=np.int32)
+    g = rng_for(PURPOSE_JDRAW, 0, base_seed)
+    return choices[g.integers(0, len(choices), size=w.M)].astype(np.int32)
+
+
+def haar_orthogonal(n: int, g: np.random.Generator) -> np.ndarray:
+    z = g.standard_normal((n, n))
+    q, r = np.linalg.qr(z)
+    return q * np.sign(np.diag(r))[None, :]
+
+
+@dataclasses.dataclass
+class BlockProblem:
+    """Stored blocks of a block-sparse H plus its shape data."""
+    grid: Tuple[int, int, int]
+    stencil: int
+    J: np.ndarray                     # int32 [M]
+    blocks: List[List[np.ndarray]]    # blocks[K][s], J_K x J_{K'_s}, float64
+    eigs: Optional[List[np.ndarray]] = None   # drawn diagonal-block spectra (if any)
+
+    @property
+    def M(self) -> int:
+        return len(self.J)
+
+    @property
+    def N(self) -> int:
+        return int(np.sum(self.J, dtype=np.int64))
+
+    def row_offsets(self) -> np.ndarray:
+        off = np.zeros(self.M + 1, dtype=np.int64)
+        np.cumsum(self.J, out=off[1:])
+        return off
+
+    def packed(self, dtype=np.float64) -> np.ndarray:
+        """Block-list layout: element-major, slot-minor, each block row-major."""
+        parts = [b.ravel() for row in self.blocks for b in row]
+        return np.concatenate(parts).astype(dtype, copy=False)
+
+    def packed_size(self) -> int:
+        return sum(b.size for row in self.blocks for b in row)
+
+    @staticmethod
+    def from_packed(grid, stencil, J, flat: np.ndarray) -> "BlockProblem":
+        J = np.asarray(J, dtype=np.int32)
+        M = len(J)
+        blocks, pos = [], 0
+        for K in range(M):
+            row = []
+            for s in range(stencil):
+                Kp = slot_neighbour(K, s, grid)
+                n = int(J[K]) * int(J[Kp])
+                row.append(np.asarray(flat[pos:pos + n], dtype=np.float64).reshape(int(J[K]), int(J[Kp])))
+                pos += n
+            blocks.append(row)
+        return BlockProblem(tuple(grid), stencil, J, blocks)
+
+
+def make_blocks(grid: Sequence[int], stencil: int, J: np.ndarray, *,
+                lam_lo: float = -0.5, lam_hi: float = 4.0, sigma_off: float = 0.05,
+                diag_kind: str = "haar", base_seed: int = BASE_SEED) -> BlockProblem:
+    """Draw the stored blocks.
+
+    diag_kind: "haar"   -> Q diag(lambda) Q^T, lambda ~ U[lam_lo, lam_hi]
+               "diag"   -> diag(lambda) (no rotation)
+    sigma_off = 0 gives a decoupled (block-diagonal) H.
+    """
+    grid = tuple(int(v) for v in grid)
+    assert stencil in (5, 7)
+    J = np.asarray(J, dtype=np.int32)
+    M = grid[0] * grid[1] * grid[2]
+    assert len(J) == M
+    blocks: List[List[Optional[np.ndarray]]] = [[None] * stencil for _ in range(M)]
+    eigs = []
+    for K in range(M):
+        n = int(J[K])
+        lam = rng_for(PURPOSE_EIG, K, base_seed).uniform(lam_lo, lam_hi, size=n)
+        eigs.append(lam)
+        if diag_kind == "haar":
+            Q = haar_orthogonal(n, rng_for(PURPOSE_HAAR, K, base_seed))
+            B = (Q * lam[None, :]) @ Q.T
+            B = 0.5 * (B + B.T)
+        elif diag_kind == "diag":
+            B = np.diag(lam)
+        else:
+            raise ValueError(diag_kind)
+        blocks[K][0] = B
+    # owned faces: +x (slot 2), +y (slot 4), +z (slot 6); the neighbour's
+    # opposite slot gets the transpose.
+    owned = (2, 4, 6) if stencil == 7 else (2, 4)
+    for K in range(M):
+        g = rng_for(PURPOSE_OFFDIAG, K, base_seed)
+        for s in owned:
+            Kp = slot_neighbour(K, s, grid)
+            G = g.normal(0.0, 1.0, size=(int(J[K]), int(J[Kp]))) * sigma_off
+            blocks[K][s] = G
+            blocks[Kp][s - 1] = G.T.copy()
+    return BlockProblem(grid, stencil, J, blocks, eigs)
+
+
+def make_scalar_lattice(grid: Sequence[int], stencil: int, nb: int, d: float, t: float) -> BlockProblem:
+    """Diagonal blocks d*I and every stored off-diagonal block t*I."""
+    grid = tuple(int(v) for v in grid)
+    M = grid[0] * grid[1] * grid[2]
+    J = np.full(M, nb, dtype=np.int32)
+    blocks = [[(d if s == 0 else t) * np.eye(nb) for s in range(stencil)] for _ in range(M)]
+    return BlockProblem(grid, stencil, J, blocks)
+
+
+def make_problem(w: Workload, base_seed: int = BASE_SEED, **kw) -> BlockProblem:
+    J = draw_alb_counts(w, base_seed)
+    return make_blocks(w.grid, w.stencil, J, lam_lo=w.lam_lo, lam_hi=w.lam_hi,
+                       sigma_off=w.sigma_off, base_seed=base_seed, **kw)
+
+
+def make_start_block(J: np.ndarray, ns: int, base_seed: int = BASE_SEED, dtype=np.float64) -> np.ndarray:
+    """X0 ~ N(0,1), N x ns, drawn element by element (rows of element K)."""
+    J = np.asarray(J)
+    N = int(np.sum(J, dtype=np.int64))
+    X = np.empty((N, ns), dtype=dtype)
+    r = 0
+    for K, n in enumerate(J):
+        n = int(n)
+        X[r:r + n] = rng_for(PURPOSE_X0, K, base_seed).standard_normal((n, ns))
+        r += n
+    return X
+
+
+def make_lanczos_start(N: int, base_seed: int = BASE_SEED) -> np.ndarray:
+    return rng_for(PURPOSE_LANCZOS, 0, base_seed).standard_normal(N)
+
+
+def fd_entries(P: BlockProblem, count: int, base_seed: int = BASE_SEED):
+    """Random (K, s, i, j) positions of stored blocks for finite-difference checks."""
+    g = rng_for(PURPOSE_FD, 0, base_seed)
+    out = []
+    for _ in range(count):
+        K = int(g.integers(0, P.M))
+        s = int(g.integers(0, P.stencil))
+        b = P.blocks[K][s]
+        out.append((K, s, int(g.integers(0, b.shape[0])), int(g.integers(0, b.shape[1]))))
+    return out
