@@ -1,0 +1,19 @@
+"""MI355X (gfx950) DG-CheFSI: Chebyshev-filtered subspace iteration on a
+block-sparse DG Hamiltonian, as a C-ABI HIP library with a thin Python binding.
+
+The binding only marshals arguments: torch tensors provide device memory and
+the current stream, every step of the method runs in libchefsi.so.  Importing
+this package loads the library and fails loudly if it is missing.
+
+    import paper_1606_03416_amd as chefsi
+    plan = chefsi.Plan((12, 12, 12), 7, J)            # element grid, stencil, ALB counts
+    Y = plan.filter(H, X, m, a, b, a0)                 # Algorithm 1 step 2
+    U = chefsi.orthonormalize(Y, passes=2)             # step 3 (in place)
+    Xn, ritz, resid, Q = plan.rayleigh_ritz(H, Y)      # steps 4-5
+    plan.sweep(H, X, m, v0=v0, ritz=ritz, ...)         # steps 1-5
+"""
+from ._binding import (  # noqa: F401
+    ChefsiError, Plan, orthonormalize, library_path, lib,
+    F64, F32, BF16, OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP,
+    OP_FILTER_BACKWARD, OP_LOSS_BACKWARD, ERR_NOT_PD, ERR_ARG, ERR_WORKSPACE, ERR_EIG,
+)

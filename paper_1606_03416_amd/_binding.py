@@ -1,0 +1,261 @@
+"""ctypes binding of libchefsi.so (argument marshalling only).
+
+torch is imported first so that the HIP runtime it ships is the one the
+library binds to (both carry the soname libamdhip64.so.7).  Tensors must be
+float64 CUDA tensors whose rows are contiguous (stride(1) == 1); the row
+stride is passed as the leading dimension.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libchefsi.so")
+if not os.path.exists(library_path):
+    raise ImportError(f"{library_path} is not built; run paper_1606_03416_amd.build.build()")
+lib = ctypes.CDLL(library_path)
+
+F64, F32, BF16 = 0, 1, 2
+OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP, OP_FILTER_BACKWARD, OP_LOSS_BACKWARD = range(7)
+ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_NOT_PD, ERR_EIG, ERR_NONFINITE, ERR_UNSUPPORTED = range(1, 8)
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_sz = ctypes.c_size_t
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("bounds_ms", _d), ("filter_ms", _d), ("filter_steps_ms", _d),
+                ("orthonormalize_ms", _d), ("rayleigh_ritz_ms", _d), ("total_ms", _d)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _sig(name, res, *args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("chefsi_version", ctypes.c_char_p)
+_sig("chefsi_last_error", ctypes.c_char_p)
+_sig("chefsi_plan_create", _i, ctypes.POINTER(_vp), _i, _i, _i, _i, ctypes.POINTER(ctypes.c_int32))
+_sig("chefsi_plan_destroy", None, _vp)
+_sig("chefsi_plan_n", _i64, _vp)
+_sig("chefsi_plan_h_elems", _i64, _vp)
+_sig("chefsi_plan_neighbour", _i, _vp, _i, _i)
+_sig("chefsi_workspace_bytes", _i, _vp, _i, _i, _i, _i, _i, ctypes.POINTER(_sz))
+_sig("chefsi_bounds", _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _dp, _vp, _sz, _vp)
+_sig("chefsi_filter", _i, _vp, _vp, _i, _d, _d, _d, _i, _vp, _i64, _vp, _i64, _i, _vp, _sz, _vp)
+_sig("chefsi_orthonormalize", _i, _i64, _i, _vp, _i64, _i, _vp, _vp, _sz, _vp)
+_sig("chefsi_orthonormalize_workspace_bytes", _i, _i64, _i, _i, ctypes.POINTER(_sz))
+_sig("chefsi_rayleigh_ritz", _i, _vp, _vp, _vp, _i64, _i, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp)
+_sig("chefsi_sweep", _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _i, _vp, _i64, _i, _vp, _vp, _vp,
+     ctypes.POINTER(Stats), _vp, _sz, _vp)
+_sig("chefsi_loss_backward", _i, _vp, _vp, _i, _d, _d, _d, _i, _i, _i, _vp, _i64, _i, _vp, _vp, _i64,
+     _dp, _vp, _sz, _vp)
+_sig("chefsi_filter_backward", _i, _vp, _vp, _i, _d, _d, _d, _i, _vp, _i64, _vp, _i64, _i, _vp, _vp,
+     _i64, _vp, _sz, _vp)
+
+
+class ChefsiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"chefsi error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise ChefsiError(rc, lib.chefsi_last_error().decode(errors="replace"))
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _mv(t: torch.Tensor, name: str, dtype=torch.float64) -> int:
+    if not t.is_cuda or t.dtype != dtype or t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D {dtype} CUDA tensor with contiguous rows")
+    return t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+
+
+def _vec(t: torch.Tensor, name: str, n: int):
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of >= {n} elements")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Plan:
+    """Element grid + stencil + ALB counts (the structure of H^DG)."""
+
+    def __init__(self, grid, stencil: int, J):
+        J = np.ascontiguousarray(np.asarray(J), dtype=np.int32)
+        nx, ny, nz = (int(v) for v in grid)
+        self.grid, self.stencil, self.J = (nx, ny, nz), int(stencil), J
+        self._h = _vp()
+        _check(lib.chefsi_plan_create(ctypes.byref(self._h), nx, ny, nz, int(stencil),
+                                      J.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        self.N = int(lib.chefsi_plan_n(self._h))
+        self.h_elems = int(lib.chefsi_plan_h_elems(self._h))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.chefsi_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def neighbour(self, K: int, s: int) -> int:
+        return int(lib.chefsi_plan_neighbour(self._h, K, s))
+
+    def workspace_bytes(self, op: int, ns: int, dtype: int = F64, passes: int = 2, lanczos_steps: int = 20) -> int:
+        out = _sz(0)
+        _check(lib.chefsi_workspace_bytes(self._h, op, ns, dtype, passes, lanczos_steps, ctypes.byref(out)))
+        return int(out.value)
+
+    def _check_H(self, H: torch.Tensor):
+        if not H.is_cuda or H.dtype != torch.float64 or not H.is_contiguous() or H.numel() != self.h_elems:
+            raise ValueError(f"H must be a contiguous float64 CUDA tensor of {self.h_elems} elements")
+
+    # -- Algorithm 1 step 1
+    def bounds(self, H, v0, lanczos_steps: int = 20, ritz_prev=None, ns: Optional[int] = None,
+               out: Optional[torch.Tensor] = None) -> Tuple[float, float, float]:
+        self._check_H(H)
+        _vec(v0, "v0", self.N)
+        if ritz_prev is not None:
+            ns = ritz_prev.numel()
+            _vec(ritz_prev, "ritz_prev", ns)
+        if ns is None:
+            raise ValueError("ns is required for first-cycle bounds")
+        ws = _workspace(self.workspace_bytes(OP_BOUNDS, ns, lanczos_steps=lanczos_steps), H.device)
+        hb = (ctypes.c_double * 3)()
+        _check(lib.chefsi_bounds(self._h, _p(H), _p(v0), lanczos_steps, _p(ritz_prev), ns, _p(out),
+                                 hb, _p(ws), ws.numel(), _stream()))
+        return float(hb[0]), float(hb[1]), float(hb[2])
+
+    # -- Algorithm 1 step 2
+    def filter(self, H, X, m: int, a: float, b: float, a0: float, dtype: int = F64,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check_H(H)
+        ldx = _mv(X, "X")
+        ns = X.shape[1]
+        if out is None:
+            out = torch.empty((self.N, ns), dtype=torch.float64, device=X.device)
+        ldy = _mv(out, "out")
+        ws = _workspace(self.workspace_bytes(OP_FILTER, ns, dtype), X.device)
+        _check(lib.chefsi_filter(self._h, _p(H), m, a, b, a0, dtype, _p(X), ldx, _p(out), ldy, ns,
+                                 _p(ws), ws.numel(), _stream()))
+        return out
+
+    # -- Algorithm 1 steps 4-5
+    def rayleigh_ritz(self, H, Yhat, out: Optional[torch.Tensor] = None, want_Q: bool = False,
+                      want_resid: bool = True):
+        self._check_H(H)
+        ldy = _mv(Yhat, "Yhat")
+        ns = Yhat.shape[1]
+        dev = Yhat.device
+        if out is None:
+            out = torch.empty((self.N, ns), dtype=torch.float64, device=dev)
+        ldx = _mv(out, "out")
+        ritz = torch.empty(ns, dtype=torch.float64, device=dev)
+        resid = torch.empty(ns, dtype=torch.float64, device=dev) if want_resid else None
+        Q = torch.empty((ns, ns), dtype=torch.float64, device=dev) if want_Q else None
+        ws = _workspace(self.workspace_bytes(OP_RAYLEIGH_RITZ, ns), dev)
+        _check(lib.chefsi_rayleigh_ritz(self._h, _p(H), _p(Yhat), ldy, ns, _p(out), ldx, _p(ritz),
+                                        _p(resid), _p(Q), _p(ws), ws.numel(), _stream()))
+        return out, ritz, resid, Q
+
+    # -- Algorithm 1, one full cycle
+    def sweep(self, H, X, m: int, *, dtype: int = F64, passes: int = 2, lanczos_steps: int = 20,
+              v0=None, bounds=None, ritz=None, warm: bool = False, want_resid: bool = True,
+              stats: bool = False, ws: Optional[torch.Tensor] = None):
+        """X is updated in place; returns (ritz, resid, bounds_used, stats_dict|None)."""
+        self._check_H(H)
+        ldx = _mv(X, "X")
+        ns = X.shape[1]
+        dev = X.device
+        if ritz is None:
+            ritz = torch.empty(ns, dtype=torch.float64, device=dev)
+        resid = torch.empty(ns, dtype=torch.float64, device=dev) if want_resid else None
+        bout = torch.empty(3, dtype=torch.float64, device=dev)
+        if bounds is not None and not torch.is_tensor(bounds):
+            bounds = torch.tensor(list(bounds), dtype=torch.float64, device=dev)
+        need = self.workspace_bytes(OP_SWEEP, ns, dtype, passes, lanczos_steps)
+        if ws is None or ws.numel() < need:
+            ws = _workspace(need, dev)
+        st = Stats()
+        _check(lib.chefsi_sweep(self._h, _p(H), m, dtype, passes, lanczos_steps, _p(v0), _p(bounds),
+                                1 if warm else 0, _p(X), ldx, ns, _p(ritz), _p(resid), _p(bout),
+                                ctypes.byref(st) if stats else None, _p(ws), ws.numel(), _stream()))
+        return ritz, resid, bout, (st.as_dict() if stats else None)
+
+    # -- adjoint of one filter + Cholesky-QR + Rayleigh-Ritz pass
+    def loss_backward(self, H, X, m: int, a: float, b: float, a0: float, k: int, passes: int = 2,
+                      ckpt_stride: int = 4):
+        self._check_H(H)
+        ldx = _mv(X, "X")
+        ns = X.shape[1]
+        dev = X.device
+        Hbar = torch.empty_like(H)
+        Xbar = torch.empty((self.N, ns), dtype=torch.float64, device=dev)
+        ws = _workspace(self.workspace_bytes(OP_LOSS_BACKWARD, ns, F64, passes), dev)
+        loss = ctypes.c_double(0.0)
+        _check(lib.chefsi_loss_backward(self._h, _p(H), m, a, b, a0, passes, k, ckpt_stride, _p(X), ldx,
+                                        ns, _p(Hbar), _p(Xbar), Xbar.stride(0), ctypes.byref(loss),
+                                        _p(ws), ws.numel(), _stream()))
+        return float(loss.value), Hbar, Xbar
+
+    def filter_backward(self, H, X, Ybar, m: int, a: float, b: float, a0: float, ckpt_stride: int = 4,
+                        Hbar: Optional[torch.Tensor] = None):
+        self._check_H(H)
+        ldx = _mv(X, "X")
+        ldyb = _mv(Ybar, "Ybar")
+        ns = X.shape[1]
+        dev = X.device
+        if Hbar is None:
+            Hbar = torch.zeros_like(H)
+        Xbar = torch.empty((self.N, ns), dtype=torch.float64, device=dev)
+        ws = _workspace(self.workspace_bytes(OP_FILTER_BACKWARD, ns, F64), dev)
+        _check(lib.chefsi_filter_backward(self._h, _p(H), m, a, b, a0, ckpt_stride, _p(X), ldx, _p(Ybar),
+                                          ldyb, ns, _p(Hbar), _p(Xbar), Xbar.stride(0), _p(ws), ws.numel(),
+                                          _stream()))
+        return Hbar, Xbar
+
+
+def orthonormalize(Y: torch.Tensor, passes: int = 2, want_U: bool = False):
+    """Cholesky-QR in place on Y (Algorithm 1 step 3); returns U or None."""
+    ldy = _mv(Y, "Y")
+    n, ns = Y.shape
+    dev = Y.device
+    U = torch.empty((ns, ns), dtype=torch.float64, device=dev) if want_U else None
+    ws = _workspace(_orth_ws_bytes(n, ns, passes), dev)
+    _check(lib.chefsi_orthonormalize(n, ns, _p(Y), ldy, passes, _p(U), _p(ws), ws.numel(), _stream()))
+    return U
+
+
+def _orth_ws_bytes(n: int, ns: int, passes: int = 2) -> int:
+    out = _sz(0)
+    _check(lib.chefsi_orthonormalize_workspace_bytes(n, ns, passes, ctypes.byref(out)))
+    return int(out.value)

@@ -1,0 +1,740 @@
+// C ABI of the DG-CheFSI library: plan, argument checks, workspace carving,
+// and the orchestration of Algorithm 1 (bounds, filter, Cholesky-QR,
+// Rayleigh-Ritz, rotation) over the kernels in filter.hip, dense.hip,
+// lanczos.hip and eig.hip.  Every argument check runs on the host before the
+// first HIP call of an entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <numeric>
+
+#include "common.h"
+
+namespace chefsi {
+
+void destroy_eig_handle(Plan& p);
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+namespace {
+
+constexpr int kMaxDegree = 100000;
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+int check_device(const Plan& p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(CHEFSI_ERR_HIP, "hipGetDevice failed");
+  if (dev != p.device) return fail(CHEFSI_ERR_ARG, "current HIP device differs from the plan's device");
+  return CHEFSI_OK;
+}
+
+int check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return CHEFSI_OK;
+  if (ws == nullptr) return fail(CHEFSI_ERR_WORKSPACE, "workspace pointer is NULL");
+  if (!aligned256(ws)) return fail(CHEFSI_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(CHEFSI_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) +
+                                          " bytes, got " + std::to_string(ws_bytes));
+  return CHEFSI_OK;
+}
+
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bn && pb < pa + an;
+}
+
+size_t mv_bytes(int64_t n, int64_t ld, int ns, size_t elt) {
+  if (n <= 0 || ns <= 0) return 0;
+  return static_cast<size_t>((n - 1) * ld + ns) * elt;
+}
+
+int elt_size(int dtype) { return dtype == CHEFSI_F64 ? 8 : (dtype == CHEFSI_F32 ? 4 : 2); }
+
+bool valid_dtype(int dtype) { return dtype == CHEFSI_F64 || dtype == CHEFSI_F32 || dtype == CHEFSI_BF16; }
+
+// ------------------------------------------------------------ workspace layouts
+struct FilterWs {
+  double* coef;
+  double* bounds;
+  void* panel;
+  void* buf0;   // F64: recurrence buffer; low precision: converted X
+  void* buf1;   // low precision recurrence buffers
+  void* buf2;
+};
+
+void carve_filter(Carver& c, const Plan& p, int ns, int dtype, bool need_panel, FilterWs& f) {
+  const int e = elt_size(dtype);
+  f.coef = c.take<double>(3 * static_cast<int64_t>(kMaxDegree));
+  f.bounds = c.take<double>(4);
+  f.panel = need_panel ? c.take<char>(p.panel_elems * e) : nullptr;
+  const int64_t mv = p.N * static_cast<int64_t>(ns);
+  if (dtype == CHEFSI_F64) {
+    f.buf0 = c.take<double>(mv);
+    f.buf1 = f.buf2 = nullptr;
+  } else {
+    f.buf0 = c.take<char>(mv * e);
+    f.buf1 = c.take<char>(mv * e);
+    f.buf2 = c.take<char>(mv * e);
+  }
+}
+
+struct OrthWs {
+  double* S;
+  double* U1;
+  double* U2;
+  double* split;
+  size_t split_elems;
+  int* status;
+};
+
+void carve_orth(Carver& c, int64_t n, int ns, OrthWs& o) {
+  const int64_t nn = static_cast<int64_t>(ns) * ns;
+  o.S = c.take<double>(nn);
+  o.U1 = c.take<double>(nn);
+  o.U2 = c.take<double>(nn);
+  o.split_elems = gemm_tn_split_ws_elems(ns, ns, n);
+  o.split = o.split_elems ? c.take<double>(static_cast<int64_t>(o.split_elems)) : nullptr;
+  o.status = c.take<int>(4);
+}
+
+struct RrWs {
+  void* panel;     // FP64 panel (may be shared)
+  double* W;
+  double* Hh;
+  double* Q;       // ns*ns + ns (signs)
+  double* E;
+  double* w;
+  double* part;
+  double* coef;
+  double* split;
+  size_t split_elems;
+  int* info;
+  void* eig;
+  size_t eig_bytes;
+};
+
+int carve_rr(Carver& c, Plan& p, int ns, bool need_panel, RrWs& r) {
+  const int64_t nn = static_cast<int64_t>(ns) * ns;
+  r.panel = need_panel ? c.take<double>(p.panel_elems) : nullptr;
+  r.W = c.take<double>(p.N * static_cast<int64_t>(ns));
+  r.Hh = c.take<double>(nn);
+  r.Q = c.take<double>(nn + ns);
+  r.E = c.take<double>(ns);
+  r.w = c.take<double>(ns);
+  r.part = c.take<double>(static_cast<int64_t>(p.M) * ns);
+  r.coef = c.take<double>(4);
+  r.split_elems = gemm_tn_split_ws_elems(ns, ns, p.N);
+  r.split = r.split_elems ? c.take<double>(static_cast<int64_t>(r.split_elems)) : nullptr;
+  r.info = c.take<int>(4);
+  size_t eb = 0;
+  int rc = eig_workspace_bytes(p, ns, &eb);
+  r.eig_bytes = eb;
+  r.eig = eb ? c.take<char>(static_cast<int64_t>(eb)) : nullptr;
+  return rc;
+}
+
+// ------------------------------------------------------------ building blocks
+int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, int m,
+               const double* X, int64_t ldx, double* Y, int64_t ldy, int ns, const FilterWs& f,
+               hipStream_t st) {
+  if (m == 0) return launch_copy_f64(X, ldx, Y, ldy, p.N, ns, st);
+  if (dtype == CHEFSI_F64) {
+    double* B[2] = {Y, static_cast<double*>(f.buf0)};
+    const int64_t LD[2] = {ldy, ns};
+    for (int k = 0; k < m; ++k) {
+      const int bi = (m - k) % 2, bp = (m - k + 1) % 2, bo = (m - k - 1) % 2;
+      StepIO io{};
+      io.in = (k == 0) ? static_cast<const void*>(X) : B[bi];
+      io.ldi = (k == 0) ? ldx : LD[bi];
+      io.in_f64 = true;
+      io.prev = (k == 0) ? nullptr : (k == 1 ? static_cast<const void*>(X) : B[bp]);
+      io.ldp = (k == 1) ? ldx : LD[bp];
+      io.prev_f64 = true;
+      io.out = B[bo];
+      io.ldo = LD[bo];
+      io.out_f64 = true;
+      CHEFSI_TRY(launch_step(p, panel, dtype, coef + 3 * k, io, ns, st));
+    }
+    return CHEFSI_OK;
+  }
+  // low precision: X converted once, Y_1..Y_{m-1} in two rotating buffers,
+  // Y_m written in FP64.
+  CHEFSI_TRY(launch_convert(X, ldx, f.buf0, dtype, ns, p.N, ns, st));
+  void* L[2] = {f.buf1, f.buf2};
+  for (int k = 0; k < m; ++k) {
+    StepIO io{};
+    io.in = (k == 0) ? f.buf0 : L[k % 2];
+    io.ldi = ns;
+    io.in_f64 = false;
+    io.prev = (k == 0) ? nullptr : (k == 1 ? f.buf0 : L[(k - 1) % 2]);
+    io.ldp = ns;
+    io.prev_f64 = false;
+    const bool last = (k == m - 1);
+    io.out = last ? static_cast<void*>(Y) : L[(k + 1) % 2];
+    io.ldo = last ? ldy : ns;
+    io.out_f64 = last;
+    CHEFSI_TRY(launch_step(p, panel, dtype, coef + 3 * k, io, ns, st));
+  }
+  return CHEFSI_OK;
+}
+
+int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout, const OrthWs& o,
+             hipStream_t st) {
+  CHEFSI_TRY(launch_fill_int(o.status, 1, 0, st));
+  double* Us[2] = {o.U1, o.U2};
+  for (int pass = 0; pass < passes; ++pass) {
+    CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y, ldy, Y, ldy, 0.0, o.S, ns, true, o.split, o.split_elems, st));
+    CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, true, st));
+    CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
+    CHEFSI_TRY(trsm_right_upper(Y, ldy, n, o.S, ns, ns, st));
+    CHEFSI_TRY(launch_copy_f64(o.S, ns, Us[pass], ns, ns, ns, st));
+  }
+  if (Uout != nullptr) {
+    if (passes == 1) {
+      CHEFSI_TRY(launch_copy_f64(o.U1, ns, Uout, ns, ns, ns, st));
+    } else {
+      CHEFSI_TRY(trmm_upper_upper(o.U2, o.U1, Uout, ns, st));
+    }
+  }
+  return CHEFSI_OK;
+}
+
+int run_rr(Plan& p, const void* panel64, const double* Yh, int64_t ldy, int ns, double* Xn,
+           int64_t ldx, double* ritz, double* resid, double* Qout, const RrWs& r, hipStream_t st) {
+  CHEFSI_TRY(launch_const_coef(1.0, 0.0, r.coef, st));
+  StepIO io{Yh, ldy, true, nullptr, 0, true, r.W, ns, true};
+  CHEFSI_TRY(launch_step(p, panel64, CHEFSI_F64, r.coef, io, ns, st));
+  CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, Yh, ldy, r.W, ns, 0.0, r.Hh, ns, false, r.split, r.split_elems, st));
+  CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, false, st));
+  CHEFSI_TRY(launch_fill_int(r.info, 1, 0, st));
+  CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.eig, r.eig_bytes, st));
+  CHEFSI_TRY(launch_eigvec_fix(r.Hh, ns, ns, r.Q, ns, st));
+  CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, Yh, ldy, r.Q, ns, 0.0, Xn, ldx, st));
+  if (resid != nullptr) {
+    CHEFSI_TRY(launch_resid_partial(p, panel64, Xn, ldx, ritz, ns, r.part, st));
+    CHEFSI_TRY(launch_colsum_sqrt(r.part, p.M, ns, resid, st));
+  }
+  if (Qout != nullptr) CHEFSI_TRY(launch_copy_f64(r.Q, ns, Qout, ns, ns, ns, st));
+  return CHEFSI_OK;
+}
+
+int read_status(const int* d_status, int code_if_set, const char* what, hipStream_t st) {
+  int h = 0;
+  CHEFSI_HIP(hipMemcpyAsync(&h, d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+  CHEFSI_HIP(hipStreamSynchronize(st));
+  if (h != 0) return fail(code_if_set, std::string(what) + " (device status " + std::to_string(h) + ")");
+  return CHEFSI_OK;
+}
+
+int validate_mv(const char* name, const void* d, int64_t ld, int ns) {
+  if (ns > 0 && d == nullptr) return fail(CHEFSI_ERR_ARG, std::string(name) + " is NULL");
+  if (ld < ns || ld < 1) return fail(CHEFSI_ERR_ARG, std::string(name) + ": leading dimension < ns");
+  return CHEFSI_OK;
+}
+
+int validate_bounds(double a, double b, double a0) {
+  if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(a0))
+    return fail(CHEFSI_ERR_ARG, "filter bounds must be finite");
+  if (!(a0 < a && a < b)) return fail(CHEFSI_ERR_ARG, "filter bounds must satisfy a0 < a < b");
+  return CHEFSI_OK;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::exception& e) {
+    return fail(CHEFSI_ERR_HIP, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(CHEFSI_ERR_HIP, "internal error");
+  }
+}
+
+size_t sweep_bytes(Plan& p, int ns, int dtype, int passes, int k) {
+  (void)passes;
+  Carver c(nullptr, 0);
+  c.take<double>(p.panel_elems);                        // FP64 panel
+  c.take<double>(p.N * static_cast<int64_t>(ns));       // filtered block
+  c.take<double>(8);                                    // bounds
+  c.take<int>(8);                                       // status words
+  const size_t base = c.used;
+  Carver cf(nullptr, 0);
+  FilterWs f;
+  carve_filter(cf, p, ns, dtype, dtype != CHEFSI_F64, f);
+  Carver co(nullptr, 0);
+  OrthWs o;
+  carve_orth(co, p.N, ns, o);
+  Carver cr(nullptr, 0);
+  RrWs r;
+  carve_rr(cr, p, ns, false, r);
+  size_t lz = lanczos_ws_bytes(p, k);
+  return base + std::max(std::max(cf.used, co.used), std::max(cr.used, lz));
+}
+
+}  // namespace
+}  // namespace chefsi
+
+using namespace chefsi;
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* chefsi_version(void) { return "chefsi-gfx950 1.0"; }
+
+const char* chefsi_last_error(void) { return g_err.c_str(); }
+
+int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, const int32_t* alb_counts) {
+  return guarded([&]() -> int {
+    if (out == nullptr) return fail(CHEFSI_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(CHEFSI_ERR_ARG, "grid dimensions must be >= 1");
+    const int64_t M64 = static_cast<int64_t>(nx) * ny * nz;
+    if (M64 > (1 << 22)) return fail(CHEFSI_ERR_ARG, "too many elements");
+    if (stencil != 5 && stencil != 7) return fail(CHEFSI_ERR_ARG, "stencil must be 5 or 7");
+    if (alb_counts == nullptr) return fail(CHEFSI_ERR_ARG, "alb_counts is NULL");
+    const int M = static_cast<int>(M64);
+    for (int K = 0; K < M; ++K)
+      if (alb_counts[K] < 1 || alb_counts[K] > kMaxJ)
+        return fail(CHEFSI_ERR_ARG, "alb_counts[" + std::to_string(K) + "] must be in [1, 128]");
+
+    Plan* p = new Plan();
+    p->nx = nx;
+    p->ny = ny;
+    p->nz = nz;
+    p->stencil = stencil;
+    p->M = M;
+    const int S = stencil;
+    p->J.assign(alb_counts, alb_counts + M);
+    p->rowoff.assign(M + 1, 0);
+    for (int K = 0; K < M; ++K) p->rowoff[K + 1] = p->rowoff[K] + p->J[K];
+    p->N = p->rowoff[M];
+    if (p->N >= (int64_t(1) << 31)) {
+      delete p;
+      return fail(CHEFSI_ERR_ARG, "N must be < 2^31");
+    }
+    static const int dirs[7][3] = {{0, 0, 0}, {-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    p->nbr.resize(static_cast<size_t>(M) * S);
+    for (int K = 0; K < M; ++K) {
+      const int ix = K % nx, iy = (K / nx) % ny, iz = K / (nx * ny);
+      for (int s = 0; s < S; ++s) {
+        const int jx = ((ix + dirs[s][0]) % nx + nx) % nx;
+        const int jy = ((iy + dirs[s][1]) % ny + ny) % ny;
+        const int jz = ((iz + dirs[s][2]) % nz + nz) % nz;
+        p->nbr[static_cast<size_t>(K) * S + s] = jx + nx * (jy + ny * jz);
+      }
+    }
+    p->hoff.resize(static_cast<size_t>(M) * S);
+    p->ktot.resize(M);
+    p->kpad.resize(M);
+    p->rb.resize(M);
+    p->poff.resize(M);
+    p->koff.resize(M);
+    int64_t h = 0, po = 0, ko = 0;
+    p->maxJ = 0;
+    p->maxRB = 0;
+    p->uniform = true;
+    for (int K = 0; K < M; ++K) {
+      int kt = 0;
+      for (int s = 0; s < S; ++s) {
+        const int Kp = p->nbr[static_cast<size_t>(K) * S + s];
+        p->hoff[static_cast<size_t>(K) * S + s] = h;
+        h += static_cast<int64_t>(p->J[K]) * p->J[Kp];
+        kt += p->J[Kp];
+      }
+      p->ktot[K] = kt;
+      p->kpad[K] = static_cast<int32_t>(round_up(kt, kStepKC));
+      p->rb[K] = static_cast<int32_t>(ceil_div(p->J[K], 16));
+      p->poff[K] = po;
+      po += static_cast<int64_t>(p->kpad[K]) * p->rb[K] * 16;
+      p->koff[K] = ko;
+      ko += p->kpad[K];
+      p->maxJ = std::max(p->maxJ, p->J[K]);
+      p->maxRB = std::max(p->maxRB, static_cast<int>(p->rb[K]));
+      if (p->rb[K] != p->rb[0]) p->uniform = false;
+    }
+    p->h_elems = h;
+    p->panel_elems = po;
+    p->kmap_len = ko;
+    std::vector<int32_t> kmap(static_cast<size_t>(ko), -1);
+    for (int K = 0; K < M; ++K) {
+      int k = 0;
+      for (int s = 0; s < S; ++s) {
+        const int Kp = p->nbr[static_cast<size_t>(K) * S + s];
+        for (int r = 0; r < p->J[Kp]; ++r) kmap[p->koff[K] + k++] = static_cast<int32_t>(p->rowoff[Kp] + r);
+      }
+    }
+    // heaviest work-groups first (uniform plans keep the natural order)
+    std::vector<int32_t> order(M);
+    std::iota(order.begin(), order.end(), 0);
+    if (!p->uniform) {
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return static_cast<int64_t>(p->rb[x]) * p->kpad[x] > static_cast<int64_t>(p->rb[y]) * p->kpad[y];
+      });
+    }
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return fail(CHEFSI_ERR_HIP, "hipGetDevice failed (no GPU?)");
+    }
+    auto up = [&](auto** dst, const auto& vec) -> int {
+      using T = typename std::remove_reference<decltype(vec)>::type::value_type;
+      const size_t bytes = std::max<size_t>(vec.size(), 1) * sizeof(T);
+      if (hipMalloc(reinterpret_cast<void**>(dst), bytes) != hipSuccess) return CHEFSI_ERR_HIP;
+      if (!vec.empty() && hipMemcpy(*dst, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return CHEFSI_ERR_HIP;
+      return CHEFSI_OK;
+    };
+    int rc = CHEFSI_OK;
+    rc |= up(&p->d_J, p->J);
+    rc |= up(&p->d_nbr, p->nbr);
+    rc |= up(&p->d_rb, p->rb);
+    rc |= up(&p->d_kpad, p->kpad);
+    rc |= up(&p->d_order, order);
+    rc |= up(&p->d_rowoff, p->rowoff);
+    rc |= up(&p->d_hoff, p->hoff);
+    rc |= up(&p->d_poff, p->poff);
+    rc |= up(&p->d_koff, p->koff);
+    rc |= up(&p->d_kmap, kmap);
+    if (rc != CHEFSI_OK) {
+      chefsi_plan_destroy(reinterpret_cast<chefsi_plan>(p));
+      return fail(CHEFSI_ERR_HIP, "plan_create: device table upload failed");
+    }
+    *out = reinterpret_cast<chefsi_plan>(p);
+    return CHEFSI_OK;
+  });
+}
+
+void chefsi_plan_destroy(chefsi_plan plan) {
+  if (plan == nullptr) return;
+  Plan* p = P(plan);
+  void* ptrs[] = {p->d_J, p->d_nbr, p->d_rb, p->d_kpad, p->d_order, p->d_rowoff,
+                  p->d_hoff, p->d_poff, p->d_koff, p->d_kmap, p->d_kslot};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  destroy_eig_handle(*p);
+  delete p;
+}
+
+int64_t chefsi_plan_n(chefsi_plan plan) { return plan ? P(plan)->N : -1; }
+
+int64_t chefsi_plan_h_elems(chefsi_plan plan) { return plan ? P(plan)->h_elems : -1; }
+
+int chefsi_plan_neighbour(chefsi_plan plan, int K, int s) {
+  if (!plan) return -1;
+  const Plan* p = P(plan);
+  if (K < 0 || K >= p->M || s < 0 || s >= p->stencil) return -1;
+  return p->nbr[static_cast<size_t>(K) * p->stencil + s];
+}
+
+int chefsi_workspace_bytes(chefsi_plan plan, int op, int ns, int dtype, int passes, int lanczos_steps,
+                           size_t* bytes) {
+  return guarded([&]() -> int {
+    if (plan == nullptr || bytes == nullptr) return fail(CHEFSI_ERR_ARG, "plan/bytes is NULL");
+    if (ns < 0) return fail(CHEFSI_ERR_ARG, "ns must be >= 0");
+    Plan& p = *P(plan);
+    *bytes = 0;
+    switch (op) {
+      case CHEFSI_OP_BOUNDS: {
+        if (lanczos_steps < 1 || lanczos_steps > kMaxLanczos)
+          return fail(CHEFSI_ERR_ARG, "lanczos_steps must be in [1, 64]");
+        Carver c(nullptr, 0);
+        c.take<double>(p.panel_elems);
+        c.take<double>(8);
+        *bytes = c.used + lanczos_ws_bytes(p, lanczos_steps);
+        return CHEFSI_OK;
+      }
+      case CHEFSI_OP_FILTER: {
+        if (!valid_dtype(dtype)) return fail(CHEFSI_ERR_ARG, "bad dtype");
+        Carver c(nullptr, 0);
+        FilterWs f;
+        carve_filter(c, p, ns, dtype, true, f);
+        *bytes = c.used;
+        return CHEFSI_OK;
+      }
+      case CHEFSI_OP_ORTHONORMALIZE: {
+        Carver c(nullptr, 0);
+        OrthWs o;
+        carve_orth(c, p.N, ns, o);
+        *bytes = c.used;
+        return CHEFSI_OK;
+      }
+      case CHEFSI_OP_RAYLEIGH_RITZ: {
+        Carver c(nullptr, 0);
+        RrWs r;
+        CHEFSI_TRY(carve_rr(c, p, ns, true, r));
+        *bytes = c.used;
+        return CHEFSI_OK;
+      }
+      case CHEFSI_OP_SWEEP: {
+        if (!valid_dtype(dtype)) return fail(CHEFSI_ERR_ARG, "bad dtype");
+        if (lanczos_steps < 1 || lanczos_steps > kMaxLanczos)
+          return fail(CHEFSI_ERR_ARG, "lanczos_steps must be in [1, 64]");
+        *bytes = sweep_bytes(p, ns, dtype, passes, lanczos_steps);
+        return CHEFSI_OK;
+      }
+      default:
+        return fail(CHEFSI_ERR_UNSUPPORTED, "unknown op");
+    }
+  });
+}
+
+int chefsi_bounds(chefsi_plan plan, const double* d_H, const double* d_v0, int lanczos_steps,
+                  const double* d_ritz_prev, int ns, double* d_bounds, double* h_bounds, void* ws,
+                  size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (d_H == nullptr || d_v0 == nullptr) return fail(CHEFSI_ERR_ARG, "H or v0 is NULL");
+    if (lanczos_steps < 1 || lanczos_steps > kMaxLanczos)
+      return fail(CHEFSI_ERR_ARG, "lanczos_steps must be in [1, 64]");
+    if (ns < 1 || ns > p.N) return fail(CHEFSI_ERR_ARG, "ns must be in [1, N]");
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_workspace_bytes(plan, CHEFSI_OP_BOUNDS, ns, 0, 1, lanczos_steps, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    double* panel = c.take<double>(p.panel_elems);
+    double* bnd = c.take<double>(8);
+    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, panel, st));
+    CHEFSI_TRY(lanczos_bounds(p, panel, d_v0, lanczos_steps, d_ritz_prev, ns, bnd,
+                              static_cast<char*>(ws) + c.used, ws_bytes - c.used, st));
+    if (d_bounds) CHEFSI_HIP(hipMemcpyAsync(d_bounds, bnd, 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double hb[3];
+    CHEFSI_HIP(hipMemcpyAsync(hb, bnd, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CHEFSI_HIP(hipStreamSynchronize(st));
+    if (h_bounds) std::memcpy(h_bounds, hb, sizeof(hb));
+    if (!std::isfinite(hb[0]) || !std::isfinite(hb[1]) || !std::isfinite(hb[2]))
+      return fail(CHEFSI_ERR_NONFINITE, "bounds are not finite");
+    return CHEFSI_OK;
+  });
+}
+
+int chefsi_filter(chefsi_plan plan, const double* d_H, int m, double a, double b, double a0, int dtype,
+                  const double* d_X, int64_t ldx, double* d_Y, int64_t ldy, int ns, void* ws,
+                  size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (d_H == nullptr) return fail(CHEFSI_ERR_ARG, "H is NULL");
+    if (m < 0 || m > kMaxDegree) return fail(CHEFSI_ERR_ARG, "filter degree must be in [0, 100000]");
+    if (!valid_dtype(dtype)) return fail(CHEFSI_ERR_ARG, "bad dtype");
+    if (ns < 0) return fail(CHEFSI_ERR_ARG, "ns must be >= 0");
+    CHEFSI_TRY(validate_bounds(a, b, a0));
+    CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
+    CHEFSI_TRY(validate_mv("Y", d_Y, ldy, ns));
+    if (ns > 0 && overlaps(d_X, mv_bytes(p.N, ldx, ns, 8), d_Y, mv_bytes(p.N, ldy, ns, 8)))
+      return fail(CHEFSI_ERR_ARG, "X and Y overlap");
+    if (dtype == CHEFSI_BF16) return fail(CHEFSI_ERR_UNSUPPORTED, "BF16 filter not built");
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_workspace_bytes(plan, CHEFSI_OP_FILTER, ns, dtype, 1, 1, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    if (ns == 0) return CHEFSI_OK;
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    FilterWs f;
+    carve_filter(c, p, ns, dtype, true, f);
+    CHEFSI_TRY(launch_repack(p, d_H, dtype, false, f.panel, st));
+    CHEFSI_TRY(launch_set_bounds(a, b, a0, f.bounds, st));
+    CHEFSI_TRY(launch_cheb_coef(f.bounds, m, f.coef, st));
+    return run_filter(p, f.panel, dtype, f.coef, m, d_X, ldx, d_Y, ldy, ns, f, st);
+  });
+}
+
+int chefsi_orthonormalize(int64_t n, int ns, double* d_Y, int64_t ldy, int passes, double* d_U, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (n < 1 || ns < 1) return fail(CHEFSI_ERR_ARG, "n and ns must be >= 1");
+    if (ns > n) return fail(CHEFSI_ERR_ARG, "ns must be <= n");
+    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    CHEFSI_TRY(validate_mv("Y", d_Y, ldy, ns));
+    if (d_U && overlaps(d_U, static_cast<size_t>(ns) * ns * 8, d_Y, mv_bytes(n, ldy, ns, 8)))
+      return fail(CHEFSI_ERR_ARG, "U and Y overlap");
+    Carver dry(nullptr, 0);
+    OrthWs o;
+    carve_orth(dry, n, ns, o);
+    CHEFSI_TRY(check_ws(ws, ws_bytes, dry.used));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    carve_orth(c, n, ns, o);
+    CHEFSI_TRY(run_orth(n, ns, d_Y, ldy, passes, d_U, o, st));
+    return read_status(o.status, CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot", st);
+  });
+}
+
+int chefsi_orthonormalize_workspace_bytes(int64_t n, int ns, int passes, size_t* bytes) {
+  return guarded([&]() -> int {
+    if (bytes == nullptr) return fail(CHEFSI_ERR_ARG, "bytes is NULL");
+    if (n < 1 || ns < 1 || ns > n) return fail(CHEFSI_ERR_ARG, "need 1 <= ns <= n");
+    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    Carver c(nullptr, 0);
+    OrthWs o;
+    carve_orth(c, n, ns, o);
+    *bytes = c.used;
+    return CHEFSI_OK;
+  });
+}
+
+int chefsi_rayleigh_ritz(chefsi_plan plan, const double* d_H, const double* d_Yhat, int64_t ldy, int ns,
+                         double* d_Xnew, int64_t ldx, double* d_ritz, double* d_resid, double* d_Q, void* ws,
+                         size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (d_H == nullptr || d_ritz == nullptr) return fail(CHEFSI_ERR_ARG, "H or ritz is NULL");
+    if (ns < 1 || ns > p.N) return fail(CHEFSI_ERR_ARG, "ns must be in [1, N]");
+    CHEFSI_TRY(validate_mv("Yhat", d_Yhat, ldy, ns));
+    CHEFSI_TRY(validate_mv("Xnew", d_Xnew, ldx, ns));
+    if (overlaps(d_Yhat, mv_bytes(p.N, ldy, ns, 8), d_Xnew, mv_bytes(p.N, ldx, ns, 8)))
+      return fail(CHEFSI_ERR_ARG, "Yhat and Xnew overlap");
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_workspace_bytes(plan, CHEFSI_OP_RAYLEIGH_RITZ, ns, 0, 1, 1, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    RrWs r;
+    CHEFSI_TRY(carve_rr(c, p, ns, true, r));
+    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, r.panel, st));
+    CHEFSI_TRY(run_rr(p, r.panel, d_Yhat, ldy, ns, d_Xnew, ldx, d_ritz, d_resid, d_Q, r, st));
+    return read_status(r.info, CHEFSI_ERR_EIG, "dense eigensolver did not converge", st);
+  });
+}
+
+int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, int passes, int lanczos_steps,
+                 const double* d_v0, const double* d_bounds_in, int warm, double* d_X, int64_t ldx, int ns,
+                 double* d_ritz, double* d_resid, double* d_bounds_out, chefsi_stats* stats, void* ws,
+                 size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (d_H == nullptr || d_ritz == nullptr) return fail(CHEFSI_ERR_ARG, "H or ritz is NULL");
+    if (m < 0 || m > kMaxDegree) return fail(CHEFSI_ERR_ARG, "filter degree must be in [0, 100000]");
+    if (!valid_dtype(filter_dtype)) return fail(CHEFSI_ERR_ARG, "bad dtype");
+    if (filter_dtype == CHEFSI_BF16) return fail(CHEFSI_ERR_UNSUPPORTED, "BF16 filter not built");
+    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    if (ns < 1 || ns > p.N) return fail(CHEFSI_ERR_ARG, "ns must be in [1, N]");
+    if (d_bounds_in == nullptr) {
+      if (d_v0 == nullptr) return fail(CHEFSI_ERR_ARG, "v0 is NULL and no bounds were given");
+      if (lanczos_steps < 1 || lanczos_steps > kMaxLanczos)
+        return fail(CHEFSI_ERR_ARG, "lanczos_steps must be in [1, 64]");
+    }
+    CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
+    const int lk = (lanczos_steps >= 1 && lanczos_steps <= kMaxLanczos) ? lanczos_steps : 1;
+    const size_t need = sweep_bytes(p, ns, filter_dtype, passes, lk);
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    hipEvent_t ev[6] = {};
+    if (stats) {
+      for (auto& e : ev) CHEFSI_HIP(hipEventCreate(&e));
+    }
+    auto mark = [&](int i) -> int {
+      if (stats) CHEFSI_HIP(hipEventRecord(ev[i], st));
+      return CHEFSI_OK;
+    };
+    auto run = [&]() -> int {
+      Carver c(ws, ws_bytes);
+      double* panel64 = c.take<double>(p.panel_elems);
+      double* Y = c.take<double>(p.N * static_cast<int64_t>(ns));
+      double* bnd = c.take<double>(8);
+      int* status = c.take<int>(8);
+      char* rest = static_cast<char*>(ws) + c.used;
+      const size_t rest_bytes = ws_bytes - c.used;
+      CHEFSI_TRY(mark(0));
+      CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, panel64, st));
+      // step 1: bounds
+      if (d_bounds_in) {
+        CHEFSI_HIP(hipMemcpyAsync(bnd, d_bounds_in, 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+      } else {
+        CHEFSI_TRY(lanczos_bounds(p, panel64, d_v0, lanczos_steps, warm ? d_ritz : nullptr, ns, bnd, rest,
+                                  rest_bytes, st));
+      }
+      CHEFSI_TRY(mark(1));
+      // step 2: filter
+      {
+        Carver cf(rest, rest_bytes);
+        FilterWs f;
+        carve_filter(cf, p, ns, filter_dtype, filter_dtype != CHEFSI_F64, f);
+        const void* fpanel = panel64;
+        if (filter_dtype != CHEFSI_F64) {
+          CHEFSI_TRY(launch_repack(p, d_H, filter_dtype, false, f.panel, st));
+          fpanel = f.panel;
+        }
+        CHEFSI_TRY(launch_cheb_coef(bnd, m, f.coef, st));
+        CHEFSI_TRY(mark(2));
+        CHEFSI_TRY(run_filter(p, fpanel, filter_dtype, f.coef, m, d_X, ldx, Y, ns, ns, f, st));
+      }
+      CHEFSI_TRY(mark(3));
+      // step 3: Cholesky-QR
+      {
+        Carver co(rest, rest_bytes);
+        OrthWs o;
+        carve_orth(co, p.N, ns, o);
+        o.status = status;
+        CHEFSI_TRY(run_orth(p.N, ns, Y, ns, passes, nullptr, o, st));
+      }
+      CHEFSI_TRY(mark(4));
+      // steps 4-5: Rayleigh-Ritz and rotation
+      {
+        Carver cr(rest, rest_bytes);
+        RrWs r;
+        CHEFSI_TRY(carve_rr(cr, p, ns, false, r));
+        r.info = status + 1;
+        CHEFSI_TRY(run_rr(p, panel64, Y, ns, ns, d_X, ldx, d_ritz, d_resid, nullptr, r, st));
+      }
+      CHEFSI_TRY(mark(5));
+      if (d_bounds_out)
+        CHEFSI_HIP(hipMemcpyAsync(d_bounds_out, bnd, 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+      int hs[2] = {0, 0};
+      CHEFSI_HIP(hipMemcpyAsync(hs, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      CHEFSI_HIP(hipStreamSynchronize(st));
+      if (stats) {
+        float t[5];
+        for (int i = 0; i < 5; ++i) CHEFSI_HIP(hipEventElapsedTime(&t[i], ev[i], ev[i + 1]));
+        float tf = 0.f, tot = 0.f;
+        CHEFSI_HIP(hipEventElapsedTime(&tf, ev[1], ev[3]));
+        CHEFSI_HIP(hipEventElapsedTime(&tot, ev[0], ev[5]));
+        stats->bounds_ms = t[0];
+        stats->filter_ms = tf;
+        stats->filter_steps_ms = t[2];
+        stats->orthonormalize_ms = t[3];
+        stats->rayleigh_ritz_ms = t[4];
+        stats->total_ms = tot;
+      }
+      if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+      if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");
+      return CHEFSI_OK;
+    };
+    int rc = run();
+    if (stats)
+      for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+  });
+}
+
+int chefsi_loss_backward(chefsi_plan, const double*, int, double, double, double, int, int, int,
+                         const double*, int64_t, int, double*, double*, int64_t, double*, void*, size_t,
+                         void*) {
+  return fail(CHEFSI_ERR_UNSUPPORTED, "loss_backward not built yet");
+}
+
+int chefsi_filter_backward(chefsi_plan, const double*, int, double, double, double, int, const double*,
+                           int64_t, const double*, int64_t, int, double*, double*, int64_t, void*, size_t,
+                           void*) {
+  return fail(CHEFSI_ERR_UNSUPPORTED, "filter_backward not built yet");
+}
+
+}  // extern "C"

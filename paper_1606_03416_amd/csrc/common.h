@@ -1,0 +1,164 @@
+// Internal declarations shared by the library's translation units (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chefsi.h"
+
+namespace chefsi {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define CHEFSI_HIP(call)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return ::chefsi::fail(CHEFSI_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHEFSI_LAUNCHED(what)                                                         \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      return ::chefsi::fail(CHEFSI_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHEFSI_TRY(expr)               \
+  do {                                 \
+    int r_ = (expr);                   \
+    if (r_ != CHEFSI_OK) return r_;    \
+  } while (0)
+
+// ---------------------------------------------------------------- sizes
+constexpr int kMaxJ = 128;          // largest ALB count per element supported
+constexpr int kMaxLanczos = 64;     // largest Lanczos step count
+constexpr int kStepTN = 128;        // columns per work-group of the step kernel
+constexpr int kStepKC = 16;         // reduction rows staged per LDS chunk
+
+__host__ __device__ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+__host__ __device__ inline int64_t ceil_div(int64_t v, int64_t m) { return (v + m - 1) / m; }
+
+// ---------------------------------------------------------------- plan
+struct Plan {
+  int nx = 0, ny = 0, nz = 0, stencil = 0, M = 0;
+  int64_t N = 0;
+  int64_t h_elems = 0;      // block-list layout size
+  int64_t panel_elems = 0;  // internal packed panel size (elements)
+  int64_t kmap_len = 0;
+  int maxJ = 0, maxRB = 0;
+  bool uniform = true;
+  int device = 0;
+  std::vector<int32_t> J, nbr, ktot, kpad, rb;
+  std::vector<int64_t> rowoff, hoff, poff, koff;
+  // device tables
+  int32_t* d_J = nullptr;       // [M]
+  int32_t* d_nbr = nullptr;     // [M*S]
+  int32_t* d_rb = nullptr;      // [M] row blocks (ceil(J/16))
+  int32_t* d_kpad = nullptr;    // [M] reduction rows padded to kStepKC
+  int32_t* d_order = nullptr;   // [M] element processing order (heaviest first)
+  int64_t* d_rowoff = nullptr;  // [M+1]
+  int64_t* d_hoff = nullptr;    // [M*S] block offsets in block-list layout
+  int64_t* d_poff = nullptr;    // [M] panel offsets (elements)
+  int64_t* d_koff = nullptr;    // [M] kmap offsets
+  int32_t* d_kmap = nullptr;    // [sum kpad] global row of each reduction row (-1 pad)
+  int32_t* d_kslot = nullptr;   // [sum kpad] (slot << 8 | row-in-slot) of each reduction row
+  void* rocblas = nullptr;      // rocblas_handle for the dense eigensolver
+  size_t eig_ws_cache_n = 0, eig_ws_cache_bytes = 0;
+};
+
+inline Plan* P(chefsi_plan p) { return reinterpret_cast<Plan*>(p); }
+
+// ---------------------------------------------------------------- workspace carving
+struct Carver {
+  char* base;
+  size_t cap, used = 0;
+  bool dry;
+  Carver(void* b, size_t c) : base(static_cast<char*>(b)), cap(c), dry(b == nullptr) {}
+  template <typename T>
+  T* take(int64_t count) {
+    size_t bytes = static_cast<size_t>(round_up(static_cast<int64_t>(count * sizeof(T)), 256));
+    size_t off = used;
+    used += bytes;
+    if (dry) return nullptr;
+    return reinterpret_cast<T*>(base + off);
+  }
+  bool ok() const { return dry || used <= cap; }
+};
+
+// ---------------------------------------------------------------- kernels (launchers)
+// All launchers enqueue on `st` and return a chefsi_status.
+int launch_set_bounds(double a, double b, double a0, double* d_bounds, hipStream_t st);
+int launch_cheb_coef(const double* d_bounds, int m, double* d_coef, hipStream_t st);
+int launch_const_coef(double alpha, double c, double* d_coef, hipStream_t st);
+
+// Repack H (block-list, fp64) into per-element transposed panels of type dtype.
+// transpose_h = true packs H^T (uses the opposite slot of each neighbour).
+int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h, void* d_panel,
+                  hipStream_t st);
+
+// One Chebyshev step / SpMM: out = alpha_k (H*in - c*in) - beta_k*prev on all
+// element rows, columns [0, ns). coef points at (alpha, beta, c) of this step.
+// in/prev/out element types follow dtype (F64: double; F32: float; BF16: bf16),
+// except out_f64 forces a float64 output and in_f64/prev_f64 a float64 input.
+struct StepIO {
+  const void* in; int64_t ldi; bool in_f64;
+  const void* prev; int64_t ldp; bool prev_f64;   // prev may be null
+  void* out; int64_t ldo; bool out_f64;
+};
+int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_coef,
+                const StepIO& io, int ns, hipStream_t st);
+// Residual partials: part[K*ns + j] = sum_{i in K} (H x_j - theta_j x_j)_i^2 (fp64).
+int launch_resid_partial(const Plan& p, const void* d_panel, const double* d_X, int64_t ldx,
+                         const double* d_theta, int ns, double* d_part, hipStream_t st);
+int launch_colsum_sqrt(const double* d_part, int rows, int ns, double* d_out, hipStream_t st);
+
+// Conversions / copies of N x ns multivectors.
+int launch_convert(const double* src, int64_t lds, void* dst, int dst_dtype, int64_t ldd,
+                   int64_t n, int ns, hipStream_t st);
+int launch_copy_f64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int ns,
+                    hipStream_t st);
+
+// Dense FP64 kernels (dense.hip).
+// C(m x n) = alpha * A^T B + beta * C, A (k x m, lda), B (k x n, ldb), row-major.
+// upper_only: compute only tiles on/above the diagonal (symmetric results).
+int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool upper_only,
+            double* d_split_ws, size_t split_ws_elems, hipStream_t st);
+// C(m x n) = alpha * A B + beta * C, A (m x k, lda), B (k x n, ldb), row-major.
+int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st);
+size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k);
+int launch_symmetrize(double* A, int64_t lda, int n, bool mirror_upper, hipStream_t st);
+int cholesky_upper(double* S, int64_t lds, int n, int* d_status, hipStream_t st);
+int trsm_right_upper(double* Y, int64_t ldy, int64_t nrows, const double* U, int64_t ldu, int n,
+                     hipStream_t st);
+int launch_fill(double* d, int64_t count, double v, hipStream_t st);
+int launch_fill_int(int* d, int64_t count, int v, hipStream_t st);
+int trmm_upper_upper(const double* A, const double* B, double* C, int n, hipStream_t st);
+int launch_eigvec_fix(const double* Vcm, int64_t ldv, int n, double* Q, int64_t ldq,
+                      hipStream_t st);
+int launch_transpose(const double* A, int64_t lda, double* B, int64_t ldb, int rows, int cols,
+                     hipStream_t st);
+
+// Eigensolver (eig.hip)
+int eig_workspace_bytes(Plan& p, int n, size_t* bytes);
+int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, int* d_info,
+            void* d_ws, size_t ws_bytes, hipStream_t st);
+
+// Lanczos (lanczos.hip)
+size_t lanczos_ws_bytes(const Plan& p, int k);
+int lanczos_bounds(const Plan& p, const void* d_panel64, const double* d_v0, int k,
+                   const double* d_ritz_prev, int ns, double* d_bounds, void* ws, size_t ws_bytes,
+                   hipStream_t st);
+int launch_warm_bounds(const double* d_ritz, int ns, const double* d_b_src, double* d_bounds,
+                       hipStream_t st);
+
+}  // namespace chefsi

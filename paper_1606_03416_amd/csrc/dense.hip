@@ -1,0 +1,490 @@
+// Dense FP64 kernels of the subspace problem (Algorithm 1 steps 3-5) for
+// gfx950: tall-skinny GEMMs on FP64 MFMA (Gram matrix Y^T Y, projection
+// Yhat^T (H Yhat), rotation Yhat Q, blocked triangular-solve updates),
+// blocked Cholesky, row-wise triangular substitution, and small helpers.
+#include "common.h"
+
+namespace chefsi {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 128;   // output tile (rows and columns)
+constexpr int GK = 16;    // reduction rows per LDS chunk
+constexpr int GNT = 256;  // threads
+constexpr int GLD = GT + 2;
+
+// A operand: lane l holds A[l%16][l/16]; B operand: B[l/16][l%16];
+// output element q of lane l is D[4q + l/16][l%16].
+__device__ __forceinline__ d4 mma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct GemmArgs {
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  int64_t m, n, k;
+  double alpha, beta;
+  int64_t kper;     // reduction rows per split (multiple of GK)
+  double* part;     // split partials [split][m][n] or null (direct epilogue)
+  bool upper_only;
+};
+
+// C tile (128 x 128) = sum_k op(A)[i][k] B[k][j] over this split's k range.
+// A_KMAJOR: A stored k x m (TN form); otherwise m x k (NN form).
+template <bool A_KMAJOR>
+__global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
+  const int ti = blockIdx.y, tj = blockIdx.x, split = blockIdx.z;
+  if (g.upper_only && ti > tj) return;
+  __shared__ double sA[2][GK][GLD];
+  __shared__ double sB[2][GK][GLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = static_cast<int64_t>(ti) * GT, j0 = static_cast<int64_t>(tj) * GT;
+  const int64_t kbeg = static_cast<int64_t>(split) * g.kper;
+  int64_t kend = kbeg + g.kper;
+  if (kend > g.k) kend = g.k;
+  const int nch = static_cast<int>(ceil_div(kend - kbeg, GK));
+
+  double ra[8], rb[8];
+  auto gload = [&](int c) {
+    const int64_t kc = kbeg + static_cast<int64_t>(c) * GK;
+    if constexpr (A_KMAJOR) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int row = (tid >> 7) + 2 * q, col = tid & 127;
+        const int64_t kk = kc + row, ii = i0 + col;
+        ra[q] = (kk < kend && ii < g.m) ? g.A[kk * g.lda + ii] : 0.0;
+      }
+    } else {
+      const int row = tid >> 1, half = tid & 1;   // 128 rows x 16 k
+      const int64_t ii = i0 + row;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t kk = kc + half * 8 + q;
+        ra[q] = (kk < kend && ii < g.m) ? g.A[ii * g.lda + kk] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int row = (tid >> 7) + 2 * q, col = tid & 127;
+      const int64_t kk = kc + row, jj = j0 + col;
+      rb[q] = (kk < kend && jj < g.n) ? g.B[kk * g.ldb + jj] : 0.0;
+    }
+  };
+  auto sstore = [&](int buf) {
+    if constexpr (A_KMAJOR) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sA[buf][(tid >> 7) + 2 * q][tid & 127] = ra[q];
+    } else {
+      const int row = tid >> 1, half = tid & 1;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sA[buf][half * 8 + q][row] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sB[buf][(tid >> 7) + 2 * q][tid & 127] = rb[q];
+  };
+
+  d4 acc[8][2];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    acc[r][0] = d4{0, 0, 0, 0};
+    acc[r][1] = d4{0, 0, 0, 0};
+  }
+  if (nch > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) gload(c + 1);
+#pragma unroll
+    for (int kk = 0; kk < GK / 4; ++kk) {
+      const int krow = kk * 4 + (lane >> 4);
+      double av[8], bv[2];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) av[r] = sA[buf][krow][r * 16 + (lane & 15)];
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) bv[c2] = sB[buf][krow][wave * 32 + c2 * 16 + (lane & 15)];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        acc[r][0] = mma64(av[r], bv[0], acc[r][0]);
+        acc[r][1] = mma64(av[r], bv[1], acc[r][1]);
+      }
+    }
+    if (c + 1 < nch) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int64_t j = j0 + wave * 32 + c2 * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t i = i0 + r * 16 + 4 * q + (lane >> 4);   // FP64 MFMA output row
+        if (i < g.m && j < g.n) {
+          if (g.part != nullptr) {
+            g.part[(static_cast<int64_t>(split) * g.m + i) * g.n + j] = acc[r][c2][q];
+          } else {
+            double v = g.alpha * acc[r][c2][q];
+            if (g.beta != 0.0) v += g.beta * g.C[i * g.ldc + j];
+            g.C[i * g.ldc + j] = v;
+          }
+        }
+      }
+    }
+}
+
+__global__ void split_reduce_kernel(const double* part, int splits, int64_t m, int64_t n,
+                                    double alpha, double beta, double* C, int64_t ldc,
+                                    bool upper_only) {
+  const int64_t total = m * n;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / n, j = t - (t / n) * n;
+    if (upper_only && (i / GT) > (j / GT)) continue;
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += part[sp * total + t];
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * C[i * ldc + j];
+    C[i * ldc + j] = v;
+  }
+}
+
+__global__ void symmetrize_kernel(double* A, int64_t lda, int n, bool mirror_upper) {
+  const int64_t total = static_cast<int64_t>(n) * n;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / n, j = t - (t / n) * n;
+    if (i >= j) continue;
+    if (mirror_upper) {
+      A[j * lda + i] = A[i * lda + j];
+    } else {
+      const double v = 0.5 * (A[i * lda + j] + A[j * lda + i]);
+      A[i * lda + j] = v;
+      A[j * lda + i] = v;
+    }
+  }
+}
+
+// Unblocked Cholesky of one nb x nb diagonal block (upper, in place), in LDS.
+constexpr int CB = 64;
+__global__ __launch_bounds__(256) void potf2_kernel(double* S, int64_t lds, int b0, int w, int* status) {
+  __shared__ double A[CB][CB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int t = tid; t < w * w; t += 256) {
+    const int r = t / w, c = t - (t / w) * w;
+    A[r][c] = (r <= c) ? S[static_cast<int64_t>(b0 + r) * lds + b0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    if (tid == 0) {
+      const double d = A[j][j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = 1;
+        A[j][j] = __builtin_nan("");
+      } else {
+        A[j][j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double piv = A[j][j];
+    for (int c = j + 1 + tid; c < w; c += 256) A[j][c] /= piv;
+    __syncthreads();
+    const int rem = w - j - 1;
+    for (int t = tid; t < rem * rem; t += 256) {
+      const int r = j + 1 + t / rem, c = j + 1 + (t - (t / rem) * rem);
+      if (r <= c) A[r][c] -= A[j][r] * A[j][c];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < w * w; t += 256) {
+    const int r = t / w, c = t - (t / w) * w;
+    S[static_cast<int64_t>(b0 + r) * lds + b0 + c] = (r <= c) ? A[r][c] : 0.0;
+  }
+  if (tid == 0 && bad) atomicExch(status, 1);
+}
+
+// Panel of the blocked Cholesky: rows b0..b0+w of columns c >= b0+w:
+// solve U_bb^T X = S_panel (forward substitution), 64 columns per work-group.
+__global__ __launch_bounds__(64) void chol_panel_kernel(double* S, int64_t lds, int b0, int w, int n) {
+  __shared__ double U[CB][CB + 1];
+  __shared__ double X[CB][CB + 1];
+  const int tid = threadIdx.x;
+  const int c0 = b0 + w + blockIdx.x * 64;
+  for (int t = tid; t < w * w; t += 64) {
+    const int r = t / w, c = t - (t / w) * w;
+    U[r][c] = S[static_cast<int64_t>(b0 + r) * lds + b0 + c];
+  }
+  for (int r = 0; r < w; ++r) {
+    const int c = c0 + tid;
+    X[r][tid] = (c < n) ? S[static_cast<int64_t>(b0 + r) * lds + c] : 0.0;
+  }
+  __syncthreads();
+  for (int r = 0; r < w; ++r) {
+    double acc = X[r][tid];
+    for (int q = 0; q < r; ++q) acc -= U[q][r] * X[q][tid];
+    X[r][tid] = acc / U[r][r];
+  }
+  __syncthreads();
+  for (int r = 0; r < w; ++r) {
+    const int c = c0 + tid;
+    if (c < n) S[static_cast<int64_t>(b0 + r) * lds + c] = X[r][tid];
+  }
+}
+
+__global__ void zero_lower_kernel(double* A, int64_t lda, int n) {
+  const int64_t total = static_cast<int64_t>(n) * n;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int64_t i = t / n, j = t - (t / n) * n;
+    if (i > j) A[i * lda + j] = 0.0;
+  }
+}
+
+// Y[:, b0:b0+w] <- Y[:, b0:b0+w] U_bb^{-1} row by row (forward substitution),
+// 64 rows per work-group.
+__global__ __launch_bounds__(64) void trsm_diag_kernel(double* Y, int64_t ldy, int64_t nrows,
+                                                       const double* U, int64_t ldu, int b0, int w) {
+  __shared__ double Ub[CB][CB + 1];
+  __shared__ double Yb[CB][CB + 1];
+  const int tid = threadIdx.x;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 64;
+  for (int t = tid; t < w * w; t += 64) {
+    const int r = t / w, c = t - (t / w) * w;
+    Ub[r][c] = U[static_cast<int64_t>(b0 + r) * ldu + b0 + c];
+  }
+  for (int r = 0; r < 64; ++r) {
+    const int64_t row = r0 + r;
+    if (tid < w) Yb[r][tid] = (row < nrows) ? Y[row * ldy + b0 + tid] : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < w; ++c) {
+    double a0 = Yb[tid][c], a1 = 0.0;
+    int q = 0;
+    for (; q + 1 < c; q += 2) {
+      a0 -= Yb[tid][q] * Ub[q][c];
+      a1 -= Yb[tid][q + 1] * Ub[q + 1][c];
+    }
+    if (q < c) a0 -= Yb[tid][q] * Ub[q][c];
+    Yb[tid][c] = (a0 + a1) / Ub[c][c];
+  }
+  __syncthreads();
+  for (int r = 0; r < 64; ++r) {
+    const int64_t row = r0 + r;
+    if (tid < w && row < nrows) Y[row * ldy + b0 + tid] = Yb[r][tid];
+  }
+}
+
+__global__ void fill_f64_kernel(double* d, int64_t count, double v) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < count; t += stride)
+    d[t] = v;
+}
+
+__global__ void fill_int_kernel(int* d, int64_t count, int v) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < count; t += stride)
+    d[t] = v;
+}
+
+// Sign of column j of a column-major eigenvector matrix: +1 if its
+// largest-magnitude entry (lowest row index on ties) is positive.
+__global__ __launch_bounds__(256) void colsign_kernel(const double* V, int64_t ldv, int n, double* sign) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const double* col = V + static_cast<int64_t>(j) * ldv;
+  double best = -1.0;
+  int bi = n;
+  for (int i = tid; i < n; i += 256) {
+    const double a = fabs(col[i]);
+    if (a > best) {
+      best = a;
+      bi = i;
+    }
+  }
+  sv[tid] = best;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      const double o = sv[tid + s];
+      const int oi = si[tid + s];
+      if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) {
+        sv[tid] = o;
+        si[tid] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) sign[j] = (si[0] < n && col[si[0]] < 0.0) ? -1.0 : 1.0;
+}
+
+// B[c][r] = A[r][c] * (scale ? scale[r] : 1), 32x32 LDS tiles.
+__global__ __launch_bounds__(256) void transpose_kernel(const double* A, int64_t lda, double* B,
+                                                        int64_t ldb, int rows, int cols,
+                                                        const double* scale) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int r = by + yy, c = bx + tx;
+    t[yy][tx] = (r < rows && c < cols) ? A[static_cast<int64_t>(r) * lda + c] * (scale ? scale[r] : 1.0) : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int c = bx + yy, r = by + tx;
+    if (r < rows && c < cols) B[static_cast<int64_t>(c) * ldb + r] = t[tx][yy];
+  }
+}
+
+unsigned grid1(int64_t total) {
+  int64_t g = ceil_div(total, 256);
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<unsigned>(g);
+}
+
+int choose_splits(int64_t tiles, int64_t k) {
+  int64_t s = ceil_div(2048, tiles > 0 ? tiles : 1);
+  const int64_t maxs = ceil_div(k, 1024);
+  if (s > maxs) s = maxs;
+  if (s > 64) s = 64;
+  if (s < 1) s = 1;
+  return static_cast<int>(s);
+}
+
+}  // namespace
+
+size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k) {
+  // the upper-triangle-only launch has fewer tiles, hence the most splits
+  const int64_t tm = ceil_div(m, GT);
+  const int64_t tiles = (m == n) ? (tm * (tm + 1)) / 2 : tm * ceil_div(n, GT);
+  const int s = choose_splits(tiles, k);
+  return s > 1 ? static_cast<size_t>(s) * m * n : 0;
+}
+
+int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool upper_only,
+            double* d_split_ws, size_t split_ws_elems, hipStream_t st) {
+  if (m <= 0 || n <= 0) return CHEFSI_OK;
+  const int64_t tm = ceil_div(m, GT), tn = ceil_div(n, GT);
+  int splits = choose_splits(upper_only ? (tm * (tm + 1)) / 2 : tm * tn, k);
+  if (splits > 1 && (d_split_ws == nullptr || split_ws_elems < static_cast<size_t>(splits) * m * n))
+    splits = 1;
+  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, 0, nullptr, upper_only};
+  g.kper = round_up(ceil_div(k, splits), GK);
+  if (k <= 0) g.kper = GK;
+  if (splits > 1) g.part = d_split_ws;
+  dim3 grid(static_cast<unsigned>(tn), static_cast<unsigned>(tm), static_cast<unsigned>(splits));
+  gemm_kernel<true><<<grid, GNT, 0, st>>>(g);
+  CHEFSI_LAUNCHED("gemm_tn");
+  if (splits > 1) {
+    split_reduce_kernel<<<grid1(m * n), 256, 0, st>>>(d_split_ws, splits, m, n, alpha, beta, C, ldc, upper_only);
+    CHEFSI_LAUNCHED("split_reduce");
+  }
+  return CHEFSI_OK;
+}
+
+int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st) {
+  if (m <= 0 || n <= 0) return CHEFSI_OK;
+  const int64_t tm = ceil_div(m, GT), tn = ceil_div(n, GT);
+  if (tm > 65535) return fail(CHEFSI_ERR_ARG, "gemm_nn: too many row tiles");
+  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, round_up(k > 0 ? k : 1, GK), nullptr, false};
+  dim3 grid(static_cast<unsigned>(tn), static_cast<unsigned>(tm), 1);
+  gemm_kernel<false><<<grid, GNT, 0, st>>>(g);
+  CHEFSI_LAUNCHED("gemm_nn");
+  return CHEFSI_OK;
+}
+
+int launch_symmetrize(double* A, int64_t lda, int n, bool mirror_upper, hipStream_t st) {
+  symmetrize_kernel<<<grid1(static_cast<int64_t>(n) * n), 256, 0, st>>>(A, lda, n, mirror_upper);
+  CHEFSI_LAUNCHED("symmetrize");
+  return CHEFSI_OK;
+}
+
+int cholesky_upper(double* S, int64_t lds, int n, int* d_status, hipStream_t st) {
+  for (int b0 = 0; b0 < n; b0 += CB) {
+    const int w = (n - b0) < CB ? (n - b0) : CB;
+    potf2_kernel<<<1, 256, 0, st>>>(S, lds, b0, w, d_status);
+    CHEFSI_LAUNCHED("potf2");
+    const int rest = n - b0 - w;
+    if (rest > 0) {
+      chol_panel_kernel<<<static_cast<unsigned>(ceil_div(rest, 64)), 64, 0, st>>>(S, lds, b0, w, n);
+      CHEFSI_LAUNCHED("chol_panel");
+      double* P = S + static_cast<int64_t>(b0) * lds + b0 + w;
+      double* T = S + static_cast<int64_t>(b0 + w) * lds + b0 + w;
+      CHEFSI_TRY(gemm_tn(rest, rest, w, -1.0, P, lds, P, lds, 1.0, T, lds, true, nullptr, 0, st));
+    }
+  }
+  zero_lower_kernel<<<grid1(static_cast<int64_t>(n) * n), 256, 0, st>>>(S, lds, n);
+  CHEFSI_LAUNCHED("zero_lower");
+  return CHEFSI_OK;
+}
+
+int trsm_right_upper(double* Y, int64_t ldy, int64_t nrows, const double* U, int64_t ldu, int n,
+                     hipStream_t st) {
+  if (nrows <= 0) return CHEFSI_OK;
+  for (int b0 = 0; b0 < n; b0 += CB) {
+    const int w = (n - b0) < CB ? (n - b0) : CB;
+    if (b0 > 0) {
+      CHEFSI_TRY(gemm_nn(nrows, w, b0, -1.0, Y, ldy, U + b0, ldu, 1.0, Y + b0, ldy, st));
+    }
+    trsm_diag_kernel<<<static_cast<unsigned>(ceil_div(nrows, 64)), 64, 0, st>>>(Y, ldy, nrows, U, ldu, b0, w);
+    CHEFSI_LAUNCHED("trsm_diag");
+  }
+  return CHEFSI_OK;
+}
+
+int launch_fill(double* d, int64_t count, double v, hipStream_t st) {
+  if (count <= 0) return CHEFSI_OK;
+  fill_f64_kernel<<<grid1(count), 256, 0, st>>>(d, count, v);
+  CHEFSI_LAUNCHED("fill");
+  return CHEFSI_OK;
+}
+
+int launch_fill_int(int* d, int64_t count, int v, hipStream_t st) {
+  if (count <= 0) return CHEFSI_OK;
+  fill_int_kernel<<<grid1(count), 256, 0, st>>>(d, count, v);
+  CHEFSI_LAUNCHED("fill_int");
+  return CHEFSI_OK;
+}
+
+int trmm_upper_upper(const double* A, const double* B, double* C, int n, hipStream_t st) {
+  return gemm_nn(n, n, n, 1.0, A, n, B, n, 0.0, C, n, st);
+}
+
+int launch_transpose(const double* A, int64_t lda, double* B, int64_t ldb, int rows, int cols,
+                     hipStream_t st) {
+  dim3 grid(static_cast<unsigned>(ceil_div(cols, 32)), static_cast<unsigned>(ceil_div(rows, 32)));
+  transpose_kernel<<<grid, 256, 0, st>>>(A, lda, B, ldb, rows, cols, nullptr);
+  CHEFSI_LAUNCHED("transpose");
+  return CHEFSI_OK;
+}
+
+// Vcm: n x n eigenvectors in column-major order (column j = eigenvector j);
+// Q (row-major) gets Q[i][j] = sign_j * Vcm[j*ldv + i].  Q[n..] holds scratch
+// for the n signs: the caller passes Q with room for n*ldq + n doubles.
+int launch_eigvec_fix(const double* Vcm, int64_t ldv, int n, double* Q, int64_t ldq, hipStream_t st) {
+  double* sign = Q + static_cast<int64_t>(n) * ldq;
+  colsign_kernel<<<static_cast<unsigned>(n), 256, 0, st>>>(Vcm, ldv, n, sign);
+  CHEFSI_LAUNCHED("colsign");
+  // Vcm viewed row-major is V^T (row j = eigenvector j): transpose with row scale.
+  dim3 grid(static_cast<unsigned>(ceil_div(n, 32)), static_cast<unsigned>(ceil_div(n, 32)));
+  transpose_kernel<<<grid, 256, 0, st>>>(Vcm, ldv, Q, ldq, n, n, sign);
+  CHEFSI_LAUNCHED("eigvec_transpose");
+  return CHEFSI_OK;
+}
+
+}  // namespace chefsi

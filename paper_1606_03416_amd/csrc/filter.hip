@@ -1,0 +1,518 @@
+// Chebyshev filter hot path for gfx950: block-sparse H^DG x multivector with
+// the three-term recurrence fused into the epilogue.
+//
+// One work-group computes the rows of one element K for kStepTN = 128
+// columns.  Its reduction runs over the concatenation of the stencil
+// neighbours' rows (eq. matvec_3: y_K = sum_{K' in N(K)} H_{K;K'} x_{K'}),
+// staged through LDS in chunks of kStepKC rows: the packed panel of H (k-major,
+// written once per call by the repack kernel) and the gathered neighbour rows
+// of the input block.  Four waves split the 128 columns; each wave keeps
+// RB x 2 MFMA 16x16 accumulators (RB = ceil(J_K/16)).  The recurrence
+// Y_{k+1} = alpha_k (H Y_k - c Y_k) - beta_k Y_{k-1} is applied in the
+// epilogue, so a step reads Y_k, Y_{k-1} and writes Y_{k+1} once.
+#include "common.h"
+
+namespace chefsi {
+
+namespace {
+
+constexpr int TN = kStepTN;
+constexpr int KC = kStepKC;
+constexpr int NT = 256;
+
+template <typename TC>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element q of a lane sits in row 4q + lane/16 (column lane%16)
+  static __device__ __forceinline__ int row(int lane, int q) { return 4 * q + (lane >> 4); }
+  static constexpr int pad = 2;
+};
+
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element q of a lane sits in row 4(lane/16) + q (column lane%16)
+  static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+  static constexpr int pad = 4;
+};
+
+struct StepArgs {
+  const void* panel;
+  const int64_t* poff;
+  const int32_t* kpad;
+  const int64_t* koff;
+  const int32_t* kmap;
+  const int32_t* J;
+  const int32_t* rbv;
+  const int64_t* rowoff;
+  const int32_t* order;
+  const double* coef;
+  const void* in;
+  int64_t ldi;
+  const void* prev;
+  int64_t ldp;
+  void* out;
+  int64_t ldo;
+  const double* theta;
+  double* part;
+  int ns;
+  int M;
+};
+
+// Work-group id -> linear work index, so that the work-groups one XCD runs
+// (hardware id b goes to XCD b % 8) are consecutive work items.
+__device__ __forceinline__ int xcd_linear(int b, int nwg) {
+  const int q = nwg >> 3, r = nwg & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+template <typename TC, typename TOUT, int RB, int EPI, int LDA>
+__device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* sA, TC* sB) {
+  using MF = Mfma<TC>;
+  using acc_t = typename MF::acc_t;
+  constexpr int JP = RB * 16;
+  constexpr int LDB = TN + MF::pad;
+  constexpr int AQ = (KC * JP) / NT;   // A elements per thread per chunk
+  constexpr int BQ = (KC * TN) / NT;   // B elements per thread per chunk
+  static_assert((KC * JP) % NT == 0, "A chunk must split evenly");
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int j0 = ct * TN;
+  const int ns = a.ns;
+  const TC* __restrict__ panel = static_cast<const TC*>(a.panel) + a.poff[K];
+  const int32_t* __restrict__ kmap = a.kmap + a.koff[K];
+  const TC* in = static_cast<const TC*>(a.in);
+  const int64_t ldi = a.ldi;
+  const int nch = a.kpad[K] / KC;
+  const int bcol = tid & (TN - 1);
+  const int brow0 = tid / TN;
+  const bool col_ok = (j0 + bcol) < ns;
+
+  TC ra[AQ];
+  TC rb[BQ];
+
+  auto gload = [&](int c) {
+    const TC* pa = panel + static_cast<int64_t>(c) * (KC * JP);
+#pragma unroll
+    for (int q = 0; q < AQ; ++q) ra[q] = pa[tid + NT * q];
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int row = brow0 + (NT / TN) * q;
+      const int g = kmap[c * KC + row];
+      rb[q] = (g >= 0 && col_ok) ? in[static_cast<int64_t>(g) * ldi + j0 + bcol] : TC(0);
+    }
+  };
+  auto sstore = [&](int buf) {
+    TC* A = sA + buf * (KC * LDA);
+    TC* B = sB + buf * (KC * LDB);
+#pragma unroll
+    for (int q = 0; q < AQ; ++q) {
+      const int e = tid + NT * q;
+      A[(e / JP) * LDA + (e % JP)] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) B[(brow0 + (NT / TN) * q) * LDB + bcol] = rb[q];
+  };
+
+  acc_t acc[RB][2];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = acc_t{0, 0, 0, 0};
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) gload(c + 1);
+    const TC* A = sA + buf * (KC * LDA);
+    const TC* B = sB + buf * (KC * LDB);
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int krow = kk * 4 + (lane >> 4);
+      TC av[RB], bv[2];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) av[r] = A[krow * LDA + r * 16 + (lane & 15)];
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) bv[c2] = B[krow * LDB + wave * 32 + c2 * 16 + (lane & 15)];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = MF::mma(av[r], bv[c2], acc[r][c2]);
+    }
+    if (c + 1 < nch) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  const int JK = a.J[K];
+  const int64_t g0 = a.rowoff[K];
+  if constexpr (EPI == 0) {
+    const TC alpha = static_cast<TC>(a.coef[0]);
+    const TC beta = static_cast<TC>(a.coef[1]);
+    const TC cc = static_cast<TC>(a.coef[2]);
+    const TC* prev = static_cast<const TC*>(a.prev);
+    TOUT* out = static_cast<TOUT*>(a.out);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) {
+        const int j = j0 + wave * 32 + c2 * 16 + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = r * 16 + MF::row(lane, q);
+          if (i < JK && j < ns) {
+            const int64_t g = g0 + i;
+            TC v = alpha * (acc[r][c2][q] - cc * in[g * ldi + j]);
+            if (prev != nullptr) v -= beta * prev[g * a.ldp + j];
+            out[g * a.ldo + j] = static_cast<TOUT>(v);
+          }
+        }
+      }
+  } else {
+    // residual partial sums: sum over the element's rows of (H x - theta x)^2
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int j = j0 + wave * 32 + c2 * 16 + (lane & 15);
+      const double th = (j < ns) ? a.theta[j] : 0.0;
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = r * 16 + MF::row(lane, q);
+          if (i < JK && j < ns) {
+            const double v = static_cast<double>(acc[r][c2][q]) -
+                             th * static_cast<double>(in[(g0 + i) * ldi + j]);
+            s += v * v;
+          }
+        }
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      if (lane < 16 && j < ns) a.part[static_cast<int64_t>(K) * ns + j] = s;
+    }
+  }
+}
+
+// UNIFORM_RB > 0: every element has UNIFORM_RB row blocks; 0: switch per element.
+template <typename TC, typename TOUT, int EPI, int UNIFORM_RB>
+__global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
+  constexpr int MAXRB = UNIFORM_RB > 0 ? UNIFORM_RB : 8;
+  constexpr int LDA = MAXRB * 16 + Mfma<TC>::pad;
+  constexpr int LDB = TN + Mfma<TC>::pad;
+  __shared__ TC sA[2 * KC * LDA];
+  __shared__ TC sB[2 * KC * LDB];
+  const int id = xcd_linear(blockIdx.x, gridDim.x);
+  const int ct = id / a.M;
+  const int e = id - ct * a.M;
+  const int K = a.order[e];
+  if constexpr (UNIFORM_RB > 0) {
+    step_body<TC, TOUT, UNIFORM_RB, EPI, LDA>(a, K, ct, sA, sB);
+  } else {
+    switch (a.rbv[K]) {
+      case 1: step_body<TC, TOUT, 1, EPI, LDA>(a, K, ct, sA, sB); break;
+      case 2: step_body<TC, TOUT, 2, EPI, LDA>(a, K, ct, sA, sB); break;
+      case 3: step_body<TC, TOUT, 3, EPI, LDA>(a, K, ct, sA, sB); break;
+      case 4: step_body<TC, TOUT, 4, EPI, LDA>(a, K, ct, sA, sB); break;
+      case 5: step_body<TC, TOUT, 5, EPI, LDA>(a, K, ct, sA, sB); break;
+      case 6: step_body<TC, TOUT, 6, EPI, LDA>(a, K, ct, sA, sB); break;
+      case 7: step_body<TC, TOUT, 7, EPI, LDA>(a, K, ct, sA, sB); break;
+      default: step_body<TC, TOUT, 8, EPI, LDA>(a, K, ct, sA, sB); break;
+    }
+  }
+}
+
+template <typename TC, typename TOUT, int EPI>
+int dispatch_step(const Plan& p, const StepArgs& a, int ns, hipStream_t st) {
+  const int64_t nct = ceil_div(ns, TN);
+  const int64_t nwg = nct * p.M;
+  if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
+  dim3 grid(static_cast<unsigned>(nwg)), block(NT);
+  if (p.uniform) {
+    switch (p.maxRB) {
+      case 1: step_kernel<TC, TOUT, EPI, 1><<<grid, block, 0, st>>>(a); break;
+      case 2: step_kernel<TC, TOUT, EPI, 2><<<grid, block, 0, st>>>(a); break;
+      case 3: step_kernel<TC, TOUT, EPI, 3><<<grid, block, 0, st>>>(a); break;
+      case 4: step_kernel<TC, TOUT, EPI, 4><<<grid, block, 0, st>>>(a); break;
+      case 5: step_kernel<TC, TOUT, EPI, 5><<<grid, block, 0, st>>>(a); break;
+      case 6: step_kernel<TC, TOUT, EPI, 6><<<grid, block, 0, st>>>(a); break;
+      case 7: step_kernel<TC, TOUT, EPI, 7><<<grid, block, 0, st>>>(a); break;
+      default: step_kernel<TC, TOUT, EPI, 8><<<grid, block, 0, st>>>(a); break;
+    }
+  } else {
+    step_kernel<TC, TOUT, EPI, 0><<<grid, block, 0, st>>>(a);
+  }
+  CHEFSI_LAUNCHED("cheb_step");
+  return CHEFSI_OK;
+}
+
+StepArgs base_args(const Plan& p, const void* panel, int ns) {
+  StepArgs a{};
+  a.panel = panel;
+  a.poff = p.d_poff;
+  a.kpad = p.d_kpad;
+  a.koff = p.d_koff;
+  a.kmap = p.d_kmap;
+  a.J = p.d_J;
+  a.rbv = p.d_rb;
+  a.rowoff = p.d_rowoff;
+  a.order = p.d_order;
+  a.ns = ns;
+  a.M = p.M;
+  return a;
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void set_bounds_kernel(double a, double b, double a0, double* d) {
+  if (threadIdx.x == 0) {
+    d[0] = a;
+    d[1] = b;
+    d[2] = a0;
+  }
+}
+
+// coef[3k + {0,1,2}] = (alpha_k, beta_k, c) of the scaled recurrence.
+__global__ void cheb_coef_kernel(const double* bounds, int m, double* coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double a = bounds[0], b = bounds[1], a0 = bounds[2];
+  const double e = 0.5 * (b - a);
+  const double c = 0.5 * (b + a);
+  const double s1 = e / (a0 - c);
+  const double tau = 2.0 / s1;
+  double s = s1;
+  for (int k = 0; k < m; ++k) {
+    if (k == 0) {
+      coef[0] = s1 / e;
+      coef[1] = 0.0;
+    } else {
+      const double sn = 1.0 / (tau - s);
+      coef[3 * k + 0] = 2.0 * sn / e;
+      coef[3 * k + 1] = s * sn;
+      s = sn;
+    }
+    coef[3 * k + 2] = c;
+  }
+}
+
+__global__ void const_coef_kernel(double alpha, double c, double* coef) {
+  if (threadIdx.x == 0) {
+    coef[0] = alpha;
+    coef[1] = 0.0;
+    coef[2] = c;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T cvt(double v) {
+  return static_cast<T>(v);
+}
+template <>
+__device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16>(double v) {
+  return __float2bfloat16(static_cast<float>(v));
+}
+
+template <typename T>
+__global__ void fill_kernel(T* d, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = i; t < count; t += stride) d[t] = cvt<T>(0.0);
+}
+
+// Scatter the stored blocks into per-element panels:
+//   panel_K[pre_s + r][i] = H_{K;K'_s}[i][r]    (or of H^T when transposing)
+// with one 32x32 tile of one block per work-group (LDS transpose).
+struct RepackArgs {
+  const double* H;
+  const int64_t* hoff;
+  const int32_t* nbr;
+  const int32_t* J;
+  const int64_t* poff;
+  const int32_t* rbv;
+  int S;
+  bool transpose_h;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void repack_kernel(RepackArgs ra, T* panel_base) {
+  __shared__ double tile[32][33];
+  const int blk = blockIdx.y;  // K * S + s
+  const int K = blk / ra.S;
+  const int s = blk - K * ra.S;
+  const int Kp = ra.nbr[blk];
+  const int JK = ra.J[K], JKp = ra.J[Kp];
+  const int JP = ra.rbv[K] * 16;
+  int pre = 0;
+  for (int t = 0; t < s; ++t) pre += ra.J[ra.nbr[K * ra.S + t]];
+  const int sopp = (s == 0) ? 0 : ((s & 1) ? s + 1 : s - 1);
+  // panel row index k = pre + (column of H_{K;K'}), panel column = row of H_{K;K'}
+  // Normal: source H_{K;s} (JK x JKp) -> panel[pre + c][r] (transpose).
+  // H^T:    source H_{K';opp(s)} (JKp x JK), element [r][c] = (H^T)_{K;K'}[c][r]
+  //         -> panel[pre + r][c] (copy).
+  const double* src = ra.transpose_h ? ra.H + ra.hoff[Kp * ra.S + sopp] : ra.H + ra.hoff[blk];
+  const int R = ra.transpose_h ? JKp : JK;
+  const int C = ra.transpose_h ? JK : JKp;
+  const int tilesC = (C + 31) / 32;
+  const int tr = blockIdx.x / tilesC;
+  const int tc = blockIdx.x - tr * tilesC;
+  if (tr * 32 >= R) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int r = tr * 32 + yy, c = tc * 32 + tx;
+    tile[yy][tx] = (r < R && c < C) ? src[static_cast<int64_t>(r) * C + c] : 0.0;
+  }
+  __syncthreads();
+  T* panel = panel_base + ra.poff[K];
+  if (!ra.transpose_h) {
+    // panel[pre + c][r] = tile[r][c]; write along r (panel columns) for coalescing
+    for (int yy = ty; yy < 32; yy += 8) {
+      const int c = tc * 32 + yy, r = tr * 32 + tx;
+      if (c < C && r < R) panel[static_cast<int64_t>(pre + c) * JP + r] = cvt<T>(tile[tx][yy]);
+    }
+  } else {
+    for (int yy = ty; yy < 32; yy += 8) {
+      const int r = tr * 32 + yy, c = tc * 32 + tx;
+      if (r < R && c < C) panel[static_cast<int64_t>(pre + r) * JP + c] = cvt<T>(tile[yy][tx]);
+    }
+  }
+}
+
+template <typename TS, typename TD>
+__global__ void convert_kernel(const TS* src, int64_t lds, TD* dst, int64_t ldd, int64_t n, int ns) {
+  const int64_t total = n * ns;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int64_t r = t / ns;
+    const int c = static_cast<int>(t - r * ns);
+    dst[r * ldd + c] = cvt<TD>(static_cast<double>(src[r * lds + c]));
+  }
+}
+
+__global__ void colsum_sqrt_kernel(const double* part, int rows, int ns, double* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  double s = 0.0;
+  for (int r = 0; r < rows; ++r) s += part[static_cast<int64_t>(r) * ns + j];
+  out[j] = sqrt(s);
+}
+
+unsigned grid_for(int64_t total, int threads = 256) {
+  int64_t g = ceil_div(total, threads);
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<unsigned>(g);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+int launch_set_bounds(double a, double b, double a0, double* d_bounds, hipStream_t st) {
+  set_bounds_kernel<<<1, 64, 0, st>>>(a, b, a0, d_bounds);
+  CHEFSI_LAUNCHED("set_bounds");
+  return CHEFSI_OK;
+}
+
+int launch_cheb_coef(const double* d_bounds, int m, double* d_coef, hipStream_t st) {
+  cheb_coef_kernel<<<1, 64, 0, st>>>(d_bounds, m, d_coef);
+  CHEFSI_LAUNCHED("cheb_coef");
+  return CHEFSI_OK;
+}
+
+int launch_const_coef(double alpha, double c, double* d_coef, hipStream_t st) {
+  const_coef_kernel<<<1, 64, 0, st>>>(alpha, c, d_coef);
+  CHEFSI_LAUNCHED("const_coef");
+  return CHEFSI_OK;
+}
+
+int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h, void* d_panel,
+                  hipStream_t st) {
+  const unsigned fill_grid = grid_for(p.panel_elems);
+  RepackArgs ra{d_H, p.d_hoff, p.d_nbr, p.d_J, p.d_poff, p.d_rb, p.stencil, transpose_h};
+  const int tiles = static_cast<int>(ceil_div(p.maxJ, 32) * ceil_div(p.maxJ, 32));
+  dim3 grid(tiles, p.M * p.stencil);
+  if (dtype == CHEFSI_F64) {
+    fill_kernel<double><<<fill_grid, 256, 0, st>>>(static_cast<double*>(d_panel), p.panel_elems);
+    repack_kernel<double><<<grid, 256, 0, st>>>(ra, static_cast<double*>(d_panel));
+  } else if (dtype == CHEFSI_F32) {
+    fill_kernel<float><<<fill_grid, 256, 0, st>>>(static_cast<float*>(d_panel), p.panel_elems);
+    repack_kernel<float><<<grid, 256, 0, st>>>(ra, static_cast<float*>(d_panel));
+  } else {
+    return fail(CHEFSI_ERR_UNSUPPORTED, "repack: dtype");
+  }
+  CHEFSI_LAUNCHED("repack");
+  return CHEFSI_OK;
+}
+
+int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_coef,
+                const StepIO& io, int ns, hipStream_t st) {
+  if (ns <= 0) return CHEFSI_OK;
+  StepArgs a = base_args(p, d_panel, ns);
+  a.coef = d_coef;
+  a.in = io.in;
+  a.ldi = io.ldi;
+  a.prev = io.prev;
+  a.ldp = io.ldp;
+  a.out = io.out;
+  a.ldo = io.ldo;
+  if (dtype == CHEFSI_F64) {
+    if (!io.in_f64 || (io.prev && !io.prev_f64) || !io.out_f64)
+      return fail(CHEFSI_ERR_ARG, "step: FP64 step needs FP64 operands");
+    return dispatch_step<double, double, 0>(p, a, ns, st);
+  }
+  if (dtype == CHEFSI_F32) {
+    if (io.in_f64 || (io.prev && io.prev_f64))
+      return fail(CHEFSI_ERR_ARG, "step: FP32 step needs FP32 inputs");
+    if (io.out_f64) return dispatch_step<float, double, 0>(p, a, ns, st);
+    return dispatch_step<float, float, 0>(p, a, ns, st);
+  }
+  return fail(CHEFSI_ERR_UNSUPPORTED, "step: dtype");
+}
+
+int launch_resid_partial(const Plan& p, const void* d_panel, const double* d_X, int64_t ldx,
+                         const double* d_theta, int ns, double* d_part, hipStream_t st) {
+  if (ns <= 0) return CHEFSI_OK;
+  StepArgs a = base_args(p, d_panel, ns);
+  a.in = d_X;
+  a.ldi = ldx;
+  a.theta = d_theta;
+  a.part = d_part;
+  return dispatch_step<double, double, 1>(p, a, ns, st);
+}
+
+int launch_colsum_sqrt(const double* d_part, int rows, int ns, double* d_out, hipStream_t st) {
+  if (ns <= 0) return CHEFSI_OK;
+  colsum_sqrt_kernel<<<static_cast<unsigned>(ceil_div(ns, 256)), 256, 0, st>>>(d_part, rows, ns, d_out);
+  CHEFSI_LAUNCHED("colsum_sqrt");
+  return CHEFSI_OK;
+}
+
+int launch_convert(const double* src, int64_t lds, void* dst, int dst_dtype, int64_t ldd,
+                   int64_t n, int ns, hipStream_t st) {
+  const unsigned g = grid_for(n * ns);
+  if (dst_dtype == CHEFSI_F64)
+    convert_kernel<double, double><<<g, 256, 0, st>>>(src, lds, static_cast<double*>(dst), ldd, n, ns);
+  else if (dst_dtype == CHEFSI_F32)
+    convert_kernel<double, float><<<g, 256, 0, st>>>(src, lds, static_cast<float*>(dst), ldd, n, ns);
+  else
+    return fail(CHEFSI_ERR_UNSUPPORTED, "convert: dtype");
+  CHEFSI_LAUNCHED("convert");
+  return CHEFSI_OK;
+}
+
+int launch_copy_f64(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int ns,
+                    hipStream_t st) {
+  return launch_convert(src, lds, dst, CHEFSI_F64, ldd, n, ns, st);
+}
+
+}  // namespace chefsi

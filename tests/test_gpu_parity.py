@@ -1,0 +1,250 @@
+"""GPU parity: every entry point of the C ABI against the FP64 CPU oracle on the
+same seeded inputs.  Tolerances: filtered block 1e-12 relative Frobenius,
+Ritz values 1e-10 relative to max(|theta|, s) with s = max(|a0|, |b|),
+orthonormality ||Yhat^T Yhat - I||_2 <= 1e-12."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import core
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def mkplan(lib, P):
+    return lib.Plan(P.grid, P.stencil, P.J)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relf(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def ritz_rel(t_gpu, t_ora, s):
+    return float(np.max(np.abs(t_gpu - t_ora) / np.maximum(np.abs(t_ora), s)))
+
+
+def mixed_problem():
+    J = np.array([8, 16, 24, 40, 64, 128, 72, 88, 104, 120, 56, 32], dtype=np.int32)
+    return synth.make_blocks((4, 3, 1), 5, J)
+
+
+PROBLEMS = {
+    "tiny": lambda: synth.make_problem(synth.TINY),
+    "len1_z_7pt": lambda: synth.make_blocks((3, 2, 1), 7, np.full(6, 24, dtype=np.int32)),
+    "mixed_5pt": mixed_problem,
+    "odd_3x3x3_nb40": lambda: synth.make_blocks((3, 3, 3), 7, np.full(27, 40, dtype=np.int32)),
+}
+
+
+# ---------------------------------------------------------------- filter
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("ns,m", [(48, 10), (1, 3), (130, 7), (257, 2)])
+def test_filter_f64_matches_oracle(lib, name, ns, m):
+    P = PROBLEMS[name]()
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    X = synth.make_start_block(P.J, ns)
+    a, b, a0 = 0.3, 5.5, -1.2
+    ref = oracle.chebyshev_filter(oracle.DenseOperator(H), X, m, a, b, a0)
+    plan = mkplan(lib, P)
+    Y = plan.filter(dev(P.packed()), dev(X), m, a, b, a0)
+    assert relf(host(Y), ref) <= 1e-12
+
+
+def test_filter_degree_zero_one_and_strided(lib):
+    P = synth.make_problem(synth.TINY)
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    plan = mkplan(lib, P)
+    Hd = dev(P.packed())
+    X = synth.make_start_block(P.J, 40)
+    # strided views: leading dimensions larger than ns
+    Xbig = dev(np.concatenate([X, np.zeros((P.N, 9))], axis=1))
+    Xv = Xbig[:, :40]
+    Ybig = torch.full((P.N, 57), 7.0, dtype=torch.float64, device="cuda")
+    Yv = Ybig[:, 3:43]
+    for m in (0, 1, 2):
+        plan.filter(Hd, Xv, m, 0.1, 4.0, -0.9, out=Yv)
+        ref = oracle.chebyshev_filter(oracle.DenseOperator(H), X, m, 0.1, 4.0, -0.9)
+        assert relf(host(Yv), ref) <= 1e-12
+    yb = host(Ybig)
+    assert np.all(yb[:, :3] == 7.0) and np.all(yb[:, 43:] == 7.0)   # untouched outside the view
+
+
+def test_filter_diff_workload_block_mode(lib):
+    w = synth.DIFF
+    P = synth.make_problem(w)
+    X = synth.make_start_block(P.J, w.ns)
+    a, b, a0 = 0.0, 5.8, -1.4
+    bop = oracle.BlockOperator(P.grid, P.stencil, P.J, P.blocks)
+    ref = oracle.chebyshev_filter(bop, X, w.m, a, b, a0)
+    plan = mkplan(lib, P)
+    Y = plan.filter(dev(P.packed()), dev(X), w.m, a, b, a0)
+    assert relf(host(Y), ref) <= 1e-12
+
+
+def test_filter_f32_error_is_small(lib):
+    P = synth.make_problem(synth.TINY)
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    X = synth.make_start_block(P.J, 64)
+    a, b, a0 = 0.2, 5.0, -1.0
+    ref = oracle.chebyshev_filter(oracle.DenseOperator(H), X, 10, a, b, a0)
+    plan = mkplan(lib, P)
+    Y = plan.filter(dev(P.packed()), dev(X), 10, a, b, a0, dtype=lib.F32)
+    err = relf(host(Y), ref)
+    print(f"FP32 filter relative error vs FP64 oracle: {err:.3e}")
+    assert 1e-9 < err <= 1e-4
+
+
+def test_filter_rejects_bad_arguments(lib):
+    P = synth.make_problem(synth.TINY)
+    plan = mkplan(lib, P)
+    Hd = dev(P.packed())
+    X = dev(synth.make_start_block(P.J, 8))
+    with pytest.raises(lib.ChefsiError) as e:
+        plan.filter(Hd, X, 3, 1.0, 1.0, -1.0)
+    assert e.value.code == lib.ERR_ARG
+    with pytest.raises(lib.ChefsiError):
+        plan.filter(Hd, X, 3, 1.0, 2.0, 1.5)
+    with pytest.raises(lib.ChefsiError):
+        plan.filter(Hd, X, -1, 0.0, 2.0, -1.5)
+    with pytest.raises(lib.ChefsiError) as e:
+        plan.filter(Hd, X, 3, 0.0, 2.0, -1.5, out=X)
+    assert e.value.code == lib.ERR_ARG
+
+
+# ---------------------------------------------------------------- Cholesky-QR
+@pytest.mark.parametrize("n,ns,passes", [(256, 48, 2), (256, 48, 1), (3000, 200, 2), (10368, 512, 2), (700, 65, 2)])
+def test_orthonormalize_matches_oracle(lib, n, ns, passes):
+    g = np.random.default_rng(n + ns)
+    Y = g.standard_normal((n, ns)) @ np.diag(np.logspace(0, 2, ns))
+    Yh_o, U_o, _ = oracle.cholesky_qr(Y, passes)
+    Yd = dev(Y)
+    U = lib.orthonormalize(Yd, passes=passes, want_U=True)
+    Yh = host(Yd)
+    kappa = np.linalg.cond(Y)
+    assert np.linalg.norm(Yh.T @ Yh - np.eye(ns), 2) <= (1e-12 if passes == 2 else 1e-15 * kappa ** 2 * 50)
+    Uh = host(U)
+    assert np.allclose(np.tril(Uh, -1), 0.0)
+    assert np.linalg.norm(Uh - U_o) / np.linalg.norm(U_o) <= 1e-12 * kappa
+    assert np.linalg.norm(Yh - Yh_o) / np.linalg.norm(Yh_o) <= 1e-13 * kappa ** (2 if passes == 1 else 1) * 10
+
+
+def test_orthonormalize_not_pd(lib):
+    g = np.random.default_rng(1)
+    Y = g.standard_normal((300, 20))
+    Y[:, 7] = 0.0
+    with pytest.raises(lib.ChefsiError) as e:
+        lib.orthonormalize(dev(Y), passes=1)
+    assert e.value.code == lib.ERR_NOT_PD
+
+
+# ---------------------------------------------------------------- Rayleigh-Ritz
+@pytest.mark.parametrize("name,ns", [("tiny", 48), ("mixed_5pt", 100), ("odd_3x3x3_nb40", 300)])
+def test_rayleigh_ritz_matches_oracle(lib, name, ns):
+    P = PROBLEMS[name]()
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    op = oracle.DenseOperator(H)
+    X = synth.make_start_block(P.J, ns)
+    Yt = oracle.chebyshev_filter(op, X, 8, 0.5, 6.0, -1.5)
+    Yh, _, _ = oracle.cholesky_qr(Yt, 2)
+    Xn_o, th_o, r_o, Q_o, _ = oracle.rayleigh_ritz(op, Yh)
+    plan = mkplan(lib, P)
+    Xn, th, r, Q = plan.rayleigh_ritz(dev(P.packed()), dev(Yh), want_Q=True)
+    th, r, Xn, Q = host(th), host(r), host(Xn), host(Q)
+    s = 6.0
+    assert ritz_rel(th, th_o, s) <= 1e-10
+    assert np.max(np.abs(r - r_o)) <= 1e-10 * s
+    # eigenvectors: compare columns whose eigenvalue is separated from its neighbours
+    gaps = np.minimum(np.diff(th_o, prepend=-np.inf), np.diff(th_o, append=np.inf))
+    ok = gaps > 1e-4 * s
+    assert np.max(np.abs(Q[:, ok] - Q_o[:, ok])) <= 1e-8
+    assert np.max(np.abs(Xn[:, ok] - Xn_o[:, ok])) <= 1e-8
+    assert np.linalg.norm(Xn.T @ Xn - np.eye(ns), 2) <= 1e-12
+
+
+# ---------------------------------------------------------------- bounds
+@pytest.mark.parametrize("name", ["tiny", "mixed_5pt"])
+def test_bounds_match_oracle(lib, name):
+    P = PROBLEMS[name]()
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    op = oracle.DenseOperator(H)
+    v0 = synth.make_lanczos_start(P.N)
+    ns = 48
+    b_o, th_l, tau = oracle.lanczos_upper_bound(op, v0, 20)
+    a_o, _, a0_o = oracle.bounds_cold(b_o, th_l, tau, ns, P.N)
+    plan = mkplan(lib, P)
+    Hd = dev(P.packed())
+    a, b, a0 = plan.bounds(Hd, dev(v0), 20, ns=ns)
+    assert abs(b - b_o) <= 1e-12 * abs(b_o)
+    assert abs(a - a_o) <= 1e-10 * abs(b_o) and abs(a0 - a0_o) <= 1e-10 * abs(b_o)
+    assert b >= np.linalg.eigvalsh(H)[-1]
+    ritz = np.sort(np.random.default_rng(0).uniform(-1, 2, ns))
+    a, b, a0 = plan.bounds(Hd, dev(v0), 20, ritz_prev=dev(ritz))
+    aw, bw, a0w = oracle.bounds_warm(ritz, b_o)
+    assert (a, a0) == (aw, a0w) and abs(b - bw) <= 1e-12 * abs(bw)
+
+
+# ---------------------------------------------------------------- full cycle
+def test_sweep_tiny_external_bounds_match_oracle(lib):
+    w = synth.TINY
+    P = synth.make_problem(w)
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    op = oracle.DenseOperator(H)
+    X0 = synth.make_start_block(P.J, w.ns)
+    v0 = synth.make_lanczos_start(P.N)
+    _, th_o, r_o, hist = core.run_sweeps(op, X0, v0, w.m, w.sweeps)
+    plan = mkplan(lib, P)
+    Hd = dev(P.packed())
+    X = dev(X0)
+    for (bnds, th_i, _) in hist:
+        ritz, resid, _, _ = plan.sweep(Hd, X, w.m, bounds=bnds)
+        s = max(abs(bnds[2]), abs(bnds[1]))
+        assert ritz_rel(host(ritz), th_i, s) <= 1e-10
+    k = 3 * w.ns // 4
+    lam = np.linalg.eigvalsh(H)
+    assert np.max(np.abs(host(ritz)[:k] - lam[:k])) <= 1e-8 * 6
+
+
+def test_sweep_own_policy_converges_like_oracle(lib):
+    w = synth.TINY
+    P = synth.make_problem(w)
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    op = oracle.DenseOperator(H)
+    X0 = synth.make_start_block(P.J, w.ns)
+    v0 = synth.make_lanczos_start(P.N)
+    _, th_o, _, hist = core.run_sweeps(op, X0, v0, w.m, w.sweeps)
+    plan = mkplan(lib, P)
+    Hd, X, v0d = dev(P.packed()), dev(X0), dev(v0)
+    ritz = None
+    for i in range(w.sweeps):
+        ritz, resid, bused, st = plan.sweep(Hd, X, w.m, v0=v0d, ritz=ritz, warm=i > 0, stats=True)
+        bo = hist[i][0]
+        assert np.max(np.abs(host(bused) - np.array(bo))) <= 1e-9 * 6, (i, host(bused), bo)
+        assert st["total_ms"] > 0
+    assert ritz_rel(host(ritz), th_o, 6.0) <= 1e-10
+
+
+def test_sweep_f32_filter_then_f64_finish(lib):
+    w = synth.TINY
+    P = synth.make_problem(w)
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    lam = np.linalg.eigvalsh(H)
+    plan = mkplan(lib, P)
+    Hd, X, v0d = dev(P.packed()), dev(synth.make_start_block(P.J, w.ns)), dev(synth.make_lanczos_start(P.N))
+    ritz = None
+    for i in range(6):
+        dt = lib.F32 if i < 3 else lib.F64
+        ritz, resid, _, _ = plan.sweep(Hd, X, w.m, dtype=dt, v0=v0d, ritz=ritz, warm=i > 0)
+    k = 3 * w.ns // 4
+    assert np.max(np.abs(host(ritz)[:k] - lam[:k])) <= 1e-9 * 6
