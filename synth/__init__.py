@@ -20,7 +20,8 @@ dimension of length 2 reaches the same neighbour through two slots and a
 length-1 dimension reaches the element itself; such blocks *add* when the
 dense matrix is formed.  Element K owns its +x/+y/+z faces: the +d block is
 drawn as G and the -d block of the neighbour is G^T, which makes the dense
-matrix exactly (bitwise) symmetric.
+matrix exactly (bitwise) symmetric, except that a length-1 dimension adds
+three terms onto a diagonal block and is symmetric to rounding.
 
 Value distributions: diagonal blocks Q diag(lambda) Q^T with lambda ~ U[lo, hi]
 and Q Haar-random (QR of a Gaussian matrix with the signs of diag(R) folded
@@ -218,16 +219,34 @@ def make_problem(w: Workload, base_seed: int = BASE_SEED, **kw) -> BlockProblem:
                        sigma_off=w.sigma_off, base_seed=base_seed, **kw)
 
 
-def make_start_block(J: np.ndarray, ns: int, base_seed: int = BASE_SEED, dtype=np.float64) -> np.ndarray:
-    """X0 ~ N(0,1), N x ns, drawn element by element (rows of element K)."""
+def make_start_block(J: np.ndarray, ns: int, base_seed: int = BASE_SEED, dtype=np.float64,
+                     threads: int = 0) -> np.ndarray:
+    """X0 ~ N(0,1), N x ns, drawn element by element (rows of element K).
+
+    Each element has its own stream, so drawing them on several threads gives
+    the same array."""
+    import concurrent.futures as cf
+    import os
     J = np.asarray(J)
     N = int(np.sum(J, dtype=np.int64))
     X = np.empty((N, ns), dtype=dtype)
-    r = 0
-    for K, n in enumerate(J):
-        n = int(n)
-        X[r:r + n] = rng_for(PURPOSE_X0, K, base_seed).standard_normal((n, ns))
-        r += n
+    off = np.zeros(len(J) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(J)
+
+    def fill(K):
+        g = rng_for(PURPOSE_X0, K, base_seed)
+        if dtype == np.float64:
+            g.standard_normal((int(J[K]), ns), out=X[off[K]:off[K + 1]])
+        else:
+            X[off[K]:off[K + 1]] = g.standard_normal((int(J[K]), ns))
+
+    nthr = threads or min(16, os.cpu_count() or 1)
+    if nthr <= 1 or N * ns < (1 << 22):
+        for K in range(len(J)):
+            fill(K)
+    else:
+        with cf.ThreadPoolExecutor(nthr) as ex:
+            list(ex.map(fill, range(len(J))))
     return X
 
 
