@@ -200,6 +200,12 @@ int chefsi_loss_backward(chefsi_plan plan, const double* d_H, int m, double a, d
                          int64_t ldx, int ns, double* d_Hbar, double* d_Xbar, int64_t ldxb,
                          double* h_loss, void* ws, size_t ws_bytes, void* stream);
 
+/* Workspace bytes of chefsi_loss_backward (op = CHEFSI_OP_LOSS_BACKWARD) or
+ * chefsi_filter_backward (op = CHEFSI_OP_FILTER_BACKWARD) for degree m, ns
+ * columns, `passes` Cholesky-QR passes and checkpoint stride ckpt_stride. */
+int chefsi_backward_workspace_bytes(chefsi_plan plan, int op, int m, int ns, int passes,
+                                    int ckpt_stride, size_t* bytes);
+
 /* Adjoint of chefsi_filter alone (FP64): given Ybar = dL/dY for Y = p_m(H)X,
  * accumulates dL/dH onto d_Hbar (block-list layout, added to) and writes
  * d_Xbar = dL/dX.  Checkpoints every ckpt_stride steps (1..m). Asynchronous. */

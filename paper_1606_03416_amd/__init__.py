@@ -13,7 +13,7 @@ this package loads the library and fails loudly if it is missing.
     plan.sweep(H, X, m, v0=v0, ritz=ritz, ...)         # steps 1-5
 """
 from ._binding import (  # noqa: F401
-    ChefsiError, Plan, orthonormalize, library_path, lib,
+    ChefsiError, Plan, orthonormalize, library_path, lib, ChefsiLoss, ChebFilter,
     F64, F32, BF16, OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP,
     OP_FILTER_BACKWARD, OP_LOSS_BACKWARD, ERR_NOT_PD, ERR_ARG, ERR_WORKSPACE, ERR_EIG,
 )

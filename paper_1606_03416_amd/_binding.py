@@ -64,6 +64,7 @@ _sig("chefsi_sweep", _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _i, _vp, _i64, _i, 
      ctypes.POINTER(Stats), _vp, _sz, _vp)
 _sig("chefsi_loss_backward", _i, _vp, _vp, _i, _d, _d, _d, _i, _i, _i, _vp, _i64, _i, _vp, _vp, _i64,
      _dp, _vp, _sz, _vp)
+_sig("chefsi_backward_workspace_bytes", _i, _vp, _i, _i, _i, _i, _i, ctypes.POINTER(_sz))
 _sig("chefsi_filter_backward", _i, _vp, _vp, _i, _d, _d, _d, _i, _vp, _i64, _vp, _i64, _i, _vp, _vp,
      _i64, _vp, _sz, _vp)
 
@@ -133,6 +134,11 @@ class Plan:
     def workspace_bytes(self, op: int, ns: int, dtype: int = F64, passes: int = 2, lanczos_steps: int = 20) -> int:
         out = _sz(0)
         _check(lib.chefsi_workspace_bytes(self._h, op, ns, dtype, passes, lanczos_steps, ctypes.byref(out)))
+        return int(out.value)
+
+    def backward_workspace_bytes(self, op: int, m: int, ns: int, passes: int = 2, ckpt_stride: int = 4) -> int:
+        out = _sz(0)
+        _check(lib.chefsi_backward_workspace_bytes(self._h, op, m, ns, passes, ckpt_stride, ctypes.byref(out)))
         return int(out.value)
 
     def _check_H(self, H: torch.Tensor):
@@ -220,7 +226,7 @@ class Plan:
         dev = X.device
         Hbar = torch.empty_like(H)
         Xbar = torch.empty((self.N, ns), dtype=torch.float64, device=dev)
-        ws = _workspace(self.workspace_bytes(OP_LOSS_BACKWARD, ns, F64, passes), dev)
+        ws = _workspace(self.backward_workspace_bytes(OP_LOSS_BACKWARD, m, ns, passes, ckpt_stride), dev)
         loss = ctypes.c_double(0.0)
         _check(lib.chefsi_loss_backward(self._h, _p(H), m, a, b, a0, passes, k, ckpt_stride, _p(X), ldx,
                                         ns, _p(Hbar), _p(Xbar), Xbar.stride(0), ctypes.byref(loss),
@@ -237,11 +243,47 @@ class Plan:
         if Hbar is None:
             Hbar = torch.zeros_like(H)
         Xbar = torch.empty((self.N, ns), dtype=torch.float64, device=dev)
-        ws = _workspace(self.workspace_bytes(OP_FILTER_BACKWARD, ns, F64), dev)
+        ws = _workspace(self.backward_workspace_bytes(OP_FILTER_BACKWARD, m, ns, 2, ckpt_stride), dev)
         _check(lib.chefsi_filter_backward(self._h, _p(H), m, a, b, a0, ckpt_stride, _p(X), ldx, _p(Ybar),
                                           ldyb, ns, _p(Hbar), _p(Xbar), Xbar.stride(0), _p(ws), ws.numel(),
                                           _stream()))
         return Hbar, Xbar
+
+
+class ChefsiLoss(torch.autograd.Function):
+    """L = sum of the k lowest Ritz values after one filter + Cholesky-QR +
+    Rayleigh-Ritz pass, with the hand-written adjoint (chefsi_loss_backward)
+    as its backward.  Bounds are held constant."""
+
+    @staticmethod
+    def forward(ctx, H, X, plan, m, bounds, k, passes=2, ckpt_stride=4):
+        a, b, a0 = bounds
+        loss, Hbar, Xbar = plan.loss_backward(H, X, m, a, b, a0, k, passes, ckpt_stride)
+        ctx.save_for_backward(Hbar, Xbar)
+        return torch.tensor(loss, dtype=torch.float64, device=H.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        Hbar, Xbar = ctx.saved_tensors
+        return g * Hbar, g * Xbar, None, None, None, None, None, None
+
+
+class ChebFilter(torch.autograd.Function):
+    """Y = p_m(H) X (FP64) with the reverse three-term sweep as its backward
+    (chefsi_filter_backward, checkpoints every ckpt_stride steps)."""
+
+    @staticmethod
+    def forward(ctx, H, X, plan, m, a, b, a0, ckpt_stride=4):
+        ctx.plan, ctx.args = plan, (m, a, b, a0, ckpt_stride)
+        ctx.save_for_backward(H, X)
+        return plan.filter(H, X, m, a, b, a0)
+
+    @staticmethod
+    def backward(ctx, Ybar):
+        H, X = ctx.saved_tensors
+        m, a, b, a0, cs = ctx.args
+        Hbar, Xbar = ctx.plan.filter_backward(H, X, Ybar.contiguous(), m, a, b, a0, cs)
+        return Hbar, Xbar, None, None, None, None, None, None
 
 
 def orthonormalize(Y: torch.Tensor, passes: int = 2, want_U: bool = False):

@@ -194,7 +194,7 @@ int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout
   double* Us[2] = {o.U1, o.U2};
   for (int pass = 0; pass < passes; ++pass) {
     CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y, ldy, Y, ldy, 0.0, o.S, ns, true, o.split, o.split_elems, st));
-    CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, true, st));
+    CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
     CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
     CHEFSI_TRY(trsm_right_upper(Y, ldy, n, o.S, ns, ns, st));
     CHEFSI_TRY(launch_copy_f64(o.S, ns, Us[pass], ns, ns, ns, st));
@@ -215,7 +215,7 @@ int run_rr(Plan& p, const void* panel64, const double* Yh, int64_t ldy, int ns, 
   StepIO io{Yh, ldy, true, nullptr, 0, true, r.W, ns, true};
   CHEFSI_TRY(launch_step(p, panel64, CHEFSI_F64, r.coef, io, ns, st));
   CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, Yh, ldy, r.W, ns, 0.0, r.Hh, ns, false, r.split, r.split_elems, st));
-  CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, false, st));
+  CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 0, st));
   CHEFSI_TRY(launch_fill_int(r.info, 1, 0, st));
   CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.eig, r.eig_bytes, st));
   CHEFSI_TRY(launch_eigvec_fix(r.Hh, ns, ns, r.Q, ns, st));
@@ -279,6 +279,153 @@ size_t sweep_bytes(Plan& p, int ns, int dtype, int passes, int k) {
   carve_rr(cr, p, ns, false, r);
   size_t lz = lanczos_ws_bytes(p, k);
   return base + std::max(std::max(cf.used, co.used), std::max(cr.used, lz));
+}
+
+
+// ------------------------------------------------------------ adjoint
+struct BwdWs {
+  double* panel = nullptr;
+  double* panelT = nullptr;
+  double* coef = nullptr;
+  double* rcoef = nullptr;
+  double* bounds = nullptr;
+  double* cconst = nullptr;
+  double* F[2] = {nullptr, nullptr};
+  std::vector<double*> ckY, ckP, seg;
+  double* LA = nullptr;
+  double* LB = nullptr;
+  // loss path
+  double *P1 = nullptr, *P2 = nullptr, *W = nullptr, *YH = nullptr, *G = nullptr;
+  double *S = nullptr, *U0 = nullptr, *U1 = nullptr, *Mb = nullptr, *Lt = nullptr, *Hh = nullptr;
+  double *Q = nullptr, *QT = nullptr, *Hhb = nullptr, *split = nullptr;
+  size_t split_elems = 0;
+  double *theta = nullptr, *E = nullptr, *loss = nullptr;
+  int* status = nullptr;
+  void* eig = nullptr;
+  size_t eig_bytes = 0;
+};
+
+int carve_bwd(Carver& c, Plan& p, int m, int ns, int passes, int stride, bool loss_path, BwdWs& b) {
+  const int64_t mv = p.N * static_cast<int64_t>(ns);
+  const int64_t nn = static_cast<int64_t>(ns) * ns;
+  const int nseg = m > 0 ? static_cast<int>(ceil_div(m, stride)) : 0;
+  b.panel = c.take<double>(p.panel_elems);
+  b.panelT = c.take<double>(p.panel_elems);
+  b.coef = c.take<double>(3 * static_cast<int64_t>(std::max(m, 1)));
+  b.rcoef = c.take<double>(3 * static_cast<int64_t>(std::max(m, 1)));
+  b.bounds = c.take<double>(4);
+  b.cconst = c.take<double>(8);
+  b.F[0] = c.take<double>(mv);
+  b.F[1] = c.take<double>(mv);
+  b.ckY.assign(nseg, nullptr);
+  b.ckP.assign(nseg, nullptr);
+  for (int i = 1; i < nseg; ++i) {
+    b.ckY[i] = c.take<double>(mv);
+    b.ckP[i] = c.take<double>(mv);
+  }
+  b.seg.assign(std::max(stride, 1), nullptr);
+  for (int t = 1; t < stride && t < m; ++t) b.seg[t] = c.take<double>(mv);
+  b.LA = c.take<double>(mv);
+  b.LB = c.take<double>(mv);
+  b.status = c.take<int>(8);
+  if (!loss_path) return CHEFSI_OK;
+  b.P1 = c.take<double>(mv);
+  b.P2 = passes == 2 ? c.take<double>(mv) : nullptr;
+  b.W = c.take<double>(mv);
+  b.YH = c.take<double>(mv);
+  b.G = c.take<double>(mv);
+  b.S = c.take<double>(nn);
+  b.U0 = c.take<double>(nn);
+  b.U1 = c.take<double>(nn);
+  b.Mb = c.take<double>(nn);
+  b.Lt = c.take<double>(nn);
+  b.Hh = c.take<double>(nn);
+  b.Q = c.take<double>(nn + ns);
+  b.QT = c.take<double>(nn);
+  b.Hhb = c.take<double>(nn);
+  b.split_elems = gemm_tn_split_ws_elems(ns, ns, p.N);
+  b.split = b.split_elems ? c.take<double>(static_cast<int64_t>(b.split_elems)) : nullptr;
+  b.theta = c.take<double>(ns);
+  b.E = c.take<double>(ns);
+  b.loss = c.take<double>(4);
+  int rc = eig_workspace_bytes(p, ns, &b.eig_bytes);
+  b.eig = b.eig_bytes ? c.take<char>(static_cast<int64_t>(b.eig_bytes)) : nullptr;
+  return rc;
+}
+
+// Forward recurrence from X, keeping (Y_{i*stride - 1}, Y_{i*stride}) for each
+// segment start i >= 1.  Runs `steps` steps; *Ylast / *ldlast get Y_steps.
+int forward_checkpointed(const Plan& p, const double* panel, const double* coef, int steps, int stride,
+                         const double* X, int64_t ldx, int ns, BwdWs& b, const double** Ylast,
+                         int64_t* ldlast, hipStream_t st) {
+  const double* Yk = X;
+  int64_t ldk = ldx;
+  const double* Ykm1 = nullptr;
+  int64_t ldkm1 = 0;
+  for (int k = 0; k < steps; ++k) {
+    double* out = b.F[(k + 1) % 2];
+    StepIO io{Yk, ldk, true, Ykm1, ldkm1, true, out, ns, true};
+    CHEFSI_TRY(launch_step(p, panel, CHEFSI_F64, coef + 3 * k, io, ns, st));
+    Ykm1 = Yk;
+    ldkm1 = ldk;
+    Yk = out;
+    ldk = ns;
+    if ((k + 1) % stride == 0) {
+      const int i = (k + 1) / stride;
+      if (i < static_cast<int>(b.ckY.size())) {
+        CHEFSI_TRY(launch_copy_f64(Yk, ldk, b.ckY[i], ns, p.N, ns, st));
+        CHEFSI_TRY(launch_copy_f64(Ykm1, ldkm1, b.ckP[i], ns, p.N, ns, st));
+      }
+    }
+  }
+  *Ylast = Yk;
+  *ldlast = ldk;
+  return CHEFSI_OK;
+}
+
+// Reverse three-term sweep from Lambda_m (already in b.LA):
+//   Hbar += sum_j alpha_j Lambda_{j+1} Y_j^T (stored blocks),
+//   Lambda_j = alpha_j (H^T - cI) Lambda_{j+1} - beta_{j+1} Lambda_{j+2},
+// recomputing Y_j segment by segment from the checkpoints; Xbar = Lambda_0.
+int reverse_sweep(const Plan& p, int m, int stride, const double* X, int64_t ldx, int ns, BwdWs& b,
+                  double* Hbar, double* Xbar, int64_t ldxb, hipStream_t st) {
+  const int nseg = static_cast<int>(ceil_div(m, stride));
+  double* lam1 = b.LA;       // Lambda_{j+1}
+  double* lam2 = nullptr;    // Lambda_{j+2}
+  std::vector<const double*> Yseg(std::max(stride, 1));
+  std::vector<int64_t> ldseg(std::max(stride, 1));
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int j0 = sg * stride;
+    const int j1 = std::min(j0 + stride, m);
+    Yseg[0] = (sg == 0) ? X : b.ckY[sg];
+    ldseg[0] = (sg == 0) ? ldx : ns;
+    const double* Yprev0 = (sg == 0) ? nullptr : b.ckP[sg];
+    for (int t = 1; t < j1 - j0; ++t) {
+      const int k = j0 + t - 1;
+      const double* prev = (t == 1) ? Yprev0 : Yseg[t - 2];
+      const int64_t ldp = (t == 1) ? ns : ldseg[t - 2];
+      StepIO io{Yseg[t - 1], ldseg[t - 1], true, prev, ldp, true, b.seg[t], ns, true};
+      CHEFSI_TRY(launch_step(p, b.panel, CHEFSI_F64, b.coef + 3 * k, io, ns, st));
+      Yseg[t] = b.seg[t];
+      ldseg[t] = ns;
+    }
+    for (int j = j1 - 1; j >= j0; --j) {
+      CHEFSI_TRY(sddmm_accumulate(p, lam1, ns, Yseg[j - j0], ldseg[j - j0], ns, 1.0, b.coef + 3 * j, Hbar, st));
+      double* out = lam2 ? lam2 : (lam1 == b.LA ? b.LB : b.LA);
+      StepIO io{lam1, ns, true, lam2, ns, true, out, ns, true};
+      CHEFSI_TRY(launch_step(p, b.panelT, CHEFSI_F64, b.rcoef + 3 * j, io, ns, st));
+      lam2 = lam1;
+      lam1 = out;
+    }
+  }
+  return launch_copy_f64(lam1, ns, Xbar, ldxb, p.N, ns, st);
+}
+
+int validate_bwd_common(Plan& p, int m, double a, double bb, double a0, int ns, int ckpt_stride) {
+  if (m < 0 || m > kMaxDegree) return fail(CHEFSI_ERR_ARG, "filter degree must be in [0, 100000]");
+  if (ns < 1 || ns > p.N) return fail(CHEFSI_ERR_ARG, "ns must be in [1, N]");
+  if (m > 0 && (ckpt_stride < 1 || ckpt_stride > m)) return fail(CHEFSI_ERR_ARG, "ckpt_stride must be in [1, m]");
+  return validate_bounds(a, bb, a0);
 }
 
 }  // namespace
@@ -725,16 +872,159 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
   });
 }
 
-int chefsi_loss_backward(chefsi_plan, const double*, int, double, double, double, int, int, int,
-                         const double*, int64_t, int, double*, double*, int64_t, double*, void*, size_t,
-                         void*) {
-  return fail(CHEFSI_ERR_UNSUPPORTED, "loss_backward not built yet");
+int chefsi_backward_workspace_bytes(chefsi_plan plan, int op, int m, int ns, int passes, int ckpt_stride,
+                                    size_t* bytes) {
+  return guarded([&]() -> int {
+    if (plan == nullptr || bytes == nullptr) return fail(CHEFSI_ERR_ARG, "plan/bytes is NULL");
+    if (op != CHEFSI_OP_LOSS_BACKWARD && op != CHEFSI_OP_FILTER_BACKWARD) return fail(CHEFSI_ERR_ARG, "bad op");
+    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    Plan& p = *P(plan);
+    if (m < 0 || ns < 1) return fail(CHEFSI_ERR_ARG, "need m >= 0 and ns >= 1");
+    const int stride = m > 0 ? std::max(1, std::min(ckpt_stride, m)) : 1;
+    Carver c(nullptr, 0);
+    BwdWs b;
+    CHEFSI_TRY(carve_bwd(c, p, m, ns, passes, stride, op == CHEFSI_OP_LOSS_BACKWARD, b));
+    *bytes = c.used;
+    return CHEFSI_OK;
+  });
 }
 
-int chefsi_filter_backward(chefsi_plan, const double*, int, double, double, double, int, const double*,
-                           int64_t, const double*, int64_t, int, double*, double*, int64_t, void*, size_t,
-                           void*) {
-  return fail(CHEFSI_ERR_UNSUPPORTED, "filter_backward not built yet");
+int chefsi_loss_backward(chefsi_plan plan, const double* d_H, int m, double a, double b, double a0, int passes,
+                         int k, int ckpt_stride, const double* d_X, int64_t ldx, int ns, double* d_Hbar,
+                         double* d_Xbar, int64_t ldxb, double* h_loss, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (d_H == nullptr || d_Hbar == nullptr) return fail(CHEFSI_ERR_ARG, "H or Hbar is NULL");
+    CHEFSI_TRY(validate_bwd_common(p, m, a, b, a0, ns, ckpt_stride));
+    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    if (k < 1 || k > ns) return fail(CHEFSI_ERR_ARG, "k must be in [1, ns]");
+    CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
+    CHEFSI_TRY(validate_mv("Xbar", d_Xbar, ldxb, ns));
+    if (overlaps(d_X, mv_bytes(p.N, ldx, ns, 8), d_Xbar, mv_bytes(p.N, ldxb, ns, 8)))
+      return fail(CHEFSI_ERR_ARG, "X and Xbar overlap");
+    const int stride = m > 0 ? ckpt_stride : 1;
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_backward_workspace_bytes(plan, CHEFSI_OP_LOSS_BACKWARD, m, ns, passes, stride, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    BwdWs w;
+    CHEFSI_TRY(carve_bwd(c, p, m, ns, passes, stride, true, w));
+    const int64_t N = p.N;
+    // ---- forward: filter (checkpointed), Cholesky-QR (per-pass factors kept), Rayleigh-Ritz
+    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, w.panel, st));
+    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, true, w.panelT, st));
+    CHEFSI_TRY(launch_set_bounds(a, b, a0, w.bounds, st));
+    CHEFSI_TRY(launch_cheb_coef(w.bounds, m, w.coef, st));
+    if (m > 0) CHEFSI_TRY(launch_rev_coef(w.coef, m, w.rcoef, st));
+    CHEFSI_TRY(launch_fill_int(w.status, 2, 0, st));
+    const double* Ym = nullptr;
+    int64_t ldm = 0;
+    CHEFSI_TRY(forward_checkpointed(p, w.panel, w.coef, m, stride, d_X, ldx, ns, w, &Ym, &ldm, st));
+    double* Qp[2] = {w.P1, w.P2};
+    double* Up[2] = {w.U0, w.U1};
+    CHEFSI_TRY(launch_copy_f64(Ym, ldm, w.P1, ns, N, ns, st));
+    for (int pass = 0; pass < passes; ++pass) {
+      if (pass == 1) CHEFSI_TRY(launch_copy_f64(w.P1, ns, w.P2, ns, N, ns, st));
+      double* Y = Qp[pass];
+      CHEFSI_TRY(gemm_tn(ns, ns, N, 1.0, Y, ns, Y, ns, 0.0, w.S, ns, true, w.split, w.split_elems, st));
+      CHEFSI_TRY(launch_symmetrize(w.S, ns, ns, 1, st));
+      CHEFSI_TRY(cholesky_upper(w.S, ns, ns, w.status, st));
+      CHEFSI_TRY(trsm_right_upper(Y, ns, N, w.S, ns, ns, st));
+      CHEFSI_TRY(launch_copy_f64(w.S, ns, Up[pass], ns, ns, ns, st));
+    }
+    double* Yh = Qp[passes - 1];
+    CHEFSI_TRY(launch_const_coef3(1.0, 0.0, 0.0, w.cconst, st));        // plain H x
+    CHEFSI_TRY(launch_const_coef3(1.0, -1.0, 0.0, w.cconst + 4, st));   // H x + prev
+    {
+      StepIO io{Yh, ns, true, nullptr, 0, true, w.W, ns, true};
+      CHEFSI_TRY(launch_step(p, w.panel, CHEFSI_F64, w.cconst, io, ns, st));
+    }
+    CHEFSI_TRY(gemm_tn(ns, ns, N, 1.0, Yh, ns, w.W, ns, 0.0, w.Hh, ns, false, w.split, w.split_elems, st));
+    CHEFSI_TRY(launch_symmetrize(w.Hh, ns, ns, 0, st));
+    CHEFSI_TRY(eig_sym(p, w.Hh, ns, ns, w.theta, w.E, w.status + 1, w.eig, w.eig_bytes, st));
+    CHEFSI_TRY(launch_eigvec_fix(w.Hh, ns, ns, w.Q, ns, st));
+    CHEFSI_TRY(launch_sum_first(w.theta, k, w.loss, st));
+    // ---- backward: Rayleigh-Ritz
+    CHEFSI_TRY(launch_transpose(w.Q, ns, w.QT, ns, ns, ns, st));
+    CHEFSI_TRY(gemm_tn(ns, ns, k, 1.0, w.QT, ns, w.QT, ns, 0.0, w.Hhb, ns, false, nullptr, 0, st));
+    CHEFSI_TRY(gemm_nn(N, ns, ns, 1.0, Yh, ns, w.Hhb, ns, 0.0, w.YH, ns, st));
+    {
+      StepIO io{w.YH, ns, true, nullptr, 0, true, w.G, ns, true};
+      CHEFSI_TRY(launch_step(p, w.panel, CHEFSI_F64, w.cconst, io, ns, st));
+      StepIO io2{w.YH, ns, true, w.G, ns, true, w.G, ns, true};
+      CHEFSI_TRY(launch_step(p, w.panelT, CHEFSI_F64, w.cconst + 4, io2, ns, st));
+    }
+    CHEFSI_TRY(launch_fill(d_Hbar, p.h_elems, 0.0, st));
+    CHEFSI_TRY(sddmm_accumulate(p, w.YH, ns, Yh, ns, ns, 1.0, nullptr, d_Hbar, st));
+    // ---- backward: Cholesky-QR passes in reverse
+    for (int pass = passes - 1; pass >= 0; --pass) {
+      double* Qv = Qp[pass];
+      CHEFSI_TRY(gemm_tn(ns, ns, N, -1.0, w.G, ns, Qv, ns, 0.0, w.Mb, ns, false, w.split, w.split_elems, st));
+      CHEFSI_TRY(launch_symmetrize(w.Mb, ns, ns, 2, st));
+      CHEFSI_TRY(gemm_nn(N, ns, ns, 1.0, Qv, ns, w.Mb, ns, 1.0, w.G, ns, st));
+      CHEFSI_TRY(launch_transpose(Up[pass], ns, w.Lt, ns, ns, ns, st));
+      CHEFSI_TRY(trsm_right_lower(w.G, ns, N, w.Lt, ns, ns, st));
+    }
+    // ---- backward: filter
+    if (m == 0) {
+      CHEFSI_TRY(launch_copy_f64(w.G, ns, d_Xbar, ldxb, N, ns, st));
+    } else {
+      CHEFSI_TRY(launch_copy_f64(w.G, ns, w.LA, ns, N, ns, st));
+      CHEFSI_TRY(reverse_sweep(p, m, stride, d_X, ldx, ns, w, d_Hbar, d_Xbar, ldxb, st));
+    }
+    double hl = 0.0;
+    int hs[2] = {0, 0};
+    CHEFSI_HIP(hipMemcpyAsync(&hl, w.loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    CHEFSI_HIP(hipMemcpyAsync(hs, w.status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CHEFSI_HIP(hipStreamSynchronize(st));
+    if (h_loss) *h_loss = hl;
+    if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+    if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");
+    return CHEFSI_OK;
+  });
+}
+
+int chefsi_filter_backward(chefsi_plan plan, const double* d_H, int m, double a, double b, double a0,
+                           int ckpt_stride, const double* d_X, int64_t ldx, const double* d_Ybar, int64_t ldyb,
+                           int ns, double* d_Hbar, double* d_Xbar, int64_t ldxb, void* ws, size_t ws_bytes,
+                           void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (d_H == nullptr || d_Hbar == nullptr) return fail(CHEFSI_ERR_ARG, "H or Hbar is NULL");
+    CHEFSI_TRY(validate_bwd_common(p, m, a, b, a0, ns, ckpt_stride));
+    CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
+    CHEFSI_TRY(validate_mv("Ybar", d_Ybar, ldyb, ns));
+    CHEFSI_TRY(validate_mv("Xbar", d_Xbar, ldxb, ns));
+    if (overlaps(d_Ybar, mv_bytes(p.N, ldyb, ns, 8), d_Xbar, mv_bytes(p.N, ldxb, ns, 8)) ||
+        overlaps(d_X, mv_bytes(p.N, ldx, ns, 8), d_Xbar, mv_bytes(p.N, ldxb, ns, 8)))
+      return fail(CHEFSI_ERR_ARG, "Xbar overlaps X or Ybar");
+    const int stride = m > 0 ? ckpt_stride : 1;
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_backward_workspace_bytes(plan, CHEFSI_OP_FILTER_BACKWARD, m, ns, 2, stride, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    BwdWs w;
+    CHEFSI_TRY(carve_bwd(c, p, m, ns, 2, stride, false, w));
+    if (m == 0) return launch_copy_f64(d_Ybar, ldyb, d_Xbar, ldxb, p.N, ns, st);
+    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, w.panel, st));
+    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, true, w.panelT, st));
+    CHEFSI_TRY(launch_set_bounds(a, b, a0, w.bounds, st));
+    CHEFSI_TRY(launch_cheb_coef(w.bounds, m, w.coef, st));
+    CHEFSI_TRY(launch_rev_coef(w.coef, m, w.rcoef, st));
+    const int nseg = static_cast<int>(ceil_div(m, stride));
+    const double* Ylast = nullptr;
+    int64_t ldl = 0;
+    CHEFSI_TRY(forward_checkpointed(p, w.panel, w.coef, (nseg - 1) * stride, stride, d_X, ldx, ns, w, &Ylast,
+                                    &ldl, st));
+    CHEFSI_TRY(launch_copy_f64(d_Ybar, ldyb, w.LA, ns, p.N, ns, st));
+    return reverse_sweep(p, m, stride, d_X, ldx, ns, w, d_Hbar, d_Xbar, ldxb, st);
+  });
 }
 
 }  // extern "C"

@@ -98,6 +98,7 @@ struct Carver {
 int launch_set_bounds(double a, double b, double a0, double* d_bounds, hipStream_t st);
 int launch_cheb_coef(const double* d_bounds, int m, double* d_coef, hipStream_t st);
 int launch_const_coef(double alpha, double c, double* d_coef, hipStream_t st);
+int launch_const_coef3(double alpha, double beta, double c, double* d_coef, hipStream_t st);
 
 // Repack H (block-list, fp64) into per-element transposed panels of type dtype.
 // transpose_h = true packs H^T (uses the opposite slot of each neighbour).
@@ -136,10 +137,21 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
 int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st);
 size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k);
-int launch_symmetrize(double* A, int64_t lda, int n, bool mirror_upper, hipStream_t st);
+// mode 0: (A + A^T)/2; 1: upper -> lower; 2: lower -> upper.
+int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st);
 int cholesky_upper(double* S, int64_t lds, int n, int* d_status, hipStream_t st);
 int trsm_right_upper(double* Y, int64_t ldy, int64_t nrows, const double* U, int64_t ldu, int n,
                      hipStream_t st);
+// Solve X L = Y in place (L lower triangular, n x n row-major).
+int trsm_right_lower(double* Y, int64_t ldy, int64_t nrows, const double* L, int64_t ldl, int n,
+                     hipStream_t st);
+// Hbar_{K;s} += alpha * (*d_alpha if non-null) * A[K rows] B[K'_s rows]^T for every stored block.
+int sddmm_accumulate(const Plan& p, const double* A, int64_t lda, const double* B, int64_t ldb, int ns,
+                     double alpha, const double* d_alpha, double* d_Hbar, hipStream_t st);
+// rcoef[3j..] = (alpha_j, beta_{j+1} (0 for j = m-1), c): coefficients of the reverse sweep.
+int launch_rev_coef(const double* d_coef, int m, double* d_rcoef, hipStream_t st);
+// out[0] = sum_{i<k} v[i]
+int launch_sum_first(const double* d_v, int k, double* d_out, hipStream_t st);
 int launch_fill(double* d, int64_t count, double v, hipStream_t st);
 int launch_fill_int(int* d, int64_t count, int v, hipStream_t st);
 int trmm_upper_upper(const double* A, const double* B, double* C, int n, hipStream_t st);

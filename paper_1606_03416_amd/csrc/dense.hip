@@ -35,74 +35,76 @@ struct GemmArgs {
   bool upper_only;
 };
 
-// C tile (128 x 128) = sum_k op(A)[i][k] B[k][j] over this split's k range.
-// A_KMAJOR: A stored k x m (TN form); otherwise m x k (NN form).
-template <bool A_KMAJOR>
-__global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
-  const int ti = blockIdx.y, tj = blockIdx.x, split = blockIdx.z;
-  if (g.upper_only && ti > tj) return;
-  __shared__ double sA[2][GK][GLD];
-  __shared__ double sB[2][GK][GLD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t i0 = static_cast<int64_t>(ti) * GT, j0 = static_cast<int64_t>(tj) * GT;
-  const int64_t kbeg = static_cast<int64_t>(split) * g.kper;
-  int64_t kend = kbeg + g.kper;
-  if (kend > g.k) kend = g.k;
-  const int nch = static_cast<int>(ceil_div(kend - kbeg, GK));
-
-  double ra[8], rb[8];
-  auto gload = [&](int c) {
-    const int64_t kc = kbeg + static_cast<int64_t>(c) * GK;
-    if constexpr (A_KMAJOR) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int row = (tid >> 7) + 2 * q, col = tid & 127;
-        const int64_t kk = kc + row, ii = i0 + col;
-        ra[q] = (kk < kend && ii < g.m) ? g.A[kk * g.lda + ii] : 0.0;
-      }
-    } else {
-      const int row = tid >> 1, half = tid & 1;   // 128 rows x 16 k
-      const int64_t ii = i0 + row;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t kk = kc + half * 8 + q;
-        ra[q] = (kk < kend && ii < g.m) ? g.A[ii * g.lda + kk] : 0.0;
-      }
-    }
+// Loads of one 128 x GK operand chunk into registers (8 values per thread),
+// branch-free: out-of-range elements read a clamped valid address and are
+// replaced by zero.
+//   KMAJOR:  X[k][idx] (row stride ld): thread reads idx = tid%128, k = tid/128 + 2q.
+//   !KMAJOR: X[idx][k] (row stride ld): thread reads idx = tid/2, k = (tid%2)*8 + q.
+template <bool KMAJOR>
+__device__ __forceinline__ void load_chunk(const double* X, int64_t ld, int64_t idx0, int64_t lim,
+                                           int64_t kc, int64_t kend, double (&r)[8]) {
+  const int tid = threadIdx.x;
+  if constexpr (KMAJOR) {
+    const int64_t idx = idx0 + (tid & 127);
+    const bool iv = idx < lim;
+    const int64_t ic = iv ? idx : lim - 1;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int row = (tid >> 7) + 2 * q, col = tid & 127;
-      const int64_t kk = kc + row, jj = j0 + col;
-      rb[q] = (kk < kend && jj < g.n) ? g.B[kk * g.ldb + jj] : 0.0;
+      const int64_t kk = kc + (tid >> 7) + 2 * q;
+      const bool v = iv && kk < kend;
+      const double x = X[(v ? kk : kend - 1) * ld + ic];
+      r[q] = v ? x : 0.0;
     }
-  };
-  auto sstore = [&](int buf) {
-    if constexpr (A_KMAJOR) {
+  } else {
+    const int64_t idx = idx0 + (tid >> 1);
+    const bool iv = idx < lim;
+    const double* row = X + (iv ? idx : lim - 1) * ld;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sA[buf][(tid >> 7) + 2 * q][tid & 127] = ra[q];
-    } else {
-      const int row = tid >> 1, half = tid & 1;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) sA[buf][half * 8 + q][row] = ra[q];
+    for (int q = 0; q < 8; ++q) {
+      const int64_t kk = kc + (tid & 1) * 8 + q;
+      const bool v = iv && kk < kend;
+      const double x = row[v ? kk : kend - 1];
+      r[q] = v ? x : 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sB[buf][(tid >> 7) + 2 * q][tid & 127] = rb[q];
-  };
-
-  d4 acc[8][2];
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    acc[r][0] = d4{0, 0, 0, 0};
-    acc[r][1] = d4{0, 0, 0, 0};
   }
+}
+
+template <bool KMAJOR>
+__device__ __forceinline__ void store_chunk(double (*S)[GLD], const double (&r)[8]) {
+  const int tid = threadIdx.x;
+  if constexpr (KMAJOR) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) S[(tid >> 7) + 2 * q][tid & 127] = r[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) S[(tid & 1) * 8 + q][tid >> 1] = r[q];
+  }
+}
+
+// acc += op(A)[i0.., k] op(B)[k, j0..] over k in [kbeg, kend) for a 128 x 128
+// tile; four waves each own 32 columns (8 x 2 MFMA 16x16 blocks).
+template <bool AK, bool BK>
+__device__ __forceinline__ void tile_mma(const double* A, int64_t lda, const double* B, int64_t ldb,
+                                         int64_t m, int64_t n, int64_t kbeg, int64_t kend, int64_t i0,
+                                         int64_t j0, double (*sA)[GK][GLD], double (*sB)[GK][GLD],
+                                         d4 (&acc)[8][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nch = kend > kbeg ? static_cast<int>(ceil_div(kend - kbeg, GK)) : 0;
+  double ra[8], rb[8];
   if (nch > 0) {
-    gload(0);
-    sstore(0);
+    load_chunk<AK>(A, lda, i0, m, kbeg, kend, ra);
+    load_chunk<BK>(B, ldb, j0, n, kbeg, kend, rb);
+    store_chunk<AK>(sA[0], ra);
+    store_chunk<BK>(sB[0], rb);
   }
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
-    if (c + 1 < nch) gload(c + 1);
+    if (c + 1 < nch) {
+      const int64_t kc = kbeg + static_cast<int64_t>(c + 1) * GK;
+      load_chunk<AK>(A, lda, i0, m, kc, kend, ra);
+      load_chunk<BK>(B, ldb, j0, n, kc, kend, rb);
+    }
 #pragma unroll
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int krow = kk * 4 + (lane >> 4);
@@ -117,10 +119,34 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
         acc[r][1] = mma64(av[r], bv[1], acc[r][1]);
       }
     }
-    if (c + 1 < nch) sstore(buf ^ 1);
+    if (c + 1 < nch) {
+      store_chunk<AK>(sA[buf ^ 1], ra);
+      store_chunk<BK>(sB[buf ^ 1], rb);
+    }
     __syncthreads();
   }
+}
 
+// C tile (128 x 128) = sum_k op(A)[i][k] B[k][j] over this split's k range.
+// A_KMAJOR: A stored k x m (TN form); otherwise m x k (NN form).  B is k x n.
+template <bool A_KMAJOR>
+__global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
+  const int ti = blockIdx.y, tj = blockIdx.x, split = blockIdx.z;
+  if (g.upper_only && ti > tj) return;
+  __shared__ double sA[2][GK][GLD];
+  __shared__ double sB[2][GK][GLD];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = static_cast<int64_t>(ti) * GT, j0 = static_cast<int64_t>(tj) * GT;
+  const int64_t kbeg = static_cast<int64_t>(split) * g.kper;
+  int64_t kend = kbeg + g.kper;
+  if (kend > g.k) kend = g.k;
+  d4 acc[8][2];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    acc[r][0] = d4{0, 0, 0, 0};
+    acc[r][1] = d4{0, 0, 0, 0};
+  }
+  tile_mma<A_KMAJOR, true>(g.A, g.lda, g.B, g.ldb, g.m, g.n, kbeg, kend, i0, j0, sA, sB, acc);
 #pragma unroll
   for (int r = 0; r < 8; ++r)
 #pragma unroll
@@ -142,6 +168,56 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
     }
 }
 
+// Gradient onto the stored blocks (block-sparse "SDDMM"):
+//   Hbar_{K;s} += alpha * A[rows of K] * B[rows of K'_s]^T,
+// reduction over the ns columns; one work-group per stored block.
+struct SddmmArgs {
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* Hbar;
+  const int64_t* hoff;
+  const int32_t* nbr;
+  const int32_t* J;
+  const int64_t* rowoff;
+  int S;
+  int ns;
+  double alpha;
+  const double* alpha_dev;   // optional device factor (e.g. a recurrence coefficient)
+};
+
+__global__ __launch_bounds__(GNT) void sddmm_kernel(SddmmArgs g) {
+  __shared__ double sA[2][GK][GLD];
+  __shared__ double sB[2][GK][GLD];
+  const int blk = blockIdx.x;
+  const int K = blk / g.S;
+  const int Kp = g.nbr[blk];
+  const int m = g.J[K], n = g.J[Kp];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  d4 acc[8][2];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    acc[r][0] = d4{0, 0, 0, 0};
+    acc[r][1] = d4{0, 0, 0, 0};
+  }
+  tile_mma<false, false>(g.A + g.rowoff[K] * g.lda, g.lda, g.B + g.rowoff[Kp] * g.ldb, g.ldb, m, n, 0,
+                         g.ns, 0, 0, sA, sB, acc);
+  double* C = g.Hbar + g.hoff[blk];
+  const double alpha = g.alpha * (g.alpha_dev ? *g.alpha_dev : 1.0);
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int j = wave * 32 + c2 * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = r * 16 + 4 * q + (lane >> 4);
+        if (i < m && j < n) C[i * n + j] += alpha * acc[r][c2][q];
+      }
+    }
+}
+
 __global__ void split_reduce_kernel(const double* part, int splits, int64_t m, int64_t n,
                                     double alpha, double beta, double* C, int64_t ldc,
                                     bool upper_only) {
@@ -158,14 +234,18 @@ __global__ void split_reduce_kernel(const double* part, int splits, int64_t m, i
   }
 }
 
-__global__ void symmetrize_kernel(double* A, int64_t lda, int n, bool mirror_upper) {
+// mode 0: (A + A^T)/2; 1: copy the upper triangle to the lower; 2: copy the
+// lower triangle to the upper (tril(A) + tril(A,-1)^T).
+__global__ void symmetrize_kernel(double* A, int64_t lda, int n, int mode) {
   const int64_t total = static_cast<int64_t>(n) * n;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
     const int64_t i = t / n, j = t - (t / n) * n;
     if (i >= j) continue;
-    if (mirror_upper) {
+    if (mode == 1) {
       A[j * lda + i] = A[i * lda + j];
+    } else if (mode == 2) {
+      A[i * lda + j] = A[j * lda + i];
     } else {
       const double v = 0.5 * (A[i * lda + j] + A[j * lda + i]);
       A[i * lda + j] = v;
@@ -277,6 +357,35 @@ __global__ __launch_bounds__(64) void trsm_diag_kernel(double* Y, int64_t ldy, i
     }
     if (q < c) a0 -= Yb[tid][q] * Ub[q][c];
     Yb[tid][c] = (a0 + a1) / Ub[c][c];
+  }
+  __syncthreads();
+  for (int r = 0; r < 64; ++r) {
+    const int64_t row = r0 + r;
+    if (tid < w && row < nrows) Y[row * ldy + b0 + tid] = Yb[r][tid];
+  }
+}
+
+// Y[:, b0:b0+w] <- Y[:, b0:b0+w] L_bb^{-1} with L lower triangular (backward
+// substitution over the block's columns), 64 rows per work-group.
+__global__ __launch_bounds__(64) void trsm_diag_lower_kernel(double* Y, int64_t ldy, int64_t nrows,
+                                                             const double* L, int64_t ldl, int b0, int w) {
+  __shared__ double Lb[CB][CB + 1];
+  __shared__ double Yb[CB][CB + 1];
+  const int tid = threadIdx.x;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 64;
+  for (int t = tid; t < w * w; t += 64) {
+    const int r = t / w, c = t - (t / w) * w;
+    Lb[r][c] = L[static_cast<int64_t>(b0 + r) * ldl + b0 + c];
+  }
+  for (int r = 0; r < 64; ++r) {
+    const int64_t row = r0 + r;
+    if (tid < w) Yb[r][tid] = (row < nrows) ? Y[row * ldy + b0 + tid] : 0.0;
+  }
+  __syncthreads();
+  for (int c = w - 1; c >= 0; --c) {
+    double acc = Yb[tid][c];
+    for (int q = c + 1; q < w; ++q) acc -= Yb[tid][q] * Lb[q][c];
+    Yb[tid][c] = acc / Lb[c][c];
   }
   __syncthreads();
   for (int r = 0; r < 64; ++r) {
@@ -408,8 +517,8 @@ int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   return CHEFSI_OK;
 }
 
-int launch_symmetrize(double* A, int64_t lda, int n, bool mirror_upper, hipStream_t st) {
-  symmetrize_kernel<<<grid1(static_cast<int64_t>(n) * n), 256, 0, st>>>(A, lda, n, mirror_upper);
+int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st) {
+  symmetrize_kernel<<<grid1(static_cast<int64_t>(n) * n), 256, 0, st>>>(A, lda, n, mode);
   CHEFSI_LAUNCHED("symmetrize");
   return CHEFSI_OK;
 }
@@ -444,6 +553,33 @@ int trsm_right_upper(double* Y, int64_t ldy, int64_t nrows, const double* U, int
     trsm_diag_kernel<<<static_cast<unsigned>(ceil_div(nrows, 64)), 64, 0, st>>>(Y, ldy, nrows, U, ldu, b0, w);
     CHEFSI_LAUNCHED("trsm_diag");
   }
+  return CHEFSI_OK;
+}
+
+int trsm_right_lower(double* Y, int64_t ldy, int64_t nrows, const double* L, int64_t ldl, int n,
+                     hipStream_t st) {
+  if (nrows <= 0) return CHEFSI_OK;
+  const int nblk = static_cast<int>(ceil_div(n, CB));
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int b0 = bi * CB;
+    const int w = (n - b0) < CB ? (n - b0) : CB;
+    const int rest = n - b0 - w;
+    if (rest > 0) {
+      CHEFSI_TRY(gemm_nn(nrows, w, rest, -1.0, Y + b0 + w, ldy, L + static_cast<int64_t>(b0 + w) * ldl + b0,
+                         ldl, 1.0, Y + b0, ldy, st));
+    }
+    trsm_diag_lower_kernel<<<static_cast<unsigned>(ceil_div(nrows, 64)), 64, 0, st>>>(Y, ldy, nrows, L, ldl, b0, w);
+    CHEFSI_LAUNCHED("trsm_diag_lower");
+  }
+  return CHEFSI_OK;
+}
+
+int sddmm_accumulate(const Plan& p, const double* A, int64_t lda, const double* B, int64_t ldb, int ns,
+                     double alpha, const double* d_alpha, double* d_Hbar, hipStream_t st) {
+  if (ns <= 0) return CHEFSI_OK;
+  SddmmArgs g{A, lda, B, ldb, d_Hbar, p.d_hoff, p.d_nbr, p.d_J, p.d_rowoff, p.stencil, ns, alpha, d_alpha};
+  sddmm_kernel<<<static_cast<unsigned>(p.M * p.stencil), GNT, 0, st>>>(g);
+  CHEFSI_LAUNCHED("sddmm");
   return CHEFSI_OK;
 }
 

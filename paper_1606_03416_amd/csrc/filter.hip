@@ -306,10 +306,26 @@ __global__ void cheb_coef_kernel(const double* bounds, int m, double* coef) {
   }
 }
 
-__global__ void const_coef_kernel(double alpha, double c, double* coef) {
+__global__ void rev_coef_kernel(const double* coef, int m, double* rcoef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int j = 0; j < m; ++j) {
+    rcoef[3 * j + 0] = coef[3 * j + 0];
+    rcoef[3 * j + 1] = (j + 1 < m) ? coef[3 * (j + 1) + 1] : 0.0;
+    rcoef[3 * j + 2] = coef[3 * j + 2];
+  }
+}
+
+__global__ void sum_first_kernel(const double* v, int k, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < k; ++i) s += v[i];
+  out[0] = s;
+}
+
+__global__ void const_coef_kernel(double alpha, double beta, double c, double* coef) {
   if (threadIdx.x == 0) {
     coef[0] = alpha;
-    coef[1] = 0.0;
+    coef[1] = beta;
     coef[2] = c;
   }
 }
@@ -429,8 +445,26 @@ int launch_cheb_coef(const double* d_bounds, int m, double* d_coef, hipStream_t 
   return CHEFSI_OK;
 }
 
+int launch_rev_coef(const double* d_coef, int m, double* d_rcoef, hipStream_t st) {
+  rev_coef_kernel<<<1, 64, 0, st>>>(d_coef, m, d_rcoef);
+  CHEFSI_LAUNCHED("rev_coef");
+  return CHEFSI_OK;
+}
+
+int launch_sum_first(const double* d_v, int k, double* d_out, hipStream_t st) {
+  sum_first_kernel<<<1, 64, 0, st>>>(d_v, k, d_out);
+  CHEFSI_LAUNCHED("sum_first");
+  return CHEFSI_OK;
+}
+
 int launch_const_coef(double alpha, double c, double* d_coef, hipStream_t st) {
-  const_coef_kernel<<<1, 64, 0, st>>>(alpha, c, d_coef);
+  const_coef_kernel<<<1, 64, 0, st>>>(alpha, 0.0, c, d_coef);
+  CHEFSI_LAUNCHED("const_coef");
+  return CHEFSI_OK;
+}
+
+int launch_const_coef3(double alpha, double beta, double c, double* d_coef, hipStream_t st) {
+  const_coef_kernel<<<1, 64, 0, st>>>(alpha, beta, c, d_coef);
   CHEFSI_LAUNCHED("const_coef");
   return CHEFSI_OK;
 }
