@@ -81,15 +81,26 @@ __device__ __forceinline__ void store_chunk(double (*S)[GLD], const double (&r)[
   }
 }
 
+// FP64 MFMA 4x4x4 (4 blocks) with the A operand replicated over the blocks:
+// lane l supplies A[l%4][l/16] and B[l/16][l%16]; the result element of lane
+// l is D[l/16][l%16], a 4 x 16 x 4 product per instruction.  On gfx950 this
+// shape sustains a much higher FP64 rate than the 16x16x4 shape.
+__device__ __forceinline__ double mma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
 // acc += op(A)[i0.., k] op(B)[k, j0..] over k in [kbeg, kend) for a 128 x 128
-// tile; four waves each own 32 columns (8 x 2 MFMA 16x16 blocks).
+// tile; wave w owns rows 32w..32w+31 (8 four-row fragments) and all 128
+// columns (8 sixteen-column fragments).
 template <bool AK, bool BK>
 __device__ __forceinline__ void tile_mma(const double* A, int64_t lda, const double* B, int64_t ldb,
                                          int64_t m, int64_t n, int64_t kbeg, int64_t kend, int64_t i0,
                                          int64_t j0, double (*sA)[GK][GLD], double (*sB)[GK][GLD],
-                                         d4 (&acc)[8][2]) {
+                                         double (&acc)[8][8]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nch = kend > kbeg ? static_cast<int>(ceil_div(kend - kbeg, GK)) : 0;
+  const int arow = wave * 32 + (lane & 3);
+  const int bcol = lane & 15;
   double ra[8], rb[8];
   if (nch > 0) {
     load_chunk<AK>(A, lda, i0, m, kbeg, kend, ra);
@@ -105,19 +116,18 @@ __device__ __forceinline__ void tile_mma(const double* A, int64_t lda, const dou
       load_chunk<AK>(A, lda, i0, m, kc, kend, ra);
       load_chunk<BK>(B, ldb, j0, n, kc, kend, rb);
     }
-#pragma unroll
+#pragma unroll 2
     for (int kk = 0; kk < GK / 4; ++kk) {
       const int krow = kk * 4 + (lane >> 4);
-      double av[8], bv[2];
+      double av[8], bv[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) av[r] = sA[buf][krow][r * 16 + (lane & 15)];
+      for (int p = 0; p < 8; ++p) av[p] = sA[buf][krow][arow + 4 * p];
 #pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) bv[c2] = sB[buf][krow][wave * 32 + c2 * 16 + (lane & 15)];
+      for (int q = 0; q < 8; ++q) bv[q] = sB[buf][krow][16 * q + bcol];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        acc[r][0] = mma64(av[r], bv[0], acc[r][0]);
-        acc[r][1] = mma64(av[r], bv[1], acc[r][1]);
-      }
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[p][q] = mma4(av[p], bv[q], acc[p][q]);
     }
     if (c + 1 < nch) {
       store_chunk<AK>(sA[buf ^ 1], ra);
@@ -130,7 +140,7 @@ __device__ __forceinline__ void tile_mma(const double* A, int64_t lda, const dou
 // C tile (128 x 128) = sum_k op(A)[i][k] B[k][j] over this split's k range.
 // A_KMAJOR: A stored k x m (TN form); otherwise m x k (NN form).  B is k x n.
 template <bool A_KMAJOR>
-__global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
+__global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
   const int ti = blockIdx.y, tj = blockIdx.x, split = blockIdx.z;
   if (g.upper_only && ti > tj) return;
   __shared__ double sA[2][GK][GLD];
@@ -140,32 +150,29 @@ __global__ __launch_bounds__(GNT) void gemm_kernel(GemmArgs g) {
   const int64_t kbeg = static_cast<int64_t>(split) * g.kper;
   int64_t kend = kbeg + g.kper;
   if (kend > g.k) kend = g.k;
-  d4 acc[8][2];
+  double acc[8][8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    acc[r][0] = d4{0, 0, 0, 0};
-    acc[r][1] = d4{0, 0, 0, 0};
-  }
+  for (int p = 0; p < 8; ++p)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
   tile_mma<A_KMAJOR, true>(g.A, g.lda, g.B, g.ldb, g.m, g.n, kbeg, kend, i0, j0, sA, sB, acc);
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int p = 0; p < 8; ++p) {
+    const int64_t i = i0 + wave * 32 + 4 * p + (lane >> 4);
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-      const int64_t j = j0 + wave * 32 + c2 * 16 + (lane & 15);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t i = i0 + r * 16 + 4 * q + (lane >> 4);   // FP64 MFMA output row
-        if (i < g.m && j < g.n) {
-          if (g.part != nullptr) {
-            g.part[(static_cast<int64_t>(split) * g.m + i) * g.n + j] = acc[r][c2][q];
-          } else {
-            double v = g.alpha * acc[r][c2][q];
-            if (g.beta != 0.0) v += g.beta * g.C[i * g.ldc + j];
-            g.C[i * g.ldc + j] = v;
-          }
+    for (int q = 0; q < 8; ++q) {
+      const int64_t j = j0 + 16 * q + (lane & 15);
+      if (i < g.m && j < g.n) {
+        if (g.part != nullptr) {
+          g.part[(static_cast<int64_t>(split) * g.m + i) * g.n + j] = acc[p][q];
+        } else {
+          double v = g.alpha * acc[p][q];
+          if (g.beta != 0.0) v += g.beta * g.C[i * g.ldc + j];
+          g.C[i * g.ldc + j] = v;
         }
       }
     }
+  }
 }
 
 // Gradient onto the stored blocks (block-sparse "SDDMM"):
@@ -187,7 +194,7 @@ struct SddmmArgs {
   const double* alpha_dev;   // optional device factor (e.g. a recurrence coefficient)
 };
 
-__global__ __launch_bounds__(GNT) void sddmm_kernel(SddmmArgs g) {
+__global__ __launch_bounds__(GNT, 2) void sddmm_kernel(SddmmArgs g) {
   __shared__ double sA[2][GK][GLD];
   __shared__ double sB[2][GK][GLD];
   const int blk = blockIdx.x;
@@ -195,27 +202,24 @@ __global__ __launch_bounds__(GNT) void sddmm_kernel(SddmmArgs g) {
   const int Kp = g.nbr[blk];
   const int m = g.J[K], n = g.J[Kp];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  d4 acc[8][2];
+  double acc[8][8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    acc[r][0] = d4{0, 0, 0, 0};
-    acc[r][1] = d4{0, 0, 0, 0};
-  }
+  for (int p = 0; p < 8; ++p)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
   tile_mma<false, false>(g.A + g.rowoff[K] * g.lda, g.lda, g.B + g.rowoff[Kp] * g.ldb, g.ldb, m, n, 0,
                          g.ns, 0, 0, sA, sB, acc);
   double* C = g.Hbar + g.hoff[blk];
   const double alpha = g.alpha * (g.alpha_dev ? *g.alpha_dev : 1.0);
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int p = 0; p < 8; ++p) {
+    const int i = wave * 32 + 4 * p + (lane >> 4);
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-      const int j = wave * 32 + c2 * 16 + (lane & 15);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = r * 16 + 4 * q + (lane >> 4);
-        if (i < m && j < n) C[i * n + j] += alpha * acc[r][c2][q];
-      }
+    for (int q = 0; q < 8; ++q) {
+      const int j = 16 * q + (lane & 15);
+      if (i < m && j < n) C[i * n + j] += alpha * acc[p][q];
     }
+  }
 }
 
 __global__ void split_reduce_kernel(const double* part, int splits, int64_t m, int64_t n,

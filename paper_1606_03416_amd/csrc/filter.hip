@@ -10,6 +10,8 @@
 // RB x 2 MFMA 16x16 accumulators (RB = ceil(J_K/16)).  The recurrence
 // Y_{k+1} = alpha_k (H Y_k - c Y_k) - beta_k Y_{k-1} is applied in the
 // epilogue, so a step reads Y_k, Y_{k-1} and writes Y_{k+1} once.
+#include <type_traits>
+
 #include "common.h"
 
 namespace chefsi {
@@ -76,34 +78,32 @@ __device__ __forceinline__ int xcd_linear(int b, int nwg) {
   return x * q + (x < r ? x : r) + i;
 }
 
-template <typename TC, typename TOUT, int RB, int EPI, int LDA>
-__device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* sA, TC* sB) {
-  using MF = Mfma<TC>;
-  using acc_t = typename MF::acc_t;
-  constexpr int JP = RB * 16;
-  constexpr int LDB = TN + MF::pad;
-  constexpr int AQ = (KC * JP) / NT;   // A elements per thread per chunk
-  constexpr int BQ = (KC * TN) / NT;   // B elements per thread per chunk
-  static_assert((KC * JP) % NT == 0, "A chunk must split evenly");
+// FP64 MFMA 4x4x4 (4 blocks) with the A operand replicated over the blocks:
+// lane l supplies A[l%4][l/16] and B[l/16][l%16] and receives D[l/16][l%16].
+// On gfx950 this shape sustains a much higher FP64 rate than 16x16x4.
+__device__ __forceinline__ double mma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int j0 = ct * TN;
-  const int ns = a.ns;
-  const TC* __restrict__ panel = static_cast<const TC*>(a.panel) + a.poff[K];
-  const int32_t* __restrict__ kmap = a.kmap + a.koff[K];
-  const TC* in = static_cast<const TC*>(a.in);
-  const int64_t ldi = a.ldi;
-  const int nch = a.kpad[K] / KC;
-  const int bcol = tid & (TN - 1);
-  const int brow0 = tid / TN;
-  const bool col_ok = (j0 + bcol) < ns;
-
+// Operand staging shared by both arithmetic paths: the k-major panel chunk
+// (KC x JP) and the gathered neighbour rows (KC x TN) of the input block.
+template <typename TC, int RB, int LDA>
+struct Stage {
+  static constexpr int JP = RB * 16;
+  static constexpr int LDB = TN + Mfma<TC>::pad;
+  static constexpr int AQ = (KC * JP) / NT;
+  static constexpr int BQ = (KC * TN) / NT;
   TC ra[AQ];
   TC rb[BQ];
+  const TC* panel;
+  const int32_t* kmap;
+  const TC* in;
+  int64_t ldi;
+  int j0, bcol, brow0;
+  bool col_ok;
 
-  auto gload = [&](int c) {
+  __device__ __forceinline__ void gload(int c) {
+    const int tid = threadIdx.x;
     const TC* pa = panel + static_cast<int64_t>(c) * (KC * JP);
 #pragma unroll
     for (int q = 0; q < AQ; ++q) ra[q] = pa[tid + NT * q];
@@ -113,10 +113,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* 
       const int g = kmap[c * KC + row];
       rb[q] = (g >= 0 && col_ok) ? in[static_cast<int64_t>(g) * ldi + j0 + bcol] : TC(0);
     }
-  };
-  auto sstore = [&](int buf) {
-    TC* A = sA + buf * (KC * LDA);
-    TC* B = sB + buf * (KC * LDB);
+  }
+  __device__ __forceinline__ void sstore(TC* A, TC* B) {
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < AQ; ++q) {
       const int e = tid + NT * q;
@@ -124,84 +123,138 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* 
     }
 #pragma unroll
     for (int q = 0; q < BQ; ++q) B[(brow0 + (NT / TN) * q) * LDB + bcol] = rb[q];
-  };
+  }
+};
 
-  acc_t acc[RB][2];
-#pragma unroll
-  for (int r = 0; r < RB; ++r)
-#pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = acc_t{0, 0, 0, 0};
+template <typename TC, typename TOUT, int RB, int EPI, int LDA>
+__device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* sA, TC* sB) {
+  using ST = Stage<TC, RB, LDA>;
+  constexpr int LDB = ST::LDB;
+  constexpr bool F64 = std::is_same<TC, double>::value;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int ns = a.ns;
+  ST st;
+  st.panel = static_cast<const TC*>(a.panel) + a.poff[K];
+  st.kmap = a.kmap + a.koff[K];
+  st.in = static_cast<const TC*>(a.in);
+  st.ldi = a.ldi;
+  st.j0 = ct * TN;
+  st.bcol = tid & (TN - 1);
+  st.brow0 = tid / TN;
+  st.col_ok = (st.j0 + st.bcol) < ns;
+  const int j0 = st.j0;
+  const int nch = a.kpad[K] / KC;
 
-  gload(0);
-  sstore(0);
+  // FP64: wave w owns rows 4*RB*w .. +4*RB (RB four-row fragments) and all 128
+  // columns (8 sixteen-column fragments), one accumulator value per fragment.
+  // FP32: wave w owns columns 32w .. 32w+31 and all rows, 16x16x4 fragments.
+  constexpr int NA = RB;
+  constexpr int NB = F64 ? 8 : 2;
+  using acc_t = typename std::conditional<F64, double, typename Mfma<float>::acc_t>::type;
+  acc_t acc[NA][NB];
+#pragma unroll
+  for (int r = 0; r < NA; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < NB; ++c2) acc[r][c2] = acc_t{};
+
+  st.gload(0);
+  st.sstore(sA, sB);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
-    if (c + 1 < nch) gload(c + 1);
+    if (c + 1 < nch) st.gload(c + 1);
     const TC* A = sA + buf * (KC * LDA);
     const TC* B = sB + buf * (KC * LDB);
 #pragma unroll
     for (int kk = 0; kk < KC / 4; ++kk) {
       const int krow = kk * 4 + (lane >> 4);
-      TC av[RB], bv[2];
+      TC av[NA], bv[NB];
+      if constexpr (F64) {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) av[r] = A[krow * LDA + r * 16 + (lane & 15)];
+        for (int r = 0; r < NA; ++r) av[r] = A[krow * LDA + wave * 4 * RB + 4 * r + (lane & 3)];
 #pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) bv[c2] = B[krow * LDB + wave * 32 + c2 * 16 + (lane & 15)];
+        for (int c2 = 0; c2 < NB; ++c2) bv[c2] = B[krow * LDB + 16 * c2 + (lane & 15)];
 #pragma unroll
-      for (int r = 0; r < RB; ++r)
+        for (int r = 0; r < NA; ++r)
 #pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = MF::mma(av[r], bv[c2], acc[r][c2]);
+          for (int c2 = 0; c2 < NB; ++c2) acc[r][c2] = mma4(av[r], bv[c2], acc[r][c2]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < NA; ++r) av[r] = A[krow * LDA + r * 16 + (lane & 15)];
+#pragma unroll
+        for (int c2 = 0; c2 < NB; ++c2) bv[c2] = B[krow * LDB + wave * 32 + c2 * 16 + (lane & 15)];
+#pragma unroll
+        for (int r = 0; r < NA; ++r)
+#pragma unroll
+          for (int c2 = 0; c2 < NB; ++c2) acc[r][c2] = Mfma<float>::mma(av[r], bv[c2], acc[r][c2]);
+      }
     }
-    if (c + 1 < nch) sstore(buf ^ 1);
+    if (c + 1 < nch) st.sstore(sA + (buf ^ 1) * (KC * LDA), sB + (buf ^ 1) * (KC * LDB));
     __syncthreads();
   }
 
+  // (row, col, value) of every accumulator element held by this lane
+  auto for_each = [&](auto&& f) {
+#pragma unroll
+    for (int r = 0; r < NA; ++r)
+#pragma unroll
+      for (int c2 = 0; c2 < NB; ++c2) {
+        if constexpr (F64) {
+          f(wave * 4 * RB + 4 * r + (lane >> 4), j0 + 16 * c2 + (lane & 15), acc[r][c2]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            f(r * 16 + Mfma<float>::row(lane, q), j0 + wave * 32 + c2 * 16 + (lane & 15), acc[r][c2][q]);
+        }
+      }
+  };
+
   const int JK = a.J[K];
   const int64_t g0 = a.rowoff[K];
+  const TC* in = st.in;
+  const int64_t ldi = st.ldi;
   if constexpr (EPI == 0) {
     const TC alpha = static_cast<TC>(a.coef[0]);
     const TC beta = static_cast<TC>(a.coef[1]);
     const TC cc = static_cast<TC>(a.coef[2]);
     const TC* prev = static_cast<const TC*>(a.prev);
     TOUT* out = static_cast<TOUT*>(a.out);
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) {
-        const int j = j0 + wave * 32 + c2 * 16 + (lane & 15);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = r * 16 + MF::row(lane, q);
-          if (i < JK && j < ns) {
-            const int64_t g = g0 + i;
-            TC v = alpha * (acc[r][c2][q] - cc * in[g * ldi + j]);
-            if (prev != nullptr) v -= beta * prev[g * a.ldp + j];
-            out[g * a.ldo + j] = static_cast<TOUT>(v);
-          }
-        }
+    for_each([&](int i, int j, TC v0) {
+      if (i < JK && j < ns) {
+        const int64_t g = g0 + i;
+        TC v = alpha * (v0 - cc * in[g * ldi + j]);
+        if (prev != nullptr) v -= beta * prev[g * a.ldp + j];
+        out[g * a.ldo + j] = static_cast<TOUT>(v);
       }
+    });
   } else {
-    // residual partial sums: sum over the element's rows of (H x - theta x)^2
+    // residual partial sums over the element's rows: sum_i (H x - theta x)_i^2
+    static_assert(F64, "residual epilogue is FP64");
+    double* red = reinterpret_cast<double*>(sB);   // free after the main loop
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-      const int j = j0 + wave * 32 + c2 * 16 + (lane & 15);
+    for (int c2 = 0; c2 < NB; ++c2) {
+      const int jl = 16 * c2 + (lane & 15);
+      const int j = j0 + jl;
       const double th = (j < ns) ? a.theta[j] : 0.0;
       double s = 0.0;
 #pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = r * 16 + MF::row(lane, q);
-          if (i < JK && j < ns) {
-            const double v = static_cast<double>(acc[r][c2][q]) -
-                             th * static_cast<double>(in[(g0 + i) * ldi + j]);
-            s += v * v;
-          }
+      for (int r = 0; r < NA; ++r) {
+        const int i = wave * 4 * RB + 4 * r + (lane >> 4);
+        if (i < JK && j < ns) {
+          const double v = static_cast<double>(acc[r][c2]) - th * static_cast<double>(in[(g0 + i) * ldi + j]);
+          s += v * v;
         }
+      }
       s += __shfl_xor(s, 16);
       s += __shfl_xor(s, 32);
-      if (lane < 16 && j < ns) a.part[static_cast<int64_t>(K) * ns + j] = s;
+      if (lane < 16) red[wave * TN + jl] = s;
+    }
+    __syncthreads();
+    if (tid < TN && j0 + tid < ns) {
+      const double s = red[tid] + red[TN + tid] + red[2 * TN + tid] + red[3 * TN + tid];
+      a.part[static_cast<int64_t>(K) * ns + j0 + tid] = s;
     }
   }
 }
