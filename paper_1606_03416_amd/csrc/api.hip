@@ -92,6 +92,8 @@ struct OrthWs {
   double* S;
   double* U1;
   double* U2;
+  double* T;      // U^{-1}
+  double* B;      // n x ns block the passes alternate with
   double* split;
   size_t split_elems;
   int* status;
@@ -102,6 +104,8 @@ void carve_orth(Carver& c, int64_t n, int ns, OrthWs& o) {
   o.S = c.take<double>(nn);
   o.U1 = c.take<double>(nn);
   o.U2 = c.take<double>(nn);
+  o.T = c.take<double>(nn);
+  o.B = c.take<double>(n * static_cast<int64_t>(ns));
   o.split_elems = gemm_tn_split_ws_elems(ns, ns, n);
   o.split = o.split_elems ? c.take<double>(static_cast<int64_t>(o.split_elems)) : nullptr;
   o.status = c.take<int>(4);
@@ -188,17 +192,30 @@ int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, 
   return CHEFSI_OK;
 }
 
+// Cholesky-QR, `passes` times: S = Y^T Y (upper triangle, mirrored),
+// U^T U = S, and Yhat = Y U^{-1} as one GEMM with the triangular inverse
+// (its zero part skipped).  The passes alternate between Y and o.B so that
+// the result ends in Y.
 int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout, const OrthWs& o,
              hipStream_t st) {
   CHEFSI_TRY(launch_fill_int(o.status, 1, 0, st));
   double* Us[2] = {o.U1, o.U2};
+  double* src = Y;
+  int64_t lds = ldy;
   for (int pass = 0; pass < passes; ++pass) {
-    CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y, ldy, Y, ldy, 0.0, o.S, ns, true, o.split, o.split_elems, st));
+    const bool last = (pass == passes - 1);
+    double* dst = (passes == 2 && last) ? Y : o.B;
+    const int64_t ldd = (dst == Y) ? ldy : ns;
+    CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, src, lds, src, lds, 0.0, o.S, ns, true, o.split, o.split_elems, st));
     CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
     CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
-    CHEFSI_TRY(trsm_right_upper(Y, ldy, n, o.S, ns, ns, st));
     CHEFSI_TRY(launch_copy_f64(o.S, ns, Us[pass], ns, ns, ns, st));
+    CHEFSI_TRY(upper_inverse(o.S, ns, o.T, st));
+    CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, src, lds, o.T, ns, 0.0, dst, ldd, st, true));
+    src = dst;
+    lds = ldd;
   }
+  if (src != Y) CHEFSI_TRY(launch_copy_f64(src, lds, Y, ldy, n, ns, st));
   if (Uout != nullptr) {
     if (passes == 1) {
       CHEFSI_TRY(launch_copy_f64(o.U1, ns, Uout, ns, ns, ns, st));
@@ -214,8 +231,9 @@ int run_rr(Plan& p, const void* panel64, const double* Yh, int64_t ldy, int ns, 
   CHEFSI_TRY(launch_const_coef(1.0, 0.0, r.coef, st));
   StepIO io{Yh, ldy, true, nullptr, 0, true, r.W, ns, true};
   CHEFSI_TRY(launch_step(p, panel64, CHEFSI_F64, r.coef, io, ns, st));
-  CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, Yh, ldy, r.W, ns, 0.0, r.Hh, ns, false, r.split, r.split_elems, st));
-  CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 0, st));
+  // Hhat = Yhat^T (H Yhat) is symmetric: form its upper triangle and mirror it
+  CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, Yh, ldy, r.W, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
+  CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
   CHEFSI_TRY(launch_fill_int(r.info, 1, 0, st));
   CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.eig, r.eig_bytes, st));
   CHEFSI_TRY(launch_eigvec_fix(r.Hh, ns, ns, r.Q, ns, st));

@@ -134,8 +134,12 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool upper_only,
             double* d_split_ws, size_t split_ws_elems, hipStream_t st);
 // C(m x n) = alpha * A B + beta * C, A (m x k, lda), B (k x n, ldb), row-major.
+// b_upper: B is upper triangular (its zero part is skipped).
 int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
-            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st);
+            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st,
+            bool b_upper = false);
+// T = U^{-1} for an upper triangular n x n U (T upper triangular).
+int upper_inverse(const double* U, int n, double* T, hipStream_t st);
 size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k);
 // mode 0: (A + A^T)/2; 1: upper -> lower; 2: lower -> upper.
 int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st);

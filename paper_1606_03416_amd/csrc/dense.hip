@@ -13,7 +13,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int GT = 128;   // output tile (rows and columns)
 constexpr int GK = 16;    // reduction rows per LDS chunk
 constexpr int GNT = 256;  // threads
-constexpr int GLD = GT + 2;
+#ifndef CHEFSI_GEMM_PAD
+#define CHEFSI_GEMM_PAD 2
+#endif
+constexpr int GLD = GT + CHEFSI_GEMM_PAD;
 
 // A operand: lane l holds A[l%16][l/16]; B operand: B[l/16][l%16];
 // output element q of lane l is D[4q + l/16][l%16].
@@ -33,6 +36,9 @@ struct GemmArgs {
   int64_t kper;     // reduction rows per split (multiple of GK)
   double* part;     // split partials [split][m][n] or null (direct epilogue)
   bool upper_only;
+  bool b_upper;     // B is upper triangular: column tile tj needs k < (tj+1)*GT only
+  int tri_tiles;    // upper_only: number of upper-triangle tiles (1-D grid)
+  int tn_tiles;     // upper_only: tiles per row of the square tile grid
 };
 
 // Loads of one 128 x GK operand chunk into registers (8 values per thread),
@@ -141,7 +147,30 @@ __device__ __forceinline__ void tile_mma(const double* A, int64_t lda, const dou
 // A_KMAJOR: A stored k x m (TN form); otherwise m x k (NN form).  B is k x n.
 template <bool A_KMAJOR>
 __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
-  const int ti = blockIdx.y, tj = blockIdx.x, split = blockIdx.z;
+  int ti, tj, split;
+  if (g.upper_only) {
+    // 1-D grid over the upper-triangle tiles only (split-major), so that no
+    // work-group idles and consecutive work-groups -- which the hardware
+    // deals out to the XCDs in turn -- carry equal work
+    const int ntiles = g.tri_tiles;
+    split = blockIdx.x / ntiles;
+    int t = blockIdx.x - split * ntiles;
+    ti = 0;
+    int rowlen = g.tn_tiles;
+    while (t >= rowlen) {
+      t -= rowlen;
+      ++ti;
+      --rowlen;
+    }
+    tj = ti + t;
+  } else {
+    // skew the column tile by the row tile: work-group b runs on XCD b % 8, and
+    // without the skew one XCD would receive every tile of one column residue
+    // (uneven work when B is triangular)
+    ti = blockIdx.y;
+    tj = (blockIdx.x + blockIdx.y) % gridDim.x;
+    split = blockIdx.z;
+  }
   if (g.upper_only && ti > tj) return;
   __shared__ double sA[2][GK][GLD];
   __shared__ double sB[2][GK][GLD];
@@ -150,6 +179,7 @@ __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
   const int64_t kbeg = static_cast<int64_t>(split) * g.kper;
   int64_t kend = kbeg + g.kper;
   if (kend > g.k) kend = g.k;
+  if (g.b_upper && kend > j0 + GT) kend = j0 + GT;
   double acc[8][8];
 #pragma unroll
   for (int p = 0; p < 8; ++p)
@@ -495,11 +525,17 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   int splits = choose_splits(upper_only ? (tm * (tm + 1)) / 2 : tm * tn, k);
   if (splits > 1 && (d_split_ws == nullptr || split_ws_elems < static_cast<size_t>(splits) * m * n))
     splits = 1;
-  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, 0, nullptr, upper_only};
+  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, 0, nullptr, upper_only, false, 0, 0};
   g.kper = round_up(ceil_div(k, splits), GK);
   if (k <= 0) g.kper = GK;
   if (splits > 1) g.part = d_split_ws;
   dim3 grid(static_cast<unsigned>(tn), static_cast<unsigned>(tm), static_cast<unsigned>(splits));
+  if (upper_only) {
+    if (tm != tn) return fail(CHEFSI_ERR_ARG, "gemm_tn: upper_only needs a square result");
+    g.tn_tiles = static_cast<int>(tn);
+    g.tri_tiles = static_cast<int>(tn * (tn + 1) / 2);
+    grid = dim3(static_cast<unsigned>(g.tri_tiles * splits), 1, 1);
+  }
   gemm_kernel<true><<<grid, GNT, 0, st>>>(g);
   CHEFSI_LAUNCHED("gemm_tn");
   if (splits > 1) {
@@ -510,11 +546,13 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
 }
 
 int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
-            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st) {
+            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st,
+            bool b_upper) {
   if (m <= 0 || n <= 0) return CHEFSI_OK;
   const int64_t tm = ceil_div(m, GT), tn = ceil_div(n, GT);
   if (tm > 65535) return fail(CHEFSI_ERR_ARG, "gemm_nn: too many row tiles");
-  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, round_up(k > 0 ? k : 1, GK), nullptr, false};
+  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, round_up(k > 0 ? k : 1, GK), nullptr, false, b_upper,
+             0, 0};
   dim3 grid(static_cast<unsigned>(tn), static_cast<unsigned>(tm), 1);
   gemm_kernel<false><<<grid, GNT, 0, st>>>(g);
   CHEFSI_LAUNCHED("gemm_nn");
@@ -585,6 +623,21 @@ int sddmm_accumulate(const Plan& p, const double* A, int64_t lda, const double* 
   sddmm_kernel<<<static_cast<unsigned>(p.M * p.stencil), GNT, 0, st>>>(g);
   CHEFSI_LAUNCHED("sddmm");
   return CHEFSI_OK;
+}
+
+// U^{-1} of an upper triangular U (n x n): solve T U = I by the blocked
+// triangular solve; T is upper triangular.
+__global__ void identity_kernel(double* T, int n) {
+  const int64_t total = static_cast<int64_t>(n) * n;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride)
+    T[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
+int upper_inverse(const double* U, int n, double* T, hipStream_t st) {
+  identity_kernel<<<grid1(static_cast<int64_t>(n) * n), 256, 0, st>>>(T, n);
+  CHEFSI_LAUNCHED("identity");
+  return trsm_right_upper(T, n, n, U, n, n, st);
 }
 
 int launch_fill(double* d, int64_t count, double v, hipStream_t st) {

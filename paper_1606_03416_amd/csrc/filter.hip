@@ -33,7 +33,10 @@ struct Mfma<double> {
   }
   // output element q of a lane sits in row 4q + lane/16 (column lane%16)
   static __device__ __forceinline__ int row(int lane, int q) { return 4 * q + (lane >> 4); }
-  static constexpr int pad = 2;
+#ifndef CHEFSI_STEP_PAD64
+#define CHEFSI_STEP_PAD64 2
+#endif
+  static constexpr int pad = CHEFSI_STEP_PAD64;
 };
 
 template <>
@@ -268,8 +271,20 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
   __shared__ TC sA[2 * KC * LDA];
   __shared__ TC sB[2 * KC * LDB];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
+#ifndef CHEFSI_STEP_ORDER
+#define CHEFSI_STEP_ORDER 0
+#endif
+#if CHEFSI_STEP_ORDER == 0
+  // column-tile major: the work-groups in flight share one column slab of X
   const int ct = id / a.M;
   const int e = id - ct * a.M;
+#else
+  // element major: the column tiles of one element run together (its H panel
+  // is read from HBM once per step)
+  const int nct = (a.ns + TN - 1) / TN;
+  const int e = id / nct;
+  const int ct = id - e * nct;
+#endif
   const int K = a.order[e];
   if constexpr (UNIFORM_RB > 0) {
     step_body<TC, TOUT, UNIFORM_RB, EPI, LDA>(a, K, ct, sA, sB);

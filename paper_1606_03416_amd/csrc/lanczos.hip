@@ -50,55 +50,138 @@ __global__ __launch_bounds__(LT) void lanczos_init_kernel(const double* v0, int6
   }
 }
 
-// Given w = H v_j: alpha_j = v_j^T w, w -= alpha_j v_j + beta_{j-1} v_{j-1},
-// two classical Gram-Schmidt passes against v_0..v_j, beta_j = ||w||,
-// v_{j+1} = w / beta_j (unless beta_j <= 1e-14 |alpha_0|).
-__global__ __launch_bounds__(LT) void lanczos_orth_kernel(double* V, double* w, int64_t N, int j,
-                                                          LanczosState* stt) {
-  __shared__ double red[64];
-  if (stt->stopped) return;
-  const int tid = threadIdx.x;
-  const double* vj = V + static_cast<int64_t>(j) * N;
-  double s = 0.0;
-  for (int64_t i = tid; i < N; i += LT) s += vj[i] * w[i];
-  const double alpha = block_sum(s, red);
-  const double bprev = (j > 0) ? stt->beta[j - 1] : 0.0;
-  const double* vp = (j > 0) ? V + static_cast<int64_t>(j - 1) * N : nullptr;
-  for (int64_t i = tid; i < N; i += LT) w[i] -= alpha * vj[i] + (vp ? bprev * vp[i] : 0.0);
-  __syncthreads();
-  __shared__ double h[kMaxLanczos + 1];
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int t = 0; t <= j; ++t) {
-      const double* vt = V + static_cast<int64_t>(t) * N;
-      double d = 0.0;
-      for (int64_t i = tid; i < N; i += LT) d += vt[i] * w[i];
-      d = block_sum(d, red);
-      if (tid == 0) h[t] = d;
-    }
-    __syncthreads();
-    for (int64_t i = tid; i < N; i += LT) {
-      double acc = w[i];
-      for (int t = 0; t <= j; ++t) acc -= h[t] * V[static_cast<int64_t>(t) * N + i];
-      w[i] = acc;
-    }
-    __syncthreads();
+// y = H x for one vector, straight from the FP64 panel: one work-group per
+// element, thread i accumulates row i over the concatenated neighbour rows
+// (HBM-bound; the panel is read once).
+__global__ __launch_bounds__(128) void spmv_kernel(const double* panel, const int64_t* poff,
+                                                   const int32_t* kpad, const int64_t* koff,
+                                                   const int32_t* kmap, const int32_t* J, const int32_t* rb,
+                                                   const int64_t* rowoff, const double* x, double* y) {
+  const int K = blockIdx.x;
+  const int i = threadIdx.x;
+  if (i >= J[K]) return;
+  const int JP = rb[K] * 16;
+  const double* pk = panel + poff[K] + i;
+  const int32_t* km = kmap + koff[K];
+  const int kp = kpad[K];
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = 0; k < kp; k += 2) {
+    const int g0 = km[k], g1 = km[k + 1];
+    a0 += pk[static_cast<int64_t>(k) * JP] * (g0 >= 0 ? x[g0] : 0.0);
+    a1 += pk[static_cast<int64_t>(k + 1) * JP] * (g1 >= 0 ? x[g1] : 0.0);
   }
-  s = 0.0;
-  for (int64_t i = tid; i < N; i += LT) s += w[i] * w[i];
-  const double beta = sqrt(block_sum(s, red));
-  if (tid == 0) {
-    stt->alpha[j] = alpha;
+  y[rowoff[K] + i] = a0 + a1;
+}
+
+constexpr int RG = 256;   // work-groups of the reduction kernels
+constexpr int RT = 256;   // threads per work-group
+
+// Work-group sum of one value per thread (result valid in all threads).
+__device__ double wg_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < RT / 64; ++w) s += red[w];
+  return s;
+}
+
+// Sum of partials[g * stride + t] over g, in a fixed order.
+__device__ __forceinline__ double sum_partials(const double* part, int stride, int t) {
+  double s = 0.0;
+  for (int g = 0; g < RG; ++g) s += part[g * stride + t];
+  return s;
+}
+
+// Partial dots of w with the vectors V[0..nv-1] over this work-group's rows.
+__device__ void partial_dots(const double* V, const double* w, int64_t N, int nv, double* part,
+                             double* red) {
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RT + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(RG) * RT;
+  for (int t = 0; t < nv; ++t) {
+    const double* vt = V + static_cast<int64_t>(t) * N;
+    double d = 0.0;
+    for (int64_t i = r0; i < N; i += stride) d += vt[i] * w[i];
+    d = wg_sum(d, red);
+    if (threadIdx.x == 0) part[blockIdx.x * (kMaxLanczos + 1) + t] = d;
+  }
+}
+
+// phase 0: partial v_j^T w
+__global__ __launch_bounds__(RT) void lz_alpha_partial(const double* V, const double* w, int64_t N, int j,
+                                                       double* part, const LanczosState* stt) {
+  __shared__ double red[RT / 64];
+  if (stt->stopped) return;
+  partial_dots(V + static_cast<int64_t>(j) * N, w, N, 1, part, red);
+}
+
+// phase 1: alpha_j = sum; w -= alpha_j v_j + beta_{j-1} v_{j-1}; partial V^T w
+__global__ __launch_bounds__(RT) void lz_three_term(double* V, double* w, int64_t N, int j, const double* part_in,
+                                                    double* part_out, LanczosState* stt) {
+  __shared__ double red[RT / 64];
+  if (stt->stopped) return;
+  const double alpha = sum_partials(part_in, kMaxLanczos + 1, 0);
+  const double bprev = (j > 0) ? stt->beta[j - 1] : 0.0;
+  const double* vj = V + static_cast<int64_t>(j) * N;
+  const double* vp = (j > 0) ? V + static_cast<int64_t>(j - 1) * N : nullptr;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RT + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(RG) * RT;
+  for (int64_t i = r0; i < N; i += stride) w[i] -= alpha * vj[i] + (vp ? bprev * vp[i] : 0.0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) stt->alpha[j] = alpha;
+  partial_dots(V, w, N, j + 1, part_out, red);
+}
+
+// phase 2: h = V^T w (summed partials); w -= V h; then partial V^T w again
+// (second Gram-Schmidt pass) or, on the last pass, partial ||w||^2.
+__global__ __launch_bounds__(RT) void lz_cgs(const double* V, double* w, int64_t N, int j, const double* part_in,
+                                             double* part_out, int last, const LanczosState* stt) {
+  __shared__ double red[RT / 64];
+  __shared__ double h[kMaxLanczos + 1];
+  if (stt->stopped) return;
+  if (threadIdx.x <= j) h[threadIdx.x] = sum_partials(part_in, kMaxLanczos + 1, threadIdx.x);
+  __syncthreads();
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RT + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(RG) * RT;
+  for (int64_t i = r0; i < N; i += stride) {
+    double acc = w[i];
+    for (int t = 0; t <= j; ++t) acc -= h[t] * V[static_cast<int64_t>(t) * N + i];
+    w[i] = acc;
+  }
+  if (!last) {
+    partial_dots(V, w, N, j + 1, part_out, red);
+  } else {
+    double d = 0.0;
+    for (int64_t i = r0; i < N; i += stride) d += w[i] * w[i];
+    d = wg_sum(d, red);
+    if (threadIdx.x == 0) part_out[blockIdx.x * (kMaxLanczos + 1)] = d;
+  }
+}
+
+// phase 3: beta_j = ||w||; v_{j+1} = w / beta_j unless beta_j <= 1e-14 |alpha_0|.
+__global__ __launch_bounds__(RT) void lz_normalize(double* V, const double* w, int64_t N, int j,
+                                                   const double* part_in, LanczosState* stt) {
+  if (stt->stopped) return;
+  const double beta = sqrt(sum_partials(part_in, kMaxLanczos + 1, 0));
+  const double a0 = stt->alpha[0];
+  const bool stop = beta <= 1e-14 * fabs(a0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     stt->beta[j] = beta;
     stt->steps = j + 1;
   }
-  const double a0 = (j == 0) ? alpha : stt->alpha[0];
-  if (beta <= 1e-14 * fabs(a0)) {
-    if (tid == 0) stt->stopped = 1;
-    return;
-  }
+  if (stop) return;
   double* vn = V + static_cast<int64_t>(j + 1) * N;
   const double inv = 1.0 / beta;
-  for (int64_t i = tid; i < N; i += LT) vn[i] = w[i] * inv;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RT + threadIdx.x;
+  const int64_t stride = static_cast<int64_t>(RG) * RT;
+  for (int64_t i = r0; i < N; i += stride) vn[i] = w[i] * inv;
+}
+
+__global__ void lz_check_stop(LanczosState* stt, int j) {
+  if (threadIdx.x == 0 && !stt->stopped && stt->steps == j + 1) {
+    if (stt->beta[j] <= 1e-14 * fabs(stt->alpha[0])) stt->stopped = 1;
+  }
 }
 
 // Eigenpairs of the tridiagonal T (order n <= 64) by cyclic Jacobi on one
@@ -213,7 +296,7 @@ size_t lanczos_ws_bytes(const Plan& p, int k) {
   c.take<double>(static_cast<int64_t>(k + 1) * p.N);
   c.take<double>(p.N);
   c.take<LanczosState>(1);
-  c.take<double>(4);
+  c.take<double>(2 * static_cast<int64_t>(RG) * (kMaxLanczos + 1));
   return c.used;
 }
 
@@ -224,16 +307,22 @@ int lanczos_bounds(const Plan& p, const void* d_panel64, const double* d_v0, int
   double* V = c.take<double>(static_cast<int64_t>(k + 1) * p.N);
   double* w = c.take<double>(p.N);
   LanczosState* stt = c.take<LanczosState>(1);
-  double* coef = c.take<double>(4);
+  double* partA = c.take<double>(2 * static_cast<int64_t>(RG) * (kMaxLanczos + 1));
+  double* partB = partA + static_cast<int64_t>(RG) * (kMaxLanczos + 1);
   if (!c.ok()) return fail(CHEFSI_ERR_WORKSPACE, "bounds: workspace too small");
   lanczos_init_kernel<<<1, LT, 0, st>>>(d_v0, p.N, V, stt);
   CHEFSI_LAUNCHED("lanczos_init");
-  CHEFSI_TRY(launch_const_coef(1.0, 0.0, coef, st));
+  const double* panel = static_cast<const double*>(d_panel64);
   for (int j = 0; j < k; ++j) {
-    StepIO io{V + static_cast<int64_t>(j) * p.N, 1, true, nullptr, 0, true, w, 1, true};
-    CHEFSI_TRY(launch_step(p, d_panel64, CHEFSI_F64, coef, io, 1, st));
-    lanczos_orth_kernel<<<1, LT, 0, st>>>(V, w, p.N, j, stt);
-    CHEFSI_LAUNCHED("lanczos_orth");
+    spmv_kernel<<<p.M, 128, 0, st>>>(panel, p.d_poff, p.d_kpad, p.d_koff, p.d_kmap, p.d_J, p.d_rb, p.d_rowoff,
+                                     V + static_cast<int64_t>(j) * p.N, w);
+    lz_alpha_partial<<<RG, RT, 0, st>>>(V, w, p.N, j, partA, stt);
+    lz_three_term<<<RG, RT, 0, st>>>(V, w, p.N, j, partA, partB, stt);
+    lz_cgs<<<RG, RT, 0, st>>>(V, w, p.N, j, partB, partA, 0, stt);
+    lz_cgs<<<RG, RT, 0, st>>>(V, w, p.N, j, partA, partB, 1, stt);
+    lz_normalize<<<RG, RT, 0, st>>>(V, w, p.N, j, partB, stt);
+    lz_check_stop<<<1, 64, 0, st>>>(stt, j);
+    CHEFSI_LAUNCHED("lanczos step");
   }
   const double frac = static_cast<double>(ns) / static_cast<double>(p.N);
   lanczos_bounds_kernel<<<1, 64, 0, st>>>(stt, d_ritz_prev, ns, frac, d_bounds);
