@@ -99,7 +99,7 @@ struct Stage {
   TC ra[AQ];
   TC rb[BQ];
   const TC* panel;
-  const int32_t* kmap;
+  const int32_t* kmap;   // LDS copy of the element's row map
   const TC* in;
   int64_t ldi;
   int j0, bcol, brow0;
@@ -130,7 +130,7 @@ struct Stage {
 };
 
 template <typename TC, typename TOUT, int RB, int EPI, int LDA>
-__device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* sA, TC* sB) {
+__device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* sA, TC* sB, int32_t* sK) {
   using ST = Stage<TC, RB, LDA>;
   constexpr int LDB = ST::LDB;
   constexpr bool F64 = std::is_same<TC, double>::value;
@@ -140,7 +140,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* 
   const int ns = a.ns;
   ST st;
   st.panel = static_cast<const TC*>(a.panel) + a.poff[K];
-  st.kmap = a.kmap + a.koff[K];
+  // the global row of every concatenated neighbour row, staged once in LDS so
+  // that the operand prefetch needs no dependent global load
+  {
+    const int32_t* km = a.kmap + a.koff[K];
+    const int kp = a.kpad[K];
+    for (int t = tid; t < kp; t += NT) sK[t] = km[t];
+  }
+  st.kmap = sK;
   st.in = static_cast<const TC*>(a.in);
   st.ldi = a.ldi;
   st.j0 = ct * TN;
@@ -149,6 +156,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* 
   st.col_ok = (st.j0 + st.bcol) < ns;
   const int j0 = st.j0;
   const int nch = a.kpad[K] / KC;
+  __syncthreads();
 
   // FP64: wave w owns rows 4*RB*w .. +4*RB (RB four-row fragments) and all 128
   // columns (8 sixteen-column fragments), one accumulator value per fragment.
@@ -270,6 +278,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
   constexpr int LDB = TN + Mfma<TC>::pad;
   __shared__ TC sA[2 * KC * LDA];
   __shared__ TC sB[2 * KC * LDB];
+  __shared__ int32_t sK[7 * kMaxJ];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
 #ifndef CHEFSI_STEP_ORDER
 #define CHEFSI_STEP_ORDER 0
@@ -287,17 +296,17 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 #endif
   const int K = a.order[e];
   if constexpr (UNIFORM_RB > 0) {
-    step_body<TC, TOUT, UNIFORM_RB, EPI, LDA>(a, K, ct, sA, sB);
+    step_body<TC, TOUT, UNIFORM_RB, EPI, LDA>(a, K, ct, sA, sB, sK);
   } else {
     switch (a.rbv[K]) {
-      case 1: step_body<TC, TOUT, 1, EPI, LDA>(a, K, ct, sA, sB); break;
-      case 2: step_body<TC, TOUT, 2, EPI, LDA>(a, K, ct, sA, sB); break;
-      case 3: step_body<TC, TOUT, 3, EPI, LDA>(a, K, ct, sA, sB); break;
-      case 4: step_body<TC, TOUT, 4, EPI, LDA>(a, K, ct, sA, sB); break;
-      case 5: step_body<TC, TOUT, 5, EPI, LDA>(a, K, ct, sA, sB); break;
-      case 6: step_body<TC, TOUT, 6, EPI, LDA>(a, K, ct, sA, sB); break;
-      case 7: step_body<TC, TOUT, 7, EPI, LDA>(a, K, ct, sA, sB); break;
-      default: step_body<TC, TOUT, 8, EPI, LDA>(a, K, ct, sA, sB); break;
+      case 1: step_body<TC, TOUT, 1, EPI, LDA>(a, K, ct, sA, sB, sK); break;
+      case 2: step_body<TC, TOUT, 2, EPI, LDA>(a, K, ct, sA, sB, sK); break;
+      case 3: step_body<TC, TOUT, 3, EPI, LDA>(a, K, ct, sA, sB, sK); break;
+      case 4: step_body<TC, TOUT, 4, EPI, LDA>(a, K, ct, sA, sB, sK); break;
+      case 5: step_body<TC, TOUT, 5, EPI, LDA>(a, K, ct, sA, sB, sK); break;
+      case 6: step_body<TC, TOUT, 6, EPI, LDA>(a, K, ct, sA, sB, sK); break;
+      case 7: step_body<TC, TOUT, 7, EPI, LDA>(a, K, ct, sA, sB, sK); break;
+      default: step_body<TC, TOUT, 8, EPI, LDA>(a, K, ct, sA, sB, sK); break;
     }
   }
 }
