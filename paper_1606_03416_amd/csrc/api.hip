@@ -93,6 +93,7 @@ struct OrthWs {
   double* U1;
   double* U2;
   double* T;      // U^{-1}
+  double* Wt;     // scratch of the triangular inverse
   double* B;      // n x ns block the passes alternate with
   double* split;
   size_t split_elems;
@@ -105,6 +106,7 @@ void carve_orth(Carver& c, int64_t n, int ns, OrthWs& o) {
   o.U1 = c.take<double>(nn);
   o.U2 = c.take<double>(nn);
   o.T = c.take<double>(nn);
+  o.Wt = c.take<double>((static_cast<int64_t>(ns) / 2 + 64) * (static_cast<int64_t>(ns) / 2 + 64));
   o.B = c.take<double>(n * static_cast<int64_t>(ns));
   o.split_elems = gemm_tn_split_ws_elems(ns, ns, n);
   o.split = o.split_elems ? c.take<double>(static_cast<int64_t>(o.split_elems)) : nullptr;
@@ -210,7 +212,7 @@ int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout
     CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
     CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
     CHEFSI_TRY(launch_copy_f64(o.S, ns, Us[pass], ns, ns, ns, st));
-    CHEFSI_TRY(upper_inverse(o.S, ns, o.T, st));
+    CHEFSI_TRY(upper_inverse(o.S, ns, o.T, o.Wt, st));
     CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, src, lds, o.T, ns, 0.0, dst, ldd, st, true));
     src = dst;
     lds = ldd;

@@ -138,8 +138,9 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
 int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st,
             bool b_upper = false);
-// T = U^{-1} for an upper triangular n x n U (T upper triangular).
-int upper_inverse(const double* U, int n, double* T, hipStream_t st);
+// T = U^{-1} for an upper triangular n x n U (T upper triangular); W is
+// scratch of (n/2 + 64)^2 doubles.
+int upper_inverse(const double* U, int n, double* T, double* W, hipStream_t st);
 size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k);
 // mode 0: (A + A^T)/2; 1: upper -> lower; 2: lower -> upper.
 int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st);

@@ -625,19 +625,54 @@ int sddmm_accumulate(const Plan& p, const double* A, int64_t lda, const double* 
   return CHEFSI_OK;
 }
 
-// U^{-1} of an upper triangular U (n x n): solve T U = I by the blocked
-// triangular solve; T is upper triangular.
-__global__ void identity_kernel(double* T, int n) {
-  const int64_t total = static_cast<int64_t>(n) * n;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride)
-    T[t] = (t / n == t % n) ? 1.0 : 0.0;
+// Inverse of the upper triangular diagonal 64 x 64 blocks of U, one block per
+// work-group: thread j forms column j of the block inverse by back
+// substitution.
+__global__ __launch_bounds__(64) void trtri_diag_kernel(const double* U, int64_t ldu, double* T, int64_t ldt,
+                                                        int n) {
+  __shared__ double Us[CB][CB + 1];
+  __shared__ double Ts[CB][CB + 1];
+  const int r0 = blockIdx.x * CB;
+  const int w = (n - r0) < CB ? (n - r0) : CB;
+  const int j = threadIdx.x;
+  for (int r = 0; r < w; ++r)
+    if (j < w) Us[r][j] = U[static_cast<int64_t>(r0 + r) * ldu + r0 + j];
+  __syncthreads();
+  if (j < w) {
+    for (int r = 0; r < w; ++r) Ts[r][j] = 0.0;
+    Ts[j][j] = 1.0 / Us[j][j];
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int k = i + 1; k <= j; ++k) acc += Us[i][k] * Ts[k][j];
+      Ts[i][j] = -acc / Us[i][i];
+    }
+  }
+  __syncthreads();
+  for (int r = 0; r < w; ++r)
+    if (j < w) T[static_cast<int64_t>(r0 + r) * ldt + r0 + j] = Ts[r][j];
 }
 
-int upper_inverse(const double* U, int n, double* T, hipStream_t st) {
-  identity_kernel<<<grid1(static_cast<int64_t>(n) * n), 256, 0, st>>>(T, n);
-  CHEFSI_LAUNCHED("identity");
-  return trsm_right_upper(T, n, n, U, n, n, st);
+// Off-diagonal blocks of T = U^{-1} by recursive halving:
+//   [U11 U12; 0 U22]^{-1} = [T11, -T11 U12 T22; 0, T22].
+int trtri_offdiag(const double* U, int64_t ldu, double* T, int64_t ldt, int n, double* W, hipStream_t st) {
+  if (n <= CB) return CHEFSI_OK;
+  const int h = CB * static_cast<int>(ceil_div(n, 2 * CB));
+  CHEFSI_TRY(trtri_offdiag(U, ldu, T, ldt, h, W, st));
+  CHEFSI_TRY(trtri_offdiag(U + static_cast<int64_t>(h) * ldu + h, ldu, T + static_cast<int64_t>(h) * ldt + h, ldt,
+                           n - h, W, st));
+  CHEFSI_TRY(gemm_nn(h, n - h, n - h, 1.0, U + h, ldu, T + static_cast<int64_t>(h) * ldt + h, ldt, 0.0, W, n - h, st,
+                     true));
+  CHEFSI_TRY(gemm_nn(h, n - h, h, -1.0, T, ldt, W, n - h, 0.0, T + h, ldt, st));
+  return CHEFSI_OK;
+}
+
+// T = U^{-1} (n x n, upper triangular, row-major); W is scratch of n*n/4
+// doubles (rounded up).
+int upper_inverse(const double* U, int n, double* T, double* W, hipStream_t st) {
+  CHEFSI_TRY(launch_fill(T, static_cast<int64_t>(n) * n, 0.0, st));
+  trtri_diag_kernel<<<static_cast<unsigned>(ceil_div(n, CB)), 64, 0, st>>>(U, n, T, n, n);
+  CHEFSI_LAUNCHED("trtri_diag");
+  return trtri_offdiag(U, n, T, n, n, W, st);
 }
 
 int launch_fill(double* d, int64_t count, double v, hipStream_t st) {
