@@ -8,7 +8,7 @@ CholeskyQR2.  Inputs are seeded synthetic blocks resident in HBM before timing.
 
 Printed: one JSON line with the sweep time (value), the filter TFLOP/s, the
 per-stage times, the roofline of the dominant kernel (the Chebyshev step),
-the mixed-precision comparison (2 FP32-filter sweeps + 2 FP64 sweeps against
+the mixed-precision comparison (2 FP32- or BF16-filter sweeps + 2 FP64 sweeps against
 4 FP64 sweeps from the same start, at the same final residual) and the CPU
 oracle baseline on a bounded sample.
 """
@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "hbm": 8000.0}   # dense MFMA TFLOP/s; HBM GB/s
 HBM_PEAK = 8000.0                                      # GB/s
 METRIC = "CheFSI sweep time + filter TFLOP/s, mixed vs FP64 at fixed Ritz error"
 
@@ -117,14 +117,17 @@ def cpu_baseline(w, P, X0, v0, passes, sample_cols):
 
 
 def filter_mode(args, w, P, plan, H, X0d, chefsi, torch):
-    """Time p_m(H)X alone (FP64) and report the step kernel's roofline."""
+    """Time p_m(H)X alone and report the step kernel's roofline: FP64 and FP32
+    steps are MFMA-bound, BF16 steps HBM-bound (intensity below the ridge)."""
     ns, m = w.ns, w.m
+    dt = {"f64": chefsi.F64, "f32": chefsi.F32, "bf16": chefsi.BF16}[args.filter_dtype]
+    esz = {"f64": 8, "f32": 4, "bf16": 2}[args.filter_dtype]
     dev = X0d.device
     Y = torch.empty_like(X0d)
     a, b, a0 = 0.0, 6.0, -1.5
     st = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        plan.filter(H, X0d, m, a, b, a0, out=Y)
+        plan.filter(H, X0d, m, a, b, a0, out=Y, dtype=dt)
     # a plain device copy of known size (for scaling HBM byte counters)
     copy_bytes = X0d.numel() * 8
     Xc = torch.empty_like(X0d)
@@ -134,9 +137,9 @@ def filter_mode(args, w, P, plan, H, X0d, chefsi, torch):
     times = []
     for _ in range(args.steps):
         e[0].record(st)
-        plan.filter(H, X0d, 1, a, b, a0, out=Y)
+        plan.filter(H, X0d, 1, a, b, a0, out=Y, dtype=dt)
         e[1].record(st)
-        plan.filter(H, X0d, m, a, b, a0, out=Y)
+        plan.filter(H, X0d, m, a, b, a0, out=Y, dtype=dt)
         e[2].record(st)
         torch.cuda.synchronize()
         t1 = e[0].elapsed_time(e[1])
@@ -145,14 +148,23 @@ def filter_mode(args, w, P, plan, H, X0d, chefsi, torch):
     step_ms = float(np.median(times))
     f_step = filter_flops_per_step(P, ns)
     achieved = f_step / (step_ms * 1e-3) / 1e12
+    alg_bytes = 3 * esz * P.N * ns + esz * P.packed_size()
+    if args.filter_dtype == "bf16":
+        gbs = alg_bytes / (step_ms * 1e-3) / 1e9
+        roof = {"kernel": "cheb_step BF16", "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm"],
+                "unit": "GB/s", "frac": round(gbs / PEAK["hbm"], 4), "bytes_per_launch": alg_bytes,
+                "tflops": round(achieved, 2)}
+    else:
+        pk = PEAK[args.filter_dtype]
+        roof = {"kernel": f"cheb_step {args.filter_dtype.upper()}", "bound": "mfma", "achieved": round(achieved, 2),
+                "peak": pk, "unit": "TFLOP/s", "frac": round(achieved / pk, 4), "flops_per_launch": f_step}
     out = {
         "mode": "filter", "workload": w.name, "N": P.N, "ns": ns, "filter_degree": m,
+        "filter_dtype": args.filter_dtype,
         "avg_step_ms": round(step_ms, 4), "filter_ms": round(step_ms * m, 3),
-        "roofline": {"kernel": "cheb_step FP64", "bound": "mfma", "achieved": round(achieved, 2),
-                     "peak": PEAK["f64"], "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),
-                     "flops_per_launch": f_step},
+        "roofline": roof,
         "calibration_copy_bytes": copy_bytes,
-        "algorithmic_bytes_per_step": 3 * 8 * P.N * ns + 8 * P.packed_size(),
+        "algorithmic_bytes_per_step": alg_bytes,
     }
     print(json.dumps(out), flush=True)
 
@@ -170,6 +182,8 @@ def main():
     ap.add_argument("--mode", default="sweep", choices=["sweep", "filter"],
                     help="filter: time only the FP64 Chebyshev filter (the dominant kernel), "
                          "with a plain device copy of known size for counter calibration")
+    ap.add_argument("--filter-dtype", default="f64", choices=["f64", "f32", "bf16"],
+                    help="arithmetic of the filter in --mode filter")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -192,7 +206,7 @@ def main():
     v0d = torch.from_numpy(v0).to(dev)
     X = X0d.clone()
     ws_bytes = max(plan.workspace_bytes(chefsi.OP_SWEEP, ns, dt, args.passes, w.lanczos_steps)
-                   for dt in (chefsi.F64, chefsi.F32))
+                   for dt in (chefsi.F64, chefsi.F32, chefsi.BF16))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     log(f"N={P.N} ns={ns} m={m}; workspace {ws.numel() / 1e9:.2f} GB")
@@ -252,7 +266,9 @@ def main():
     if not args.no_mixed:
         k = 3 * ns // 4
         runs = {}
-        for label, dts in (("f64x4", [chefsi.F64] * 4), ("f32x2+f64x2", [chefsi.F32] * 2 + [chefsi.F64] * 2)):
+        plans = (("f64x4", [chefsi.F64] * 4), ("f32x2+f64x2", [chefsi.F32] * 2 + [chefsi.F64] * 2),
+                 ("bf16x2+f64x2", [chefsi.BF16] * 2 + [chefsi.F64] * 2))
+        for label, dts in plans:
             Xm = X0d.clone()
             rz = None
             times, ftimes = [], []
@@ -264,23 +280,30 @@ def main():
                            "ritz": rz.cpu().numpy(), "max_resid": float(rs[:k].max().item())}
             del Xm
             log(f"{label}: sweeps {runs[label]['sweep_ms']} ms, max resid {runs[label]['max_resid']:.3e}")
-        r64, rmx = runs["f64x4"], runs["f32x2+f64x2"]
+        r64 = runs["f64x4"]
         s = float(max(abs(bnd[2].item()), abs(bnd[1].item())))
-        f32_filter_tflops = fl["filter"] / (np.mean(rmx["filter_steps_ms"][:2]) * 1e-3) / 1e12
         f64_filter_tflops = fl["filter"] / (np.mean(r64["filter_steps_ms"]) * 1e-3) / 1e12
         result["mixed"] = {
-            "protocol": "same X0: 4 FP64 sweeps vs 2 FP32-filter sweeps + 2 FP64 sweeps; Ritz error = max FP64 "
-                        "residual over the lowest 3/4 N_s",
+            "protocol": "same X0: 4 FP64 sweeps vs 2 low-precision-filter sweeps + 2 FP64 sweeps; Ritz error = "
+                        "max FP64 residual over the lowest 3/4 N_s",
             "f64_total_ms": round(sum(r64["sweep_ms"]), 2),
-            "mixed_total_ms": round(sum(rmx["sweep_ms"]), 2),
-            "speedup_total": round(sum(r64["sweep_ms"]) / sum(rmx["sweep_ms"]), 3),
-            "speedup_lowp_sweep": round(np.mean(r64["sweep_ms"][:2]) / np.mean(rmx["sweep_ms"][:2]), 3),
-            "speedup_filter": round(f32_filter_tflops / f64_filter_tflops, 3),
-            "f32_filter_tflops": round(f32_filter_tflops, 2),
-            "f64_max_resid": r64["max_resid"], "mixed_max_resid": rmx["max_resid"],
-            "ritz_max_rel_diff": float(np.max(np.abs(rmx["ritz"][:k] - r64["ritz"][:k]) /
-                                              np.maximum(np.abs(r64["ritz"][:k]), s))),
+            "f64_filter_tflops": round(f64_filter_tflops, 2),
+            "f64_max_resid": r64["max_resid"],
         }
+        for tag, label in (("f32", "f32x2+f64x2"), ("bf16", "bf16x2+f64x2")):
+            rmx = runs[label]
+            lowp_tflops = fl["filter"] / (np.mean(rmx["filter_steps_ms"][:2]) * 1e-3) / 1e12
+            result["mixed"][tag] = {
+                "mixed_total_ms": round(sum(rmx["sweep_ms"]), 2),
+                "speedup_total": round(sum(r64["sweep_ms"]) / sum(rmx["sweep_ms"]), 3),
+                "speedup_lowp_sweep": round(np.mean(r64["sweep_ms"][:2]) / np.mean(rmx["sweep_ms"][:2]), 3),
+                "speedup_filter": round(lowp_tflops / f64_filter_tflops, 3),
+                "filter_tflops": round(lowp_tflops, 2),
+                "max_resid": rmx["max_resid"],
+                "resid_ratio_vs_f64": round(rmx["max_resid"] / r64["max_resid"], 4),
+                "ritz_max_rel_diff": float(np.max(np.abs(rmx["ritz"][:k] - r64["ritz"][:k]) /
+                                                  np.maximum(np.abs(r64["ritz"][:k]), s))),
+            }
 
     if not args.no_cpu:
         log("CPU oracle baseline on a column sample")

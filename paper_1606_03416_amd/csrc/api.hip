@@ -60,6 +60,9 @@ size_t mv_bytes(int64_t n, int64_t ld, int ns, size_t elt) {
 
 int elt_size(int dtype) { return dtype == CHEFSI_F64 ? 8 : (dtype == CHEFSI_F32 ? 4 : 2); }
 
+// leading dimension of the internal BF16 recurrence buffers (16-byte rows)
+int64_t lowp_ld(int ns) { return round_up(ns, 8); }
+
 bool valid_dtype(int dtype) { return dtype == CHEFSI_F64 || dtype == CHEFSI_F32 || dtype == CHEFSI_BF16; }
 
 // ------------------------------------------------------------ workspace layouts
@@ -81,6 +84,11 @@ void carve_filter(Carver& c, const Plan& p, int ns, int dtype, bool need_panel, 
   if (dtype == CHEFSI_F64) {
     f.buf0 = c.take<double>(mv);
     f.buf1 = f.buf2 = nullptr;
+  } else if (dtype == CHEFSI_BF16) {
+    const int64_t mvp = p.N * lowp_ld(ns);
+    f.buf0 = c.take<char>(mvp * e);
+    f.buf1 = c.take<char>(mvp * e);
+    f.buf2 = c.take<char>(mvp * e);
   } else {
     f.buf0 = c.take<char>(mv * e);
     f.buf1 = c.take<char>(mv * e);
@@ -175,19 +183,20 @@ int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, 
   }
   // low precision: X converted once, Y_1..Y_{m-1} in two rotating buffers,
   // Y_m written in FP64.
-  CHEFSI_TRY(launch_convert(X, ldx, f.buf0, dtype, ns, p.N, ns, st));
+  const int64_t ldl = (dtype == CHEFSI_BF16) ? lowp_ld(ns) : ns;
+  CHEFSI_TRY(launch_convert(X, ldx, f.buf0, dtype, ldl, p.N, ns, st));
   void* L[2] = {f.buf1, f.buf2};
   for (int k = 0; k < m; ++k) {
     StepIO io{};
     io.in = (k == 0) ? f.buf0 : L[k % 2];
-    io.ldi = ns;
+    io.ldi = ldl;
     io.in_f64 = false;
     io.prev = (k == 0) ? nullptr : (k == 1 ? f.buf0 : L[(k - 1) % 2]);
-    io.ldp = ns;
+    io.ldp = ldl;
     io.prev_f64 = false;
     const bool last = (k == m - 1);
     io.out = last ? static_cast<void*>(Y) : L[(k + 1) % 2];
-    io.ldo = last ? ldy : ns;
+    io.ldo = last ? ldy : ldl;
     io.out_f64 = last;
     CHEFSI_TRY(launch_step(p, panel, dtype, coef + 3 * k, io, ns, st));
   }
@@ -519,7 +528,7 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
         kt += p->J[Kp];
       }
       p->ktot[K] = kt;
-      p->kpad[K] = static_cast<int32_t>(round_up(kt, kStepKC));
+      p->kpad[K] = static_cast<int32_t>(round_up(kt, kPadK));
       p->rb[K] = static_cast<int32_t>(ceil_div(p->J[K], 16));
       p->poff[K] = po;
       po += static_cast<int64_t>(p->kpad[K]) * p->rb[K] * 16;
@@ -701,7 +710,6 @@ int chefsi_filter(chefsi_plan plan, const double* d_H, int m, double a, double b
     CHEFSI_TRY(validate_mv("Y", d_Y, ldy, ns));
     if (ns > 0 && overlaps(d_X, mv_bytes(p.N, ldx, ns, 8), d_Y, mv_bytes(p.N, ldy, ns, 8)))
       return fail(CHEFSI_ERR_ARG, "X and Y overlap");
-    if (dtype == CHEFSI_BF16) return fail(CHEFSI_ERR_UNSUPPORTED, "BF16 filter not built");
     size_t need = 0;
     CHEFSI_TRY(chefsi_workspace_bytes(plan, CHEFSI_OP_FILTER, ns, dtype, 1, 1, &need));
     CHEFSI_TRY(check_ws(ws, ws_bytes, need));
@@ -788,7 +796,6 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
     if (d_H == nullptr || d_ritz == nullptr) return fail(CHEFSI_ERR_ARG, "H or ritz is NULL");
     if (m < 0 || m > kMaxDegree) return fail(CHEFSI_ERR_ARG, "filter degree must be in [0, 100000]");
     if (!valid_dtype(filter_dtype)) return fail(CHEFSI_ERR_ARG, "bad dtype");
-    if (filter_dtype == CHEFSI_BF16) return fail(CHEFSI_ERR_UNSUPPORTED, "BF16 filter not built");
     if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
     if (ns < 1 || ns > p.N) return fail(CHEFSI_ERR_ARG, "ns must be in [1, N]");
     if (d_bounds_in == nullptr) {

@@ -41,7 +41,8 @@ int fail(int code, const std::string& msg);
 constexpr int kMaxJ = 128;          // largest ALB count per element supported
 constexpr int kMaxLanczos = 64;     // largest Lanczos step count
 constexpr int kStepTN = 128;        // columns per work-group of the step kernel
-constexpr int kStepKC = 16;         // reduction rows staged per LDS chunk
+constexpr int kStepKC = 16;         // reduction rows staged per LDS chunk (FP64/FP32)
+constexpr int kPadK = 32;           // reduction rows of an element padded to this (BF16 chunk)
 
 __host__ __device__ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 __host__ __device__ inline int64_t ceil_div(int64_t v, int64_t m) { return (v + m - 1) / m; }
@@ -62,7 +63,7 @@ struct Plan {
   int32_t* d_J = nullptr;       // [M]
   int32_t* d_nbr = nullptr;     // [M*S]
   int32_t* d_rb = nullptr;      // [M] row blocks (ceil(J/16))
-  int32_t* d_kpad = nullptr;    // [M] reduction rows padded to kStepKC
+  int32_t* d_kpad = nullptr;    // [M] reduction rows padded to kPadK
   int32_t* d_order = nullptr;   // [M] element processing order (heaviest first)
   int64_t* d_rowoff = nullptr;  // [M+1]
   int64_t* d_hoff = nullptr;    // [M*S] block offsets in block-list layout

@@ -88,6 +88,15 @@ __device__ __forceinline__ double mma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
+// float <-> bf16 (round to nearest even; NaN stays NaN)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>(0x7fc0u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
 // Operand staging shared by both arithmetic paths: the k-major panel chunk
 // (KC x JP) and the gathered neighbour rows (KC x TN) of the input block.
 template <typename TC, int RB, int LDA>
@@ -311,6 +320,190 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- BF16 path
+// BF16 storage and MFMA operands (v_mfma_f32_16x16x32_bf16), FP32
+// accumulation and epilogue.  Lane l supplies A[l%16][8(l/16)..+7] and
+// B[8(l/16)..+7][l%16] and receives D[4(l/16)+q][l%16], q = 0..3.  One MFMA
+// k-step covers a whole 32-row chunk; the gathered X rows are transposed on
+// their way into LDS so that each lane's eight reduction rows are contiguous.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int KB = kPadK;     // reduction rows per chunk
+constexpr int BLD = KB + 8;   // LDS row length (bf16 units), 16-byte aligned rows
+
+template <typename TOUT, int RB>
+__device__ __forceinline__ void step_body_bf16(const StepArgs& a, int K, int ct, uint16_t* sA, uint16_t* sB,
+                                               int32_t* sK) {
+  constexpr int JP = RB * 16;
+  constexpr int AV = (JP * KB / 8 + NT - 1) / NT;   // 16-byte vectors of A per thread per chunk
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ns = a.ns;
+  const int j0 = ct * TN;
+  {
+    const int32_t* km = a.kmap + a.koff[K];
+    const int kp = a.kpad[K];
+    for (int t = tid; t < kp; t += NT) sK[t] = km[t];
+  }
+  const int nch = a.kpad[K] / KB;
+  const uint16_t* panel = static_cast<const uint16_t*>(a.panel) + a.poff[K];
+  const uint16_t* in = static_cast<const uint16_t*>(a.in);
+  const int64_t ldi = a.ldi;
+  const int rp = tid >> 4;          // row pair of the chunk (rows 2rp, 2rp+1)
+  const int cg = (tid & 15) * 8;    // first of this thread's 8 columns
+  __syncthreads();
+
+  uint4 ra[AV];
+  uint4 rb[2];
+  auto gload = [&](int c) {
+    const uint4* pa = reinterpret_cast<const uint4*>(panel + static_cast<int64_t>(c) * JP * KB);
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int idx = tid + NT * v;
+      if (idx < JP * KB / 8) ra[v] = pa[idx];
+    }
+#pragma unroll
+    for (int r2 = 0; r2 < 2; ++r2) {
+      const int g = sK[c * KB + 2 * rp + r2];
+      const int col = j0 + cg;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (g >= 0) {
+        const uint16_t* src = in + static_cast<int64_t>(g) * ldi + col;
+        if (col + 8 <= ns) {
+          v = *reinterpret_cast<const uint4*>(src);
+        } else if (col < ns) {
+          uint16_t t[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) t[e] = (col + e < ns) ? src[e] : static_cast<uint16_t>(0);
+          v = make_uint4(t[0] | (static_cast<uint32_t>(t[1]) << 16), t[2] | (static_cast<uint32_t>(t[3]) << 16),
+                         t[4] | (static_cast<uint32_t>(t[5]) << 16), t[6] | (static_cast<uint32_t>(t[7]) << 16));
+        }
+      }
+      rb[r2] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+    uint16_t* A = sA + buf * (kMaxJ * BLD);
+    uint16_t* B = sB + buf * (TN * BLD);
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int idx = tid + NT * v;
+      if (idx < JP * KB / 8) *reinterpret_cast<uint4*>(A + (idx >> 2) * BLD + (idx & 3) * 8) = ra[v];
+    }
+    const uint32_t lo[4] = {rb[0].x, rb[0].y, rb[0].z, rb[0].w};
+    const uint32_t hi[4] = {rb[1].x, rb[1].y, rb[1].z, rb[1].w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t x0 = (lo[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+      const uint32_t x1 = (hi[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+      *reinterpret_cast<uint32_t*>(B + (cg + e) * BLD + 2 * rp) = x0 | (x1 << 16);
+    }
+  };
+
+  f32x4 acc[RB][2];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    acc[r][0] = f32x4{0, 0, 0, 0};
+    acc[r][1] = f32x4{0, 0, 0, 0};
+  }
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) gload(c + 1);
+    const uint16_t* A = sA + buf * (kMaxJ * BLD);
+    const uint16_t* B = sB + buf * (TN * BLD);
+    const int kq = 8 * (lane >> 4);
+    bf16x8 bv[2];
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2)
+      bv[c2] = *reinterpret_cast<const bf16x8*>(B + (wave * 32 + c2 * 16 + (lane & 15)) * BLD + kq);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + (r * 16 + (lane & 15)) * BLD + kq);
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[c2], acc[r][c2], 0, 0, 0);
+    }
+    if (c + 1 < nch) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  const int JK = a.J[K];
+  const int64_t g0 = a.rowoff[K];
+  const float alpha = static_cast<float>(a.coef[0]);
+  const float beta = static_cast<float>(a.coef[1]);
+  const float cc = static_cast<float>(a.coef[2]);
+  const uint16_t* prev = static_cast<const uint16_t*>(a.prev);
+  TOUT* out = static_cast<TOUT*>(a.out);
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int j = j0 + wave * 32 + c2 * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = r * 16 + 4 * (lane >> 4) + q;
+        if (i < JK && j < ns) {
+          const int64_t g = g0 + i;
+          float v = alpha * (acc[r][c2][q] - cc * bf2f(in[g * ldi + j]));
+          if (prev != nullptr) v -= beta * bf2f(prev[g * a.ldp + j]);
+          if constexpr (std::is_same<TOUT, double>::value)
+            out[g * a.ldo + j] = static_cast<double>(v);
+          else
+            out[g * a.ldo + j] = f2bf(v);
+        }
+      }
+    }
+}
+
+template <typename TOUT, int UNIFORM_RB>
+__global__ __launch_bounds__(NT) void step_kernel_bf16(StepArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2 * kMaxJ * BLD];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2 * TN * BLD];
+  __shared__ int32_t sK[7 * kMaxJ];
+  const int id = xcd_linear(blockIdx.x, gridDim.x);
+  const int ct = id / a.M;
+  const int e = id - ct * a.M;
+  const int K = a.order[e];
+  if constexpr (UNIFORM_RB > 0) {
+    step_body_bf16<TOUT, UNIFORM_RB>(a, K, ct, sA, sB, sK);
+  } else {
+    switch (a.rbv[K]) {
+      case 1: step_body_bf16<TOUT, 1>(a, K, ct, sA, sB, sK); break;
+      case 2: step_body_bf16<TOUT, 2>(a, K, ct, sA, sB, sK); break;
+      case 3: step_body_bf16<TOUT, 3>(a, K, ct, sA, sB, sK); break;
+      case 4: step_body_bf16<TOUT, 4>(a, K, ct, sA, sB, sK); break;
+      case 5: step_body_bf16<TOUT, 5>(a, K, ct, sA, sB, sK); break;
+      case 6: step_body_bf16<TOUT, 6>(a, K, ct, sA, sB, sK); break;
+      case 7: step_body_bf16<TOUT, 7>(a, K, ct, sA, sB, sK); break;
+      default: step_body_bf16<TOUT, 8>(a, K, ct, sA, sB, sK); break;
+    }
+  }
+}
+
+template <typename TOUT>
+int dispatch_step_bf16(const Plan& p, const StepArgs& a, int ns, hipStream_t st) {
+  const int64_t nwg = ceil_div(ns, TN) * p.M;
+  if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
+  dim3 grid(static_cast<unsigned>(nwg)), block(NT);
+  if (p.uniform) {
+    switch (p.maxRB) {
+      case 1: step_kernel_bf16<TOUT, 1><<<grid, block, 0, st>>>(a); break;
+      case 2: step_kernel_bf16<TOUT, 2><<<grid, block, 0, st>>>(a); break;
+      case 3: step_kernel_bf16<TOUT, 3><<<grid, block, 0, st>>>(a); break;
+      case 4: step_kernel_bf16<TOUT, 4><<<grid, block, 0, st>>>(a); break;
+      case 5: step_kernel_bf16<TOUT, 5><<<grid, block, 0, st>>>(a); break;
+      case 6: step_kernel_bf16<TOUT, 6><<<grid, block, 0, st>>>(a); break;
+      case 7: step_kernel_bf16<TOUT, 7><<<grid, block, 0, st>>>(a); break;
+      default: step_kernel_bf16<TOUT, 8><<<grid, block, 0, st>>>(a); break;
+    }
+  } else {
+    step_kernel_bf16<TOUT, 0><<<grid, block, 0, st>>>(a);
+  }
+  CHEFSI_LAUNCHED("cheb_step_bf16");
+  return CHEFSI_OK;
+}
+
 template <typename TC, typename TOUT, int EPI>
 int dispatch_step(const Plan& p, const StepArgs& a, int ns, hipStream_t st) {
   const int64_t nct = ceil_div(ns, TN);
@@ -411,9 +604,10 @@ template <typename T>
 __device__ __forceinline__ T cvt(double v) {
   return static_cast<T>(v);
 }
+// bf16 values are stored as raw 16-bit patterns (uint16_t)
 template <>
-__device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16>(double v) {
-  return __float2bfloat16(static_cast<float>(v));
+__device__ __forceinline__ uint16_t cvt<uint16_t>(double v) {
+  return f2bf(static_cast<float>(v));
 }
 
 template <typename T>
@@ -437,7 +631,16 @@ struct RepackArgs {
   bool transpose_h;
 };
 
-template <typename T>
+// CHUNKED (bf16 path): within each 32-row chunk of the element's reduction
+// rows the panel is stored row-of-H-major, [JP][32], so that one lane's eight
+// consecutive reduction rows are contiguous.
+template <typename T, bool CHUNKED>
+__device__ __forceinline__ int64_t panel_index(int k, int i, int JP) {
+  if constexpr (CHUNKED) return (static_cast<int64_t>(k >> 5) * JP + i) * 32 + (k & 31);
+  return static_cast<int64_t>(k) * JP + i;
+}
+
+template <typename T, bool CHUNKED>
 __global__ __launch_bounds__(256) void repack_kernel(RepackArgs ra, T* panel_base) {
   __shared__ double tile[32][33];
   const int blk = blockIdx.y;  // K * S + s
@@ -471,12 +674,12 @@ __global__ __launch_bounds__(256) void repack_kernel(RepackArgs ra, T* panel_bas
     // panel[pre + c][r] = tile[r][c]; write along r (panel columns) for coalescing
     for (int yy = ty; yy < 32; yy += 8) {
       const int c = tc * 32 + yy, r = tr * 32 + tx;
-      if (c < C && r < R) panel[static_cast<int64_t>(pre + c) * JP + r] = cvt<T>(tile[tx][yy]);
+      if (c < C && r < R) panel[panel_index<T, CHUNKED>(pre + c, r, JP)] = cvt<T>(tile[tx][yy]);
     }
   } else {
     for (int yy = ty; yy < 32; yy += 8) {
       const int r = tr * 32 + yy, c = tc * 32 + tx;
-      if (r < R && c < C) panel[static_cast<int64_t>(pre + r) * JP + c] = cvt<T>(tile[yy][tx]);
+      if (r < R && c < C) panel[panel_index<T, CHUNKED>(pre + r, c, JP)] = cvt<T>(tile[yy][tx]);
     }
   }
 }
@@ -554,10 +757,13 @@ int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h,
   dim3 grid(tiles, p.M * p.stencil);
   if (dtype == CHEFSI_F64) {
     fill_kernel<double><<<fill_grid, 256, 0, st>>>(static_cast<double*>(d_panel), p.panel_elems);
-    repack_kernel<double><<<grid, 256, 0, st>>>(ra, static_cast<double*>(d_panel));
+    repack_kernel<double, false><<<grid, 256, 0, st>>>(ra, static_cast<double*>(d_panel));
   } else if (dtype == CHEFSI_F32) {
     fill_kernel<float><<<fill_grid, 256, 0, st>>>(static_cast<float*>(d_panel), p.panel_elems);
-    repack_kernel<float><<<grid, 256, 0, st>>>(ra, static_cast<float*>(d_panel));
+    repack_kernel<float, false><<<grid, 256, 0, st>>>(ra, static_cast<float*>(d_panel));
+  } else if (dtype == CHEFSI_BF16) {
+    fill_kernel<uint16_t><<<fill_grid, 256, 0, st>>>(static_cast<uint16_t*>(d_panel), p.panel_elems);
+    repack_kernel<uint16_t, true><<<grid, 256, 0, st>>>(ra, static_cast<uint16_t*>(d_panel));
   } else {
     return fail(CHEFSI_ERR_UNSUPPORTED, "repack: dtype");
   }
@@ -587,6 +793,14 @@ int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_c
     if (io.out_f64) return dispatch_step<float, double, 0>(p, a, ns, st);
     return dispatch_step<float, float, 0>(p, a, ns, st);
   }
+  if (dtype == CHEFSI_BF16) {
+    if (io.in_f64 || (io.prev && io.prev_f64))
+      return fail(CHEFSI_ERR_ARG, "step: BF16 step needs BF16 inputs");
+    if ((io.ldi % 8) != 0 || (reinterpret_cast<uintptr_t>(io.in) & 15u) != 0)
+      return fail(CHEFSI_ERR_ARG, "step: BF16 input rows must be 16-byte aligned");
+    if (io.out_f64) return dispatch_step_bf16<double>(p, a, ns, st);
+    return dispatch_step_bf16<uint16_t>(p, a, ns, st);
+  }
   return fail(CHEFSI_ERR_UNSUPPORTED, "step: dtype");
 }
 
@@ -615,6 +829,8 @@ int launch_convert(const double* src, int64_t lds, void* dst, int dst_dtype, int
     convert_kernel<double, double><<<g, 256, 0, st>>>(src, lds, static_cast<double*>(dst), ldd, n, ns);
   else if (dst_dtype == CHEFSI_F32)
     convert_kernel<double, float><<<g, 256, 0, st>>>(src, lds, static_cast<float*>(dst), ldd, n, ns);
+  else if (dst_dtype == CHEFSI_BF16)
+    convert_kernel<double, uint16_t><<<g, 256, 0, st>>>(src, lds, static_cast<uint16_t*>(dst), ldd, n, ns);
   else
     return fail(CHEFSI_ERR_UNSUPPORTED, "convert: dtype");
   CHEFSI_LAUNCHED("convert");

@@ -106,6 +106,24 @@ def test_filter_f32_error_is_small(lib):
     assert 1e-9 < err <= 1e-4
 
 
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("ns,m", [(64, 10), (1, 3), (130, 7), (257, 2), (9, 1)])
+def test_filter_bf16_error_is_small(lib, name, ns, m):
+    """BF16 storage of H and of the recurrence, FP32 accumulation: the error
+    against the FP64 oracle is that of 8-bit mantissas (loose bound), and far
+    above FP64 rounding (so the low-precision kernel really ran)."""
+    P = PROBLEMS[name]()
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    X = synth.make_start_block(P.J, ns)
+    a, b, a0 = 0.3, 5.5, -1.2
+    ref = oracle.chebyshev_filter(oracle.DenseOperator(H), X, m, a, b, a0)
+    plan = mkplan(lib, P)
+    Y = plan.filter(dev(P.packed()), dev(X), m, a, b, a0, dtype=lib.BF16)
+    err = relf(host(Y), ref)
+    print(f"BF16 filter relative error vs FP64 oracle ({name}, ns={ns}, m={m}): {err:.3e}")
+    assert 1e-6 < err <= 3e-2
+
+
 def test_filter_rejects_bad_arguments(lib):
     P = synth.make_problem(synth.TINY)
     plan = mkplan(lib, P)
@@ -235,7 +253,8 @@ def test_sweep_own_policy_converges_like_oracle(lib):
     assert ritz_rel(host(ritz), th_o, 6.0) <= 1e-10
 
 
-def test_sweep_f32_filter_then_f64_finish(lib):
+@pytest.mark.parametrize("low", ["F32", "BF16"])
+def test_sweep_low_precision_filter_then_f64_finish(lib, low):
     w = synth.TINY
     P = synth.make_problem(w)
     H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
@@ -244,7 +263,7 @@ def test_sweep_f32_filter_then_f64_finish(lib):
     Hd, X, v0d = dev(P.packed()), dev(synth.make_start_block(P.J, w.ns)), dev(synth.make_lanczos_start(P.N))
     ritz = None
     for i in range(6):
-        dt = lib.F32 if i < 3 else lib.F64
+        dt = getattr(lib, low) if i < 3 else lib.F64
         ritz, resid, _, _ = plan.sweep(Hd, X, w.m, dtype=dt, v0=v0d, ritz=ritz, warm=i > 0)
     k = 3 * w.ns // 4
     assert np.max(np.abs(host(ritz)[:k] - lam[:k])) <= 1e-9 * 6
