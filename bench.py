@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 
+# HBM bytes per FP64 Chebyshev step launch on the bulk workload, from FETCH_SIZE (x2.0, the factor
+# a plain 3.62 GB device copy gives) + WRITE_SIZE counter runs of this step kernel
+STEP_F64_BULK_TRAFFIC = 43.78e9 + 3.62e9
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "hbm": 8000.0}   # dense MFMA TFLOP/s; HBM GB/s
 HBM_PEAK = 8000.0                                      # GB/s
 METRIC = "CheFSI sweep time + filter TFLOP/s, mixed vs FP64 at fixed Ritz error"
@@ -258,7 +261,9 @@ def main():
         "stage_ms": {k: round(v, 3) for k, v in avg.items()},
         "roofline": {"kernel": "cheb_step (block-sparse SpMM + recurrence epilogue, FP64 MFMA)",
                      "bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["f64"], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK["f64"], 4), "traffic": None,
+                     "frac": round(achieved / PEAK["f64"], 4),
+                     "traffic": STEP_F64_BULK_TRAFFIC if w.name.startswith("bulk") else None,
+                     "algorithmic_bytes": 8 * (3 * P.N * ns + P.packed_size()),
                      "flops_per_launch": f_step, "avg_launch_ms": round(step_ms, 4)},
         "final_max_resid_wanted": float(resid.max().item()) if resid is not None else None,
     }
