@@ -177,7 +177,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="bulk", choices=["tiny", "diff", "bulk"])
+    ap.add_argument("--workload", default="bulk", choices=["tiny", "diff", "bulk", "sheet"])
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -195,7 +195,7 @@ def main():
     import torch
     import paper_1606_03416_amd as chefsi
 
-    w = {"tiny": synth.TINY, "diff": synth.DIFF, "bulk": synth.BULK}[args.workload]
+    w = {"tiny": synth.TINY, "diff": synth.DIFF, "bulk": synth.BULK, "sheet": synth.SHEET}[args.workload]
     log(f"workload {w.name}: generating inputs")
     P = synth.make_problem(w)
     X0 = synth.make_start_block(P.J, w.ns)

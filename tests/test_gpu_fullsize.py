@@ -1,0 +1,136 @@
+"""Full-size GPU checks on the bulk (12x12x12 elements, 64 ALBs, N_s = 4,096,
+m = 16) and sheet (48x40x1 elements, 5-block stencil, ALB counts drawn from
+{64, 72, ..., 128}, N_s = 8,192, m = 20) workloads, in the launch configuration
+the benchmark times (whole multivector, CholeskyQR2, 20 Lanczos steps).
+
+The oracle cannot filter or diagonalise at these sizes, so the checks are:
+* the filter is column-separable, so sampled columns of the GPU result are
+  compared with the block-mode oracle filter of the same columns of X;
+* after a sweep, properties that hold at any size: orthonormality of X, the
+  Ritz values equal the Rayleigh quotients x_i^T H x_i of the returned vectors
+  (recomputed by the oracle's block operator on sampled columns), the reported
+  residuals equal ||H x_i - theta_i x_i||, and the Ritz values ascend."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SAMPLE_SEED = 88
+
+
+def sample_columns(ns, count=6):
+    g = np.random.default_rng(SAMPLE_SEED)
+    cols = set(g.choice(ns, size=count, replace=False).tolist()) | {0, ns - 1}
+    return np.array(sorted(cols))
+
+
+def relf(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module", params=["bulk", "sheet"])
+def case(request, lib):
+    w = {"bulk": synth.BULK, "sheet": synth.SHEET}[request.param]
+    P = synth.make_problem(w)
+    X0 = synth.make_start_block(P.J, w.ns)
+    v0 = synth.make_lanczos_start(P.N)
+    plan = lib.Plan(P.grid, P.stencil, P.J)
+    dev = torch.device("cuda", 0)
+    H = torch.from_numpy(P.packed()).to(dev)
+    ws = torch.empty(max(plan.workspace_bytes(lib.OP_SWEEP, w.ns, dt, 2, w.lanczos_steps)
+                         for dt in (lib.F64, lib.F32)), dtype=torch.uint8, device=dev)
+    bop = oracle.BlockOperator(P.grid, P.stencil, P.J, P.blocks)
+    print(f"\n[{w.name}] N={P.N} ns={w.ns} m={w.m}", flush=True)
+    yield w, P, X0, v0, plan, H, ws, bop
+    del H, ws
+    torch.cuda.empty_cache()
+
+
+def test_filter_sampled_columns_match_oracle(case, lib):
+    w, P, X0, v0, plan, H, ws, bop = case
+    a, b, a0 = 0.5, 7.0, -1.5
+    Xd = torch.from_numpy(X0).cuda()
+    Y = plan.filter(H, Xd, w.m, a, b, a0)
+    cols = sample_columns(w.ns)
+    Yc = Y[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    ref = oracle.chebyshev_filter(bop, X0[:, cols], w.m, a, b, a0)
+    err = relf(Yc, ref)
+    print(f"[{w.name}] FP64 filter, {len(cols)} sampled columns: rel Frobenius error {err:.3e}")
+    assert err <= 1e-12
+    Y32 = plan.filter(H, Xd, w.m, a, b, a0, dtype=lib.F32)
+    err32 = relf(Y32[:, torch.from_numpy(cols).cuda()].cpu().numpy(), ref)
+    print(f"[{w.name}] FP32 filter, same columns: rel error {err32:.3e}")
+    assert err32 <= 1e-4
+    del Y, Y32, Xd
+
+
+def rayleigh_checks(name, P, bop, X, ritz, resid, s):
+    ns = X.shape[1]
+    G = X.T @ X
+    G.diagonal().sub_(1.0)
+    orth = float(torch.linalg.eigvalsh(G).abs().max().item())
+    print(f"[{name}] ||X^T X - I||_2 = {orth:.3e}")
+    assert orth <= 1e-12
+    del G
+    th = ritz.cpu().numpy()
+    assert np.all(np.isfinite(th)) and np.all(np.diff(th) >= 0)
+    cols = sample_columns(ns)
+    Xc = X[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    HX = bop.apply(Xc)
+    rq = np.einsum("ij,ij->j", Xc, HX) / np.einsum("ij,ij->j", Xc, Xc)
+    rel = np.max(np.abs(rq - th[cols]) / np.maximum(np.abs(th[cols]), s))
+    print(f"[{name}] sampled Rayleigh quotients vs Ritz values: max rel {rel:.3e}")
+    assert rel <= 1e-10
+    r_o = np.linalg.norm(HX - Xc * th[cols], axis=0)
+    r_g = resid.cpu().numpy()[cols]
+    dr = np.max(np.abs(r_o - r_g))
+    print(f"[{name}] sampled residual norms: max abs difference {dr:.3e} (largest {r_o.max():.3e})")
+    assert dr <= 1e-10 * s
+
+
+def test_sweeps_full_size_properties(case, lib):
+    """Two FP64 sweeps (cold bounds, then warm), as the benchmark runs them."""
+    w, P, X0, v0, plan, H, ws, bop = case
+    X = torch.from_numpy(X0).cuda()
+    v0d = torch.from_numpy(v0).cuda()
+    ritz = None
+    for i in range(2):
+        ritz, resid, bnd, _ = plan.sweep(H, X, w.m, passes=2, lanczos_steps=w.lanczos_steps, v0=v0d,
+                                         ritz=ritz, warm=i > 0, ws=ws)
+    bh = bnd.cpu().numpy()
+    s = float(max(abs(bh[1]), abs(bh[2])))
+    assert bh[2] < bh[0] < bh[1]
+    rayleigh_checks(w.name, P, bop, X, ritz, resid, s)
+    del X
+
+
+def test_mixed_sweeps_reach_the_fp64_ritz_error(case, lib):
+    """Two FP32-filter sweeps then two FP64 sweeps from the same start as four
+    FP64 sweeps: the wanted (lowest 3/4) Ritz values agree and the mixed run's
+    worst wanted residual is that of the FP64 run (5 % slack)."""
+    w, P, X0, v0, plan, H, ws, bop = case
+    v0d = torch.from_numpy(v0).cuda()
+    k = 3 * w.ns // 4
+    out = {}
+    for label, dts in (("f64", [lib.F64] * 4), ("mixed", [lib.F32] * 2 + [lib.F64] * 2)):
+        X = torch.from_numpy(X0).cuda()
+        ritz = None
+        for i, dt in enumerate(dts):
+            ritz, resid, bnd, _ = plan.sweep(H, X, w.m, dtype=dt, passes=2, lanczos_steps=w.lanczos_steps,
+                                             v0=v0d, ritz=ritz, warm=i > 0, ws=ws)
+        out[label] = (ritz.cpu().numpy(), float(resid[:k].max().item()), bnd.cpu().numpy())
+        if label == "mixed":
+            s = float(max(abs(out[label][2][1]), abs(out[label][2][2])))
+            rayleigh_checks(w.name + " mixed", P, bop, X, ritz, resid, s)
+        del X
+    (t64, r64, b64), (tmx, rmx, _) = out["f64"], out["mixed"]
+    s = float(max(abs(b64[1]), abs(b64[2])))
+    dth = np.max(np.abs(tmx[:k] - t64[:k]) / np.maximum(np.abs(t64[:k]), s))
+    print(f"[{w.name}] max wanted residual: FP64 {r64:.3e}, mixed {rmx:.3e}; Ritz rel diff {dth:.3e}")
+    assert rmx <= 1.05 * r64
+    assert dth <= 1e-8
