@@ -60,9 +60,6 @@ size_t mv_bytes(int64_t n, int64_t ld, int ns, size_t elt) {
 
 int elt_size(int dtype) { return dtype == CHEFSI_F64 ? 8 : (dtype == CHEFSI_F32 ? 4 : 2); }
 
-// leading dimension of the internal BF16 recurrence buffers (16-byte rows)
-int64_t lowp_ld(int ns) { return round_up(ns, 8); }
-
 bool valid_dtype(int dtype) { return dtype == CHEFSI_F64 || dtype == CHEFSI_F32 || dtype == CHEFSI_BF16; }
 
 // ------------------------------------------------------------ workspace layouts
@@ -79,13 +76,14 @@ void carve_filter(Carver& c, const Plan& p, int ns, int dtype, bool need_panel, 
   const int e = elt_size(dtype);
   f.coef = c.take<double>(3 * static_cast<int64_t>(kMaxDegree));
   f.bounds = c.take<double>(4);
-  f.panel = need_panel ? c.take<char>(p.panel_elems * e) : nullptr;
+  const int64_t pe = (dtype == CHEFSI_BF16) ? p.panel8_elems : p.panel_elems;
+  f.panel = need_panel ? c.take<char>(pe * e) : nullptr;
   const int64_t mv = p.N * static_cast<int64_t>(ns);
   if (dtype == CHEFSI_F64) {
     f.buf0 = c.take<double>(mv);
     f.buf1 = f.buf2 = nullptr;
   } else if (dtype == CHEFSI_BF16) {
-    const int64_t mvp = p.N * lowp_ld(ns);
+    const int64_t mvp = p.N8 * static_cast<int64_t>(ns);
     f.buf0 = c.take<char>(mvp * e);
     f.buf1 = c.take<char>(mvp * e);
     f.buf2 = c.take<char>(mvp * e);
@@ -183,20 +181,30 @@ int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, 
   }
   // low precision: X converted once, Y_1..Y_{m-1} in two rotating buffers,
   // Y_m written in FP64.
-  const int64_t ldl = (dtype == CHEFSI_BF16) ? lowp_ld(ns) : ns;
-  CHEFSI_TRY(launch_convert(X, ldx, f.buf0, dtype, ldl, p.N, ns, st));
   void* L[2] = {f.buf1, f.buf2};
+  if (dtype == CHEFSI_BF16) {
+    CHEFSI_TRY(launch_to_tiles_b16(p, X, ldx, f.buf0, ns, st));
+    for (int k = 0; k < m; ++k) {
+      const bool last = (k == m - 1);
+      const void* in = (k == 0) ? f.buf0 : L[k % 2];
+      const void* prev = (k == 0) ? nullptr : (k == 1 ? f.buf0 : L[(k - 1) % 2]);
+      void* out = last ? static_cast<void*>(Y) : L[(k + 1) % 2];
+      CHEFSI_TRY(launch_step_b16(p, panel, coef + 3 * k, in, prev, out, last, ldy, ns, st));
+    }
+    return CHEFSI_OK;
+  }
+  CHEFSI_TRY(launch_convert(X, ldx, f.buf0, dtype, ns, p.N, ns, st));
   for (int k = 0; k < m; ++k) {
     StepIO io{};
     io.in = (k == 0) ? f.buf0 : L[k % 2];
-    io.ldi = ldl;
+    io.ldi = ns;
     io.in_f64 = false;
     io.prev = (k == 0) ? nullptr : (k == 1 ? f.buf0 : L[(k - 1) % 2]);
-    io.ldp = ldl;
+    io.ldp = ns;
     io.prev_f64 = false;
     const bool last = (k == m - 1);
     io.out = last ? static_cast<void*>(Y) : L[(k + 1) % 2];
-    io.ldo = last ? ldy : ldl;
+    io.ldo = last ? ldy : ns;
     io.out_f64 = last;
     CHEFSI_TRY(launch_step(p, panel, dtype, coef + 3 * k, io, ns, st));
   }
@@ -528,7 +536,7 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
         kt += p->J[Kp];
       }
       p->ktot[K] = kt;
-      p->kpad[K] = static_cast<int32_t>(round_up(kt, kPadK));
+      p->kpad[K] = static_cast<int32_t>(round_up(kt, kStepKC));
       p->rb[K] = static_cast<int32_t>(ceil_div(p->J[K], 16));
       p->poff[K] = po;
       po += static_cast<int64_t>(p->kpad[K]) * p->rb[K] * 16;
@@ -548,6 +556,40 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
         const int Kp = p->nbr[static_cast<size_t>(K) * S + s];
         for (int r = 0; r < p->J[Kp]; ++r) kmap[p->koff[K] + k++] = static_cast<int32_t>(p->rowoff[Kp] + r);
       }
+    }
+    // BF16 layout: element rows padded to multiples of 8
+    p->rowoff8.assign(M + 1, 0);
+    for (int K = 0; K < M; ++K) p->rowoff8[K + 1] = p->rowoff8[K] + round_up(p->J[K], 8);
+    p->N8 = p->rowoff8[M];
+    p->kpad8.assign(M, 0);
+    p->poff8.assign(M, 0);
+    p->kgoff.assign(M, 0);
+    int64_t po8 = 0, kg = 0;
+    for (int K = 0; K < M; ++K) {
+      int kt8 = 0;
+      for (int s = 0; s < S; ++s) kt8 += static_cast<int>(round_up(p->J[p->nbr[static_cast<size_t>(K) * S + s]], 8));
+      p->kpad8[K] = static_cast<int32_t>(round_up(kt8, kPadK));
+      p->poff8[K] = po8;
+      po8 += static_cast<int64_t>(p->kpad8[K]) * p->rb[K] * 16;
+      p->kgoff[K] = kg;
+      kg += p->kpad8[K] / 8;
+    }
+    p->panel8_elems = po8;
+    std::vector<int32_t> kg8(static_cast<size_t>(kg), -1);
+    for (int K = 0; K < M; ++K) {
+      int64_t g = p->kgoff[K];
+      for (int s = 0; s < S; ++s) {
+        const int Kp = p->nbr[static_cast<size_t>(K) * S + s];
+        const int J8 = static_cast<int>(round_up(p->J[Kp], 8));
+        for (int r = 0; r < J8; r += 8) kg8[g++] = static_cast<int32_t>((p->rowoff8[Kp] + r) / 8);
+      }
+    }
+    std::vector<int32_t> rowsrc8(static_cast<size_t>(p->N8), -1);
+    for (int K = 0; K < M; ++K)
+      for (int i = 0; i < p->J[K]; ++i) rowsrc8[p->rowoff8[K] + i] = static_cast<int32_t>(p->rowoff[K] + i);
+    if (p->N8 > 0x7fffffff) {
+      delete p;
+      return fail(CHEFSI_ERR_ARG, "plan_create: too many rows");
     }
     // heaviest work-groups first (uniform plans keep the natural order)
     std::vector<int32_t> order(M);
@@ -580,6 +622,12 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
     rc |= up(&p->d_poff, p->poff);
     rc |= up(&p->d_koff, p->koff);
     rc |= up(&p->d_kmap, kmap);
+    rc |= up(&p->d_rowoff8, p->rowoff8);
+    rc |= up(&p->d_poff8, p->poff8);
+    rc |= up(&p->d_kpad8, p->kpad8);
+    rc |= up(&p->d_kgoff, p->kgoff);
+    rc |= up(&p->d_kg8, kg8);
+    rc |= up(&p->d_rowsrc8, rowsrc8);
     if (rc != CHEFSI_OK) {
       chefsi_plan_destroy(reinterpret_cast<chefsi_plan>(p));
       return fail(CHEFSI_ERR_HIP, "plan_create: device table upload failed");
@@ -593,7 +641,8 @@ void chefsi_plan_destroy(chefsi_plan plan) {
   if (plan == nullptr) return;
   Plan* p = P(plan);
   void* ptrs[] = {p->d_J, p->d_nbr, p->d_rb, p->d_kpad, p->d_order, p->d_rowoff,
-                  p->d_hoff, p->d_poff, p->d_koff, p->d_kmap, p->d_kslot};
+                  p->d_hoff, p->d_poff, p->d_koff, p->d_kmap, p->d_kslot, p->d_rowoff8,
+                  p->d_poff8, p->d_kpad8, p->d_kgoff, p->d_kg8, p->d_rowsrc8};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   destroy_eig_handle(*p);
@@ -719,9 +768,10 @@ int chefsi_filter(chefsi_plan plan, const double* d_H, int m, double a, double b
     Carver c(ws, ws_bytes);
     FilterWs f;
     carve_filter(c, p, ns, dtype, true, f);
-    CHEFSI_TRY(launch_repack(p, d_H, dtype, false, f.panel, st));
     CHEFSI_TRY(launch_set_bounds(a, b, a0, f.bounds, st));
     CHEFSI_TRY(launch_cheb_coef(f.bounds, m, f.coef, st));
+    if (m > 0)
+      CHEFSI_TRY(launch_repack(p, d_H, dtype, false, f.panel, st, dtype == CHEFSI_BF16 ? f.coef + 2 : nullptr));
     return run_filter(p, f.panel, dtype, f.coef, m, d_X, ldx, d_Y, ldy, ns, f, st);
   });
 }
@@ -842,11 +892,12 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         FilterWs f;
         carve_filter(cf, p, ns, filter_dtype, filter_dtype != CHEFSI_F64, f);
         const void* fpanel = panel64;
-        if (filter_dtype != CHEFSI_F64) {
-          CHEFSI_TRY(launch_repack(p, d_H, filter_dtype, false, f.panel, st));
+        CHEFSI_TRY(launch_cheb_coef(bnd, m, f.coef, st));
+        if (filter_dtype != CHEFSI_F64 && m > 0) {
+          CHEFSI_TRY(launch_repack(p, d_H, filter_dtype, false, f.panel, st,
+                                   filter_dtype == CHEFSI_BF16 ? f.coef + 2 : nullptr));
           fpanel = f.panel;
         }
-        CHEFSI_TRY(launch_cheb_coef(bnd, m, f.coef, st));
         CHEFSI_TRY(mark(2));
         CHEFSI_TRY(run_filter(p, fpanel, filter_dtype, f.coef, m, d_X, ldx, Y, ns, ns, f, st));
       }

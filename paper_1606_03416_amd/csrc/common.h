@@ -71,6 +71,19 @@ struct Plan {
   int64_t* d_koff = nullptr;    // [M] kmap offsets
   int32_t* d_kmap = nullptr;    // [sum kpad] global row of each reduction row (-1 pad)
   int32_t* d_kslot = nullptr;   // [sum kpad] (slot << 8 | row-in-slot) of each reduction row
+  // BF16 filter: multivectors in 8-row tiles whose element row ranges are
+  // padded to multiples of 8 (zero rows), so every 8 consecutive reduction
+  // rows of a neighbour segment are one tile, contiguous per state.
+  int64_t N8 = 0;               // padded row count (state stride)
+  int64_t panel8_elems = 0;     // BF16 panel size (elements)
+  std::vector<int64_t> rowoff8, poff8, kgoff;
+  std::vector<int32_t> kpad8;
+  int64_t* d_rowoff8 = nullptr; // [M+1] padded row offsets
+  int64_t* d_poff8 = nullptr;   // [M] BF16 panel offsets
+  int32_t* d_kpad8 = nullptr;   // [M] padded reduction rows, multiple of kPadK
+  int64_t* d_kgoff = nullptr;   // [M] offsets into d_kg8
+  int32_t* d_kg8 = nullptr;     // [sum kpad8/8] 8-row tile of each reduction-row group (-1 pad)
+  int32_t* d_rowsrc8 = nullptr; // [N8] source row of each padded row (-1 padding)
   void* rocblas = nullptr;      // rocblas_handle for the dense eigensolver
   size_t eig_ws_cache_n = 0, eig_ws_cache_bytes = 0;
 };
@@ -103,8 +116,11 @@ int launch_const_coef3(double alpha, double beta, double c, double* d_coef, hipS
 
 // Repack H (block-list, fp64) into per-element transposed panels of type dtype.
 // transpose_h = true packs H^T (uses the opposite slot of each neighbour).
+// BF16 panels use the 8-padded reduction rows and 32-row chunks (panel8_elems).
+// d_shift (device, may be null) is subtracted from the diagonal of the self
+// block; used for BF16 panels, which carry H - cI.
 int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h, void* d_panel,
-                  hipStream_t st);
+                  hipStream_t st, const double* d_shift = nullptr);
 
 // One Chebyshev step / SpMM: out = alpha_k (H*in - c*in) - beta_k*prev on all
 // element rows, columns [0, ns). coef points at (alpha, beta, c) of this step.
@@ -117,6 +133,14 @@ struct StepIO {
 };
 int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_coef,
                 const StepIO& io, int ns, hipStream_t st);
+// BF16 step on 8-row-tiled buffers (rows padded per element to multiples of
+// 8; element (row, state j) at ((row/8)*ns + j)*8 + row%8), with a panel that
+// carries H - cI: out = alpha*(panel*in) - beta*prev.  in/prev bf16; out bf16
+// tiled, or float64 row-major (ldo) when out_f64.
+int launch_step_b16(const Plan& p, const void* d_panel8, const double* d_coef, const void* in, const void* prev,
+                    void* out, bool out_f64, int64_t ldo, int ns, hipStream_t st);
+// float64 row-major X (ldx) -> bf16 8-row tiles with zero padding rows.
+int launch_to_tiles_b16(const Plan& p, const double* X, int64_t ldx, void* out, int ns, hipStream_t st);
 // Residual partials: part[K*ns + j] = sum_{i in K} (H x_j - theta_j x_j)_i^2 (fp64).
 int launch_resid_partial(const Plan& p, const void* d_panel, const double* d_X, int64_t ldx,
                          const double* d_theta, int ns, double* d_part, hipStream_t st);

@@ -323,185 +323,216 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 // ---------------------------------------------------------------- BF16 path
 // BF16 storage and MFMA operands (v_mfma_f32_16x16x32_bf16), FP32
 // accumulation and epilogue.  Lane l supplies A[l%16][8(l/16)..+7] and
-// B[8(l/16)..+7][l%16] and receives D[4(l/16)+q][l%16], q = 0..3.  One MFMA
-// k-step covers a whole 32-row chunk; the gathered X rows are transposed on
-// their way into LDS so that each lane's eight reduction rows are contiguous.
+// B[8(l/16)..+7][l%16] and receives D[4(l/16)+q][l%16], q = 0..3.
+//
+// The recurrence is kept in 8-row tiles: rows padded per element to multiples
+// of 8, and tile G stores its 8 rows state by state, element (G, j, e) at
+// (G*ns + j)*8 + e.  Each element's panel is stored in 32-row chunks [JP][32],
+// with -c folded into the diagonal of the self block, so the step is
+// out = alpha*acc - beta*prev.  Both MFMA operands are single 16-byte loads
+// straight from memory (a lane's eight reduction rows of one neighbour are
+// contiguous, and 16 consecutive states are 256 contiguous bytes).  No LDS
+// staging and no barriers in the main loop; each wave computes all of the
+// element's rows for 16*BNC columns, and the four waves of a work-group share
+// the element's panel through L1.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int KB = kPadK;     // reduction rows per chunk
-constexpr int BLD = KB + 8;   // LDS row length (bf16 units), 16-byte aligned rows
+constexpr int BNC = 4;                 // 16-column fragments per wave
+constexpr int BTN = (NT / 64) * 16 * BNC;  // columns per work-group
 
-template <typename TOUT, int RB>
-__device__ __forceinline__ void step_body_bf16(const StepArgs& a, int K, int ct, uint16_t* sA, uint16_t* sB,
-                                               int32_t* sK) {
+struct StepArgsB {
+  const uint16_t* panel;
+  const int64_t* poff8;
+  const int32_t* kpad8;
+  const int64_t* kgoff;
+  const int32_t* kg8;    // 8-row tile index of each reduction-row group (-1 pad)
+  const int32_t* J;
+  const int32_t* rbv;
+  const int64_t* rowoff8;
+  const int64_t* rowoff;
+  const int32_t* order;
+  const double* coef;
+  const uint16_t* in;
+  const uint16_t* prev;
+  void* out;
+  int64_t ldo;   // row stride of a float64 row-major output
+  int ns;
+  int M;
+};
+
+template <bool F64OUT, int RB>
+__device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct, int32_t* sG) {
   constexpr int JP = RB * 16;
-  constexpr int AV = (JP * KB / 8 + NT - 1) / NT;   // 16-byte vectors of A per thread per chunk
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ns = a.ns;
-  const int j0 = ct * TN;
+  const int q = lane >> 4, l16 = lane & 15;
+  const int ngrp = a.kpad8[K] >> 3;
   {
-    const int32_t* km = a.kmap + a.koff[K];
-    const int kp = a.kpad[K];
-    for (int t = tid; t < kp; t += NT) sK[t] = km[t];
+    const int32_t* kg = a.kg8 + a.kgoff[K];
+    for (int t = tid; t < ngrp; t += NT) sG[t] = kg[t];
   }
-  const int nch = a.kpad[K] / KB;
-  const uint16_t* panel = static_cast<const uint16_t*>(a.panel) + a.poff[K];
-  const uint16_t* in = static_cast<const uint16_t*>(a.in);
-  const int64_t ldi = a.ldi;
-  const int rp = tid >> 4;          // row pair of the chunk (rows 2rp, 2rp+1)
-  const int cg = (tid & 15) * 8;    // first of this thread's 8 columns
   __syncthreads();
-
-  uint4 ra[AV];
-  uint4 rb[2];
-  auto gload = [&](int c) {
-    const uint4* pa = reinterpret_cast<const uint4*>(panel + static_cast<int64_t>(c) * JP * KB);
+  const int nch = ngrp >> 2;
+  const int ns = a.ns;
+  const int jb = ct * BTN + wave * (16 * BNC) + l16;
+  const uint16_t* pa = a.panel + a.poff8[K] + l16 * 32 + 8 * q;
+  const uint16_t* pb[BNC];
+  bool vb[BNC];
 #pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int idx = tid + NT * v;
-      if (idx < JP * KB / 8) ra[v] = pa[idx];
-    }
-#pragma unroll
-    for (int r2 = 0; r2 < 2; ++r2) {
-      const int g = sK[c * KB + 2 * rp + r2];
-      const int col = j0 + cg;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (g >= 0) {
-        const uint16_t* src = in + static_cast<int64_t>(g) * ldi + col;
-        if (col + 8 <= ns) {
-          v = *reinterpret_cast<const uint4*>(src);
-        } else if (col < ns) {
-          uint16_t t[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) t[e] = (col + e < ns) ? src[e] : static_cast<uint16_t>(0);
-          v = make_uint4(t[0] | (static_cast<uint32_t>(t[1]) << 16), t[2] | (static_cast<uint32_t>(t[3]) << 16),
-                         t[4] | (static_cast<uint32_t>(t[5]) << 16), t[6] | (static_cast<uint32_t>(t[7]) << 16));
-        }
-      }
-      rb[r2] = v;
-    }
-  };
-  auto sstore = [&](int buf) {
-    uint16_t* A = sA + buf * (kMaxJ * BLD);
-    uint16_t* B = sB + buf * (TN * BLD);
-#pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int idx = tid + NT * v;
-      if (idx < JP * KB / 8) *reinterpret_cast<uint4*>(A + (idx >> 2) * BLD + (idx & 3) * 8) = ra[v];
-    }
-    const uint32_t lo[4] = {rb[0].x, rb[0].y, rb[0].z, rb[0].w};
-    const uint32_t hi[4] = {rb[1].x, rb[1].y, rb[1].z, rb[1].w};
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint32_t x0 = (lo[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-      const uint32_t x1 = (hi[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-      *reinterpret_cast<uint32_t*>(B + (cg + e) * BLD + 2 * rp) = x0 | (x1 << 16);
-    }
-  };
-
-  f32x4 acc[RB][2];
-#pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    acc[r][0] = f32x4{0, 0, 0, 0};
-    acc[r][1] = f32x4{0, 0, 0, 0};
+  for (int n = 0; n < BNC; ++n) {
+    const int j = jb + 16 * n;
+    vb[n] = j < ns;
+    pb[n] = a.in + static_cast<int64_t>(vb[n] ? j : 0) * 8;
   }
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) gload(c + 1);
-    const uint16_t* A = sA + buf * (kMaxJ * BLD);
-    const uint16_t* B = sB + buf * (TN * BLD);
-    const int kq = 8 * (lane >> 4);
-    bf16x8 bv[2];
-#pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2)
-      bv[c2] = *reinterpret_cast<const bf16x8*>(B + (wave * 32 + c2 * 16 + (lane & 15)) * BLD + kq);
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + (r * 16 + (lane & 15)) * BLD + kq);
-#pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[c2], acc[r][c2], 0, 0, 0);
-    }
-    if (c + 1 < nch) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  const int JK = a.J[K];
-  const int64_t g0 = a.rowoff[K];
-  const float alpha = static_cast<float>(a.coef[0]);
-  const float beta = static_cast<float>(a.coef[1]);
-  const float cc = static_cast<float>(a.coef[2]);
-  const uint16_t* prev = static_cast<const uint16_t*>(a.prev);
-  TOUT* out = static_cast<TOUT*>(a.out);
+  const int64_t tstride = static_cast<int64_t>(ns) * 8;   // elements per 8-row tile
+  f32x4 acc[RB][BNC];
 #pragma unroll
   for (int r = 0; r < RB; ++r)
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-      const int j = j0 + wave * 32 + c2 * 16 + (lane & 15);
+    for (int n = 0; n < BNC; ++n) acc[r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto load = [&](int c, bf16x8* A, bf16x8* B) {
+    const uint16_t* p = pa + static_cast<int64_t>(c) * (JP * 32);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = r * 16 + 4 * (lane >> 4) + q;
-        if (i < JK && j < ns) {
-          const int64_t g = g0 + i;
-          float v = alpha * (acc[r][c2][q] - cc * bf2f(in[g * ldi + j]));
-          if (prev != nullptr) v -= beta * bf2f(prev[g * a.ldp + j]);
-          if constexpr (std::is_same<TOUT, double>::value)
-            out[g * a.ldo + j] = static_cast<double>(v);
-          else
-            out[g * a.ldo + j] = f2bf(v);
-        }
+    for (int r = 0; r < RB; ++r) A[r] = *reinterpret_cast<const bf16x8*>(p + r * (16 * 32));
+    const int G = sG[c * 4 + q];
+    const int64_t go = static_cast<int64_t>(G) * tstride;
+#pragma unroll
+    for (int n = 0; n < BNC; ++n) {
+      bf16x8 v = {};
+      if (vb[n] && G >= 0) v = *reinterpret_cast<const bf16x8*>(pb[n] + go);
+      B[n] = v;
+    }
+  };
+  auto mma = [&](const bf16x8* A, const bf16x8* B) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int n = 0; n < BNC; ++n) acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], B[n], acc[r][n], 0, 0, 0);
+  };
+  bf16x8 A0[RB], B0[BNC], A1[RB], B1[BNC];
+  load(0, A0, B0);
+  int c = 0;
+  for (; c + 2 <= nch; c += 2) {
+    load(c + 1, A1, B1);
+    mma(A0, B0);
+    if (c + 2 < nch) load(c + 2, A0, B0);
+    mma(A1, B1);
+  }
+  if (c < nch) mma(A0, B0);
+
+  const int JK = a.J[K];
+  const int J8 = round_up(JK, 8);
+  const int64_t g8 = a.rowoff8[K];
+  const float alpha = static_cast<float>(a.coef[0]);
+  const float beta = static_cast<float>(a.coef[1]);
+#pragma unroll
+  for (int n = 0; n < BNC; ++n) {
+    const int j = jb + 16 * n;
+    if (!vb[n]) continue;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int i0 = r * 16 + 4 * q;
+      if (i0 >= J8) continue;
+      const int64_t row = g8 + i0;   // multiple of 4: the 4 rows share one tile
+      const int64_t o = (row >> 3) * tstride + static_cast<int64_t>(j) * 8 + (row & 7);
+      uint2 xp = make_uint2(0, 0);
+      if (a.prev != nullptr) xp = *reinterpret_cast<const uint2*>(a.prev + o);
+      const uint32_t wp[2] = {xp.x, xp.y};
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float y = bf2f(static_cast<uint16_t>(wp[e >> 1] >> (16 * (e & 1))));
+        v[e] = (i0 + e < JK) ? alpha * acc[r][n][e] - beta * y : 0.f;
+      }
+      if constexpr (F64OUT) {
+        double* out = static_cast<double*>(a.out);
+        const int64_t g0 = a.rowoff[K];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (i0 + e < JK) out[(g0 + i0 + e) * a.ldo + j] = static_cast<double>(v[e]);
+      } else {
+        uint16_t* out = static_cast<uint16_t*>(a.out);
+        *reinterpret_cast<uint2*>(out + o) =
+            make_uint2(f2bf(v[0]) | (static_cast<uint32_t>(f2bf(v[1])) << 16),
+                       f2bf(v[2]) | (static_cast<uint32_t>(f2bf(v[3])) << 16));
       }
     }
+  }
 }
 
-template <typename TOUT, int UNIFORM_RB>
-__global__ __launch_bounds__(NT) void step_kernel_bf16(StepArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[2 * kMaxJ * BLD];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[2 * TN * BLD];
-  __shared__ int32_t sK[7 * kMaxJ];
+template <bool F64OUT, int UNIFORM_RB>
+__global__ __launch_bounds__(NT) void step_kernel_b16(StepArgsB a) {
+  __shared__ int32_t sG[7 * kMaxJ / 8];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
   const int ct = id / a.M;
   const int e = id - ct * a.M;
   const int K = a.order[e];
   if constexpr (UNIFORM_RB > 0) {
-    step_body_bf16<TOUT, UNIFORM_RB>(a, K, ct, sA, sB, sK);
+    step_body_b16<F64OUT, UNIFORM_RB>(a, K, ct, sG);
   } else {
     switch (a.rbv[K]) {
-      case 1: step_body_bf16<TOUT, 1>(a, K, ct, sA, sB, sK); break;
-      case 2: step_body_bf16<TOUT, 2>(a, K, ct, sA, sB, sK); break;
-      case 3: step_body_bf16<TOUT, 3>(a, K, ct, sA, sB, sK); break;
-      case 4: step_body_bf16<TOUT, 4>(a, K, ct, sA, sB, sK); break;
-      case 5: step_body_bf16<TOUT, 5>(a, K, ct, sA, sB, sK); break;
-      case 6: step_body_bf16<TOUT, 6>(a, K, ct, sA, sB, sK); break;
-      case 7: step_body_bf16<TOUT, 7>(a, K, ct, sA, sB, sK); break;
-      default: step_body_bf16<TOUT, 8>(a, K, ct, sA, sB, sK); break;
+      case 1: step_body_b16<F64OUT, 1>(a, K, ct, sG); break;
+      case 2: step_body_b16<F64OUT, 2>(a, K, ct, sG); break;
+      case 3: step_body_b16<F64OUT, 3>(a, K, ct, sG); break;
+      case 4: step_body_b16<F64OUT, 4>(a, K, ct, sG); break;
+      case 5: step_body_b16<F64OUT, 5>(a, K, ct, sG); break;
+      case 6: step_body_b16<F64OUT, 6>(a, K, ct, sG); break;
+      case 7: step_body_b16<F64OUT, 7>(a, K, ct, sG); break;
+      default: step_body_b16<F64OUT, 8>(a, K, ct, sG); break;
     }
   }
 }
 
-template <typename TOUT>
-int dispatch_step_bf16(const Plan& p, const StepArgs& a, int ns, hipStream_t st) {
-  const int64_t nwg = ceil_div(ns, TN) * p.M;
-  if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
-  dim3 grid(static_cast<unsigned>(nwg)), block(NT);
+template <bool F64OUT>
+void dispatch_step_b16(const Plan& p, const StepArgsB& a, dim3 grid, hipStream_t st) {
   if (p.uniform) {
     switch (p.maxRB) {
-      case 1: step_kernel_bf16<TOUT, 1><<<grid, block, 0, st>>>(a); break;
-      case 2: step_kernel_bf16<TOUT, 2><<<grid, block, 0, st>>>(a); break;
-      case 3: step_kernel_bf16<TOUT, 3><<<grid, block, 0, st>>>(a); break;
-      case 4: step_kernel_bf16<TOUT, 4><<<grid, block, 0, st>>>(a); break;
-      case 5: step_kernel_bf16<TOUT, 5><<<grid, block, 0, st>>>(a); break;
-      case 6: step_kernel_bf16<TOUT, 6><<<grid, block, 0, st>>>(a); break;
-      case 7: step_kernel_bf16<TOUT, 7><<<grid, block, 0, st>>>(a); break;
-      default: step_kernel_bf16<TOUT, 8><<<grid, block, 0, st>>>(a); break;
+      case 1: step_kernel_b16<F64OUT, 1><<<grid, NT, 0, st>>>(a); break;
+      case 2: step_kernel_b16<F64OUT, 2><<<grid, NT, 0, st>>>(a); break;
+      case 3: step_kernel_b16<F64OUT, 3><<<grid, NT, 0, st>>>(a); break;
+      case 4: step_kernel_b16<F64OUT, 4><<<grid, NT, 0, st>>>(a); break;
+      case 5: step_kernel_b16<F64OUT, 5><<<grid, NT, 0, st>>>(a); break;
+      case 6: step_kernel_b16<F64OUT, 6><<<grid, NT, 0, st>>>(a); break;
+      case 7: step_kernel_b16<F64OUT, 7><<<grid, NT, 0, st>>>(a); break;
+      default: step_kernel_b16<F64OUT, 8><<<grid, NT, 0, st>>>(a); break;
     }
   } else {
-    step_kernel_bf16<TOUT, 0><<<grid, block, 0, st>>>(a);
+    step_kernel_b16<F64OUT, 0><<<grid, NT, 0, st>>>(a);
   }
-  CHEFSI_LAUNCHED("cheb_step_bf16");
-  return CHEFSI_OK;
+}
+
+// X (float64 row-major) -> bf16 8-row tiles with zero padding rows, through a
+// 64 x 64 LDS tile: reads along a row; each thread then writes the 8 rows of
+// one (tile, state) pair as 16 contiguous bytes.
+__global__ __launch_bounds__(256) void to_tiles_b16_kernel(const double* X, int64_t ldx, const int32_t* rowsrc8,
+                                                           int64_t N8, int ns, uint16_t* out) {
+  __shared__ float tile[64][65];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int c0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr;
+    const int c = c0 + tx;
+    float v = 0.f;
+    if (r < N8 && c < ns) {
+      const int32_t src = rowsrc8[r];
+      if (src >= 0) v = static_cast<float>(X[static_cast<int64_t>(src) * ldx + c]);
+    }
+    tile[rr][tx] = v;
+  }
+  __syncthreads();
+  // 8 row tiles x 64 states per block; thread t covers (tile t/64 and t/64+4, state t%64)
+  for (int gg = ty; gg < 8; gg += 4) {
+    const int c = c0 + tx;
+    const int64_t G = (r0 >> 3) + gg;
+    if (c < ns && G * 8 < N8) {
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        w[e] = f2bf(tile[gg * 8 + 2 * e][tx]) | (static_cast<uint32_t>(f2bf(tile[gg * 8 + 2 * e + 1][tx])) << 16);
+      *reinterpret_cast<uint4*>(out + (G * ns + c) * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
 }
 
 template <typename TC, typename TOUT, int EPI>
@@ -629,6 +660,7 @@ struct RepackArgs {
   const int32_t* rbv;
   int S;
   bool transpose_h;
+  const double* shift;   // if set: the self block gets -shift on its diagonal
 };
 
 // CHUNKED (bf16 path): within each 32-row chunk of the element's reduction
@@ -650,7 +682,10 @@ __global__ __launch_bounds__(256) void repack_kernel(RepackArgs ra, T* panel_bas
   const int JK = ra.J[K], JKp = ra.J[Kp];
   const int JP = ra.rbv[K] * 16;
   int pre = 0;
-  for (int t = 0; t < s; ++t) pre += ra.J[ra.nbr[K * ra.S + t]];
+  for (int t = 0; t < s; ++t) {
+    const int Jt = ra.J[ra.nbr[K * ra.S + t]];
+    pre += CHUNKED ? round_up(Jt, 8) : Jt;   // BF16 panels: 8-padded neighbour segments
+  }
   const int sopp = (s == 0) ? 0 : ((s & 1) ? s + 1 : s - 1);
   // panel row index k = pre + (column of H_{K;K'}), panel column = row of H_{K;K'}
   // Normal: source H_{K;s} (JK x JKp) -> panel[pre + c][r] (transpose).
@@ -664,9 +699,10 @@ __global__ __launch_bounds__(256) void repack_kernel(RepackArgs ra, T* panel_bas
   const int tc = blockIdx.x - tr * tilesC;
   if (tr * 32 >= R) return;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double sh = (ra.shift != nullptr && s == 0) ? *ra.shift : 0.0;
   for (int yy = ty; yy < 32; yy += 8) {
     const int r = tr * 32 + yy, c = tc * 32 + tx;
-    tile[yy][tx] = (r < R && c < C) ? src[static_cast<int64_t>(r) * C + c] : 0.0;
+    tile[yy][tx] = (r < R && c < C) ? src[static_cast<int64_t>(r) * C + c] - (r == c ? sh : 0.0) : 0.0;
   }
   __syncthreads();
   T* panel = panel_base + ra.poff[K];
@@ -750,9 +786,9 @@ int launch_const_coef3(double alpha, double beta, double c, double* d_coef, hipS
 }
 
 int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h, void* d_panel,
-                  hipStream_t st) {
+                  hipStream_t st, const double* d_shift) {
   const unsigned fill_grid = grid_for(p.panel_elems);
-  RepackArgs ra{d_H, p.d_hoff, p.d_nbr, p.d_J, p.d_poff, p.d_rb, p.stencil, transpose_h};
+  RepackArgs ra{d_H, p.d_hoff, p.d_nbr, p.d_J, p.d_poff, p.d_rb, p.stencil, transpose_h, nullptr};
   const int tiles = static_cast<int>(ceil_div(p.maxJ, 32) * ceil_div(p.maxJ, 32));
   dim3 grid(tiles, p.M * p.stencil);
   if (dtype == CHEFSI_F64) {
@@ -762,8 +798,12 @@ int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h,
     fill_kernel<float><<<fill_grid, 256, 0, st>>>(static_cast<float*>(d_panel), p.panel_elems);
     repack_kernel<float, false><<<grid, 256, 0, st>>>(ra, static_cast<float*>(d_panel));
   } else if (dtype == CHEFSI_BF16) {
-    fill_kernel<uint16_t><<<fill_grid, 256, 0, st>>>(static_cast<uint16_t*>(d_panel), p.panel_elems);
-    repack_kernel<uint16_t, true><<<grid, 256, 0, st>>>(ra, static_cast<uint16_t*>(d_panel));
+    const unsigned fill8 = grid_for(p.panel8_elems);
+    RepackArgs rb = ra;
+    rb.poff = p.d_poff8;
+    rb.shift = d_shift;
+    fill_kernel<uint16_t><<<fill8, 256, 0, st>>>(static_cast<uint16_t*>(d_panel), p.panel8_elems);
+    repack_kernel<uint16_t, true><<<grid, 256, 0, st>>>(rb, static_cast<uint16_t*>(d_panel));
   } else {
     return fail(CHEFSI_ERR_UNSUPPORTED, "repack: dtype");
   }
@@ -793,15 +833,51 @@ int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_c
     if (io.out_f64) return dispatch_step<float, double, 0>(p, a, ns, st);
     return dispatch_step<float, float, 0>(p, a, ns, st);
   }
-  if (dtype == CHEFSI_BF16) {
-    if (io.in_f64 || (io.prev && io.prev_f64))
-      return fail(CHEFSI_ERR_ARG, "step: BF16 step needs BF16 inputs");
-    if ((io.ldi % 8) != 0 || (reinterpret_cast<uintptr_t>(io.in) & 15u) != 0)
-      return fail(CHEFSI_ERR_ARG, "step: BF16 input rows must be 16-byte aligned");
-    if (io.out_f64) return dispatch_step_bf16<double>(p, a, ns, st);
-    return dispatch_step_bf16<uint16_t>(p, a, ns, st);
-  }
   return fail(CHEFSI_ERR_UNSUPPORTED, "step: dtype");
+}
+
+int launch_step_b16(const Plan& p, const void* d_panel8, const double* d_coef, const void* in, const void* prev,
+                    void* out, bool out_f64, int64_t ldo, int ns, hipStream_t st) {
+  if (ns <= 0) return CHEFSI_OK;
+  if (in == nullptr || out == nullptr) return fail(CHEFSI_ERR_ARG, "step: null buffer");
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(prev) | reinterpret_cast<uintptr_t>(d_panel8)) & 15u)
+    return fail(CHEFSI_ERR_ARG, "step: BF16 buffers must be 16-byte aligned");
+  if (!out_f64 && (reinterpret_cast<uintptr_t>(out) & 7u)) return fail(CHEFSI_ERR_ARG, "step: BF16 output alignment");
+  const int64_t nwg = ceil_div(ns, BTN) * p.M;
+  if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
+  StepArgsB a{};
+  a.panel = static_cast<const uint16_t*>(d_panel8);
+  a.poff8 = p.d_poff8;
+  a.kpad8 = p.d_kpad8;
+  a.kgoff = p.d_kgoff;
+  a.kg8 = p.d_kg8;
+  a.J = p.d_J;
+  a.rbv = p.d_rb;
+  a.rowoff8 = p.d_rowoff8;
+  a.rowoff = p.d_rowoff;
+  a.order = p.d_order;
+  a.coef = d_coef;
+  a.in = static_cast<const uint16_t*>(in);
+  a.prev = static_cast<const uint16_t*>(prev);
+  a.out = out;
+  a.ldo = ldo;
+  a.ns = ns;
+  a.M = p.M;
+  dim3 grid(static_cast<unsigned>(nwg));
+  if (out_f64)
+    dispatch_step_b16<true>(p, a, grid, st);
+  else
+    dispatch_step_b16<false>(p, a, grid, st);
+  CHEFSI_LAUNCHED("cheb_step_b16");
+  return CHEFSI_OK;
+}
+
+int launch_to_tiles_b16(const Plan& p, const double* X, int64_t ldx, void* out, int ns, hipStream_t st) {
+  if (ns <= 0) return CHEFSI_OK;
+  dim3 grid(static_cast<unsigned>(ceil_div(p.N8, 64)), static_cast<unsigned>(ceil_div(ns, 64)));
+  to_tiles_b16_kernel<<<grid, 256, 0, st>>>(X, ldx, p.d_rowsrc8, p.N8, ns, static_cast<uint16_t*>(out));
+  CHEFSI_LAUNCHED("to_tiles_b16");
+  return CHEFSI_OK;
 }
 
 int launch_resid_partial(const Plan& p, const void* d_panel, const double* d_X, int64_t ldx,
@@ -829,8 +905,6 @@ int launch_convert(const double* src, int64_t lds, void* dst, int dst_dtype, int
     convert_kernel<double, double><<<g, 256, 0, st>>>(src, lds, static_cast<double*>(dst), ldd, n, ns);
   else if (dst_dtype == CHEFSI_F32)
     convert_kernel<double, float><<<g, 256, 0, st>>>(src, lds, static_cast<float*>(dst), ldd, n, ns);
-  else if (dst_dtype == CHEFSI_BF16)
-    convert_kernel<double, uint16_t><<<g, 256, 0, st>>>(src, lds, static_cast<uint16_t*>(dst), ldd, n, ns);
   else
     return fail(CHEFSI_ERR_UNSUPPORTED, "convert: dtype");
   CHEFSI_LAUNCHED("convert");
