@@ -591,13 +591,31 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
       delete p;
       return fail(CHEFSI_ERR_ARG, "plan_create: too many rows");
     }
-    // heaviest work-groups first (uniform plans keep the natural order)
-    std::vector<int32_t> order(M);
-    std::iota(order.begin(), order.end(), 0);
-    if (!p->uniform) {
-      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return static_cast<int64_t>(p->rb[x]) * p->kpad[x] > static_cast<int64_t>(p->rb[y]) * p->kpad[y];
-      });
+    // Element processing order of the step kernels.  Consecutive work-groups
+    // of one XCD take consecutive entries, so a compact traversal keeps the
+    // neighbour rows they gather in that XCD's L2: columns of BX x BY
+    // elements, walked z-slab by z-slab.
+#ifndef CHEFSI_ELEM_ORDER
+#define CHEFSI_ELEM_ORDER 1
+#endif
+    std::vector<int32_t> order;
+    order.reserve(M);
+    if (CHEFSI_ELEM_ORDER >= 1 && (p->uniform || CHEFSI_ELEM_ORDER >= 2)) {
+      const int BX = std::min(nx, 4), BY = std::min(ny, 4);
+      for (int by = 0; by < ny; by += BY)
+        for (int bx = 0; bx < nx; bx += BX)
+          for (int z = 0; z < nz; ++z)
+            for (int y = by; y < std::min(ny, by + BY); ++y)
+              for (int x = bx; x < std::min(nx, bx + BX); ++x) order.push_back(x + nx * (y + ny * z));
+    } else {
+      order.resize(M);
+      std::iota(order.begin(), order.end(), 0);
+      // mixed block sizes: heaviest work-groups first
+      if (!p->uniform) {
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+          return static_cast<int64_t>(p->rb[x]) * p->kpad[x] > static_cast<int64_t>(p->rb[y]) * p->kpad[y];
+        });
+      }
     }
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;

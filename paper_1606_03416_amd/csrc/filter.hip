@@ -337,8 +337,15 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
 // the element's panel through L1.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int BNC = 4;                 // 16-column fragments per wave
-constexpr int BTN = (NT / 64) * 16 * BNC;  // columns per work-group
+#ifndef CHEFSI_B16_NC
+#define CHEFSI_B16_NC 4
+#endif
+#ifndef CHEFSI_B16_WAVES
+#define CHEFSI_B16_WAVES 4
+#endif
+constexpr int BNC = CHEFSI_B16_NC;     // 16-column fragments per wave
+constexpr int BNT = 64 * CHEFSI_B16_WAVES;  // threads per work-group
+constexpr int BTN = CHEFSI_B16_WAVES * 16 * BNC;  // columns per work-group
 
 struct StepArgsB {
   const uint16_t* panel;
@@ -368,7 +375,7 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
   const int ngrp = a.kpad8[K] >> 3;
   {
     const int32_t* kg = a.kg8 + a.kgoff[K];
-    for (int t = tid; t < ngrp; t += NT) sG[t] = kg[t];
+    for (int t = tid; t < ngrp; t += BNT) sG[t] = kg[t];
   }
   __syncthreads();
   const int nch = ngrp >> 2;
@@ -460,8 +467,11 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
   }
 }
 
+#ifndef CHEFSI_B16_WPE
+#define CHEFSI_B16_WPE 3
+#endif
 template <bool F64OUT, int UNIFORM_RB>
-__global__ __launch_bounds__(NT) void step_kernel_b16(StepArgsB a) {
+__global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(CHEFSI_B16_WPE))) void step_kernel_b16(StepArgsB a) {
   __shared__ int32_t sG[7 * kMaxJ / 8];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
   const int ct = id / a.M;
@@ -487,17 +497,17 @@ template <bool F64OUT>
 void dispatch_step_b16(const Plan& p, const StepArgsB& a, dim3 grid, hipStream_t st) {
   if (p.uniform) {
     switch (p.maxRB) {
-      case 1: step_kernel_b16<F64OUT, 1><<<grid, NT, 0, st>>>(a); break;
-      case 2: step_kernel_b16<F64OUT, 2><<<grid, NT, 0, st>>>(a); break;
-      case 3: step_kernel_b16<F64OUT, 3><<<grid, NT, 0, st>>>(a); break;
-      case 4: step_kernel_b16<F64OUT, 4><<<grid, NT, 0, st>>>(a); break;
-      case 5: step_kernel_b16<F64OUT, 5><<<grid, NT, 0, st>>>(a); break;
-      case 6: step_kernel_b16<F64OUT, 6><<<grid, NT, 0, st>>>(a); break;
-      case 7: step_kernel_b16<F64OUT, 7><<<grid, NT, 0, st>>>(a); break;
-      default: step_kernel_b16<F64OUT, 8><<<grid, NT, 0, st>>>(a); break;
+      case 1: step_kernel_b16<F64OUT, 1><<<grid, BNT, 0, st>>>(a); break;
+      case 2: step_kernel_b16<F64OUT, 2><<<grid, BNT, 0, st>>>(a); break;
+      case 3: step_kernel_b16<F64OUT, 3><<<grid, BNT, 0, st>>>(a); break;
+      case 4: step_kernel_b16<F64OUT, 4><<<grid, BNT, 0, st>>>(a); break;
+      case 5: step_kernel_b16<F64OUT, 5><<<grid, BNT, 0, st>>>(a); break;
+      case 6: step_kernel_b16<F64OUT, 6><<<grid, BNT, 0, st>>>(a); break;
+      case 7: step_kernel_b16<F64OUT, 7><<<grid, BNT, 0, st>>>(a); break;
+      default: step_kernel_b16<F64OUT, 8><<<grid, BNT, 0, st>>>(a); break;
     }
   } else {
-    step_kernel_b16<F64OUT, 0><<<grid, NT, 0, st>>>(a);
+    step_kernel_b16<F64OUT, 0><<<grid, BNT, 0, st>>>(a);
   }
 }
 
