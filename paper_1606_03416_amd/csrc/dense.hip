@@ -12,14 +12,21 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 128;   // output tile (rows and columns)
 constexpr int GK = 16;    // reduction rows per LDS chunk
-constexpr int GNT = 256;  // threads
-#ifndef CHEFSI_GEMM_PAD
-#define CHEFSI_GEMM_PAD 2
-#endif
-constexpr int GLD = GT + CHEFSI_GEMM_PAD;
+constexpr int GNT = 256;  // threads: 2 x 2 waves of 64 x 64 outputs
+// LDS operand chunk, two layouts of 2304 doubles each:
+//   k-major  [GK][LDK]: rows 144 doubles apart, so the two k rows a half-wave
+//            reads fall on disjoint halves of the 64 banks;
+//   idx-major [GT][LDI]: rows 17 doubles apart (an odd stride), so the 16
+//            rows a quarter-wave reads fall on distinct bank pairs.
+constexpr int LDK = 144;
+constexpr int LDI = 17;
+constexpr int GBUF = GK * LDK;
+static_assert(GT * LDI <= GBUF, "both operand layouts fit one buffer");
 
-// A operand: lane l holds A[l%16][l/16]; B operand: B[l/16][l%16];
-// output element q of lane l is D[4q + l/16][l%16].
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// FP64 MFMA 16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16]; output
+// element v of lane l is D[4v + l/16][l%16].
 __device__ __forceinline__ d4 mma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -41,111 +48,168 @@ struct GemmArgs {
   int tn_tiles;     // upper_only: tiles per row of the square tile grid
 };
 
-// Loads of one 128 x GK operand chunk into registers (8 values per thread),
-// branch-free: out-of-range elements read a clamped valid address and are
-// replaced by zero.
-//   KMAJOR:  X[k][idx] (row stride ld): thread reads idx = tid%128, k = tid/128 + 2q.
-//   !KMAJOR: X[idx][k] (row stride ld): thread reads idx = tid/2, k = (tid%2)*8 + q.
-template <bool KMAJOR>
+// One GT x GK operand chunk, 16 bytes (two doubles) per thread per load, four
+// loads per thread; out-of-range elements are zero.
+//   KMAJOR:  X[k][idx] (row stride ld): load e covers k row 4e + tid/64,
+//            idx pair 2*(tid%64): a wave reads one whole 1 KB row.
+//   !KMAJOR: X[idx][k]: load e covers idx row 32e + tid/8, k pair 2*(tid%8):
+//            eight lanes read one 128-byte row segment.
+// VEC: ld even and X 16-byte aligned (pairs are single 16-byte loads).
+template <bool KMAJOR, bool VEC>
 __device__ __forceinline__ void load_chunk(const double* X, int64_t ld, int64_t idx0, int64_t lim,
-                                           int64_t kc, int64_t kend, double (&r)[8]) {
+                                           int64_t kc, int64_t kend, double2 (&r)[4]) {
   const int tid = threadIdx.x;
-  if constexpr (KMAJOR) {
-    const int64_t idx = idx0 + (tid & 127);
-    const bool iv = idx < lim;
-    const int64_t ic = iv ? idx : lim - 1;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t kk = kc + (tid >> 7) + 2 * q;
-      const bool v = iv && kk < kend;
-      const double x = X[(v ? kk : kend - 1) * ld + ic];
-      r[q] = v ? x : 0.0;
+  for (int e = 0; e < 4; ++e) {
+    int64_t row, col, rlim, clim;   // row/col of X in memory
+    if constexpr (KMAJOR) {
+      row = kc + 4 * e + (tid >> 6);
+      col = idx0 + 2 * (tid & 63);
+      rlim = kend;
+      clim = lim;
+    } else {
+      row = idx0 + 32 * e + (tid >> 3);
+      col = kc + 2 * (tid & 7);
+      rlim = lim;
+      clim = kend;
     }
-  } else {
-    const int64_t idx = idx0 + (tid >> 1);
-    const bool iv = idx < lim;
-    const double* row = X + (iv ? idx : lim - 1) * ld;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t kk = kc + (tid & 1) * 8 + q;
-      const bool v = iv && kk < kend;
-      const double x = row[v ? kk : kend - 1];
-      r[q] = v ? x : 0.0;
+    double2 v = make_double2(0.0, 0.0);
+    if (row < rlim) {
+      const double* src = X + row * ld + col;
+      if (VEC && col + 1 < clim) {
+        v = *reinterpret_cast<const double2*>(src);
+      } else {
+        if (col < clim) v.x = src[0];
+        if (col + 1 < clim) v.y = src[1];
+      }
     }
+    r[e] = v;
   }
 }
 
 template <bool KMAJOR>
-__device__ __forceinline__ void store_chunk(double (*S)[GLD], const double (&r)[8]) {
+__device__ __forceinline__ void store_chunk(double* S, const double2 (&r)[4]) {
   const int tid = threadIdx.x;
-  if constexpr (KMAJOR) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) S[(tid >> 7) + 2 * q][tid & 127] = r[q];
-  } else {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) S[(tid & 1) * 8 + q][tid >> 1] = r[q];
+  for (int e = 0; e < 4; ++e) {
+    if constexpr (KMAJOR) {
+      *reinterpret_cast<double2*>(S + (4 * e + (tid >> 6)) * LDK + 2 * (tid & 63)) = r[e];
+    } else {
+      double* d = S + (32 * e + (tid >> 3)) * LDI + 2 * (tid & 7);
+      d[0] = r[e].x;
+      d[1] = r[e].y;
+    }
   }
 }
 
-// FP64 MFMA 4x4x4 (4 blocks) with the A operand replicated over the blocks:
-// lane l supplies A[l%4][l/16] and B[l/16][l%16]; the result element of lane
-// l is D[l/16][l%16], a 4 x 16 x 4 product per instruction.  On gfx950 this
-// shape sustains a much higher FP64 rate than the 16x16x4 shape.
-__device__ __forceinline__ double mma4(double a, double b, double c) {
-  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+// Unguarded operand pointers of this thread for the four loads of a chunk
+// (fully interior tiles with 16-byte-aligned rows), advanced chunk by chunk.
+template <bool KMAJOR>
+struct FastPtr {
+  const double* p[4];
+  int64_t step;
+  __device__ __forceinline__ void init(const double* X, int64_t ld, int64_t idx0, int64_t kc) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      p[e] = KMAJOR ? X + (kc + 4 * e + (tid >> 6)) * ld + idx0 + 2 * (tid & 63)
+                    : X + (idx0 + 32 * e + (tid >> 3)) * ld + kc + 2 * (tid & 7);
+    step = KMAJOR ? GK * ld : GK;
+  }
+  __device__ __forceinline__ void load(int c, double2 (&r)[4]) const {
+    const int64_t o = c * step;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = *reinterpret_cast<const double2*>(p[e] + o);
+  }
+};
+
+// MFMA operand of lane l for reduction step kk (k = 4kk + l/16) and index
+// base + l%16.
+template <bool KMAJOR>
+__device__ __forceinline__ double frag(const double* S, int kk, int base, int lane) {
+  if constexpr (KMAJOR) return S[(4 * kk + (lane >> 4)) * LDK + base + (lane & 15)];
+  return S[(base + (lane & 15)) * LDI + 4 * kk + (lane >> 4)];
 }
 
 // acc += op(A)[i0.., k] op(B)[k, j0..] over k in [kbeg, kend) for a 128 x 128
-// tile; wave w owns rows 32w..32w+31 (8 four-row fragments) and all 128
-// columns (8 sixteen-column fragments).
-template <bool AK, bool BK>
+// tile; wave (wr, wc) owns rows 64wr..+63 and columns 64wc..+63 as 4 x 4
+// sixteen-square fragments.  A is k-major (AK) or row-major; B is k-major (BK)
+// or stored n x k (its rows are the output columns).  Interior tiles with
+// aligned rows take unguarded loads for every full chunk; the LDS operands of
+// reduction step kk+1 are read while the MFMAs of step kk run.
+template <bool AK, bool BK, bool VEC>
 __device__ __forceinline__ void tile_mma(const double* A, int64_t lda, const double* B, int64_t ldb,
                                          int64_t m, int64_t n, int64_t kbeg, int64_t kend, int64_t i0,
-                                         int64_t j0, double (*sA)[GK][GLD], double (*sB)[GK][GLD],
-                                         double (&acc)[8][8]) {
+                                         int64_t j0, double* sA, double* sB, d4 (&acc)[4][4]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ib = (wave >> 1) * 64, jb = (wave & 1) * 64;
   const int nch = kend > kbeg ? static_cast<int>(ceil_div(kend - kbeg, GK)) : 0;
-  const int arow = wave * 32 + (lane & 3);
-  const int bcol = lane & 15;
-  double ra[8], rb[8];
+  const int nfull = kend > kbeg ? static_cast<int>((kend - kbeg) / GK) : 0;
+  const bool fast = VEC && i0 + GT <= m && j0 + GT <= n;
+  FastPtr<AK> pa;
+  FastPtr<BK> pb;
+  pa.init(A, lda, i0, kbeg);
+  pb.init(B, ldb, j0, kbeg);
+  double2 ra[4], rb[4];
+  auto gload = [&](int c) {
+    if (fast && c < nfull) {
+      pa.load(c, ra);
+      pb.load(c, rb);
+    } else {
+      const int64_t kc = kbeg + static_cast<int64_t>(c) * GK;
+      load_chunk<AK, VEC>(A, lda, i0, m, kc, kend, ra);
+      load_chunk<BK, VEC>(B, ldb, j0, n, kc, kend, rb);
+    }
+  };
   if (nch > 0) {
-    load_chunk<AK>(A, lda, i0, m, kbeg, kend, ra);
-    load_chunk<BK>(B, ldb, j0, n, kbeg, kend, rb);
-    store_chunk<AK>(sA[0], ra);
-    store_chunk<BK>(sB[0], rb);
+    gload(0);
+    store_chunk<AK>(sA, ra);
+    store_chunk<BK>(sB, rb);
   }
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
+    if (c + 1 < nch) gload(c + 1);
+    const double* SA = sA + buf * GBUF;
+    const double* SB = sB + buf * GBUF;
+    double a0[4], b0[4], a1[4], b1[4];
+    auto rd = [&](int kk, double (&av)[4], double (&bv)[4]) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) av[p] = frag<AK>(SA, kk, ib + 16 * p, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = frag<BK>(SB, kk, jb + 16 * q, lane);
+    };
+    auto mm = [&](const double (&av)[4], const double (&bv)[4]) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = mma64(av[p], bv[q], acc[p][q]);
+    };
+    rd(0, a0, b0);
+    rd(1, a1, b1);
+    mm(a0, b0);
+    rd(2, a0, b0);
+    mm(a1, b1);
+    rd(3, a1, b1);
+    mm(a0, b0);
+    mm(a1, b1);
     if (c + 1 < nch) {
-      const int64_t kc = kbeg + static_cast<int64_t>(c + 1) * GK;
-      load_chunk<AK>(A, lda, i0, m, kc, kend, ra);
-      load_chunk<BK>(B, ldb, j0, n, kc, kend, rb);
-    }
-#pragma unroll 2
-    for (int kk = 0; kk < GK / 4; ++kk) {
-      const int krow = kk * 4 + (lane >> 4);
-      double av[8], bv[8];
-#pragma unroll
-      for (int p = 0; p < 8; ++p) av[p] = sA[buf][krow][arow + 4 * p];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) bv[q] = sB[buf][krow][16 * q + bcol];
-#pragma unroll
-      for (int p = 0; p < 8; ++p)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[p][q] = mma4(av[p], bv[q], acc[p][q]);
-    }
-    if (c + 1 < nch) {
-      store_chunk<AK>(sA[buf ^ 1], ra);
-      store_chunk<BK>(sB[buf ^ 1], rb);
+      store_chunk<AK>(sA + (buf ^ 1) * GBUF, ra);
+      store_chunk<BK>(sB + (buf ^ 1) * GBUF, rb);
     }
     __syncthreads();
   }
 }
 
+// Output element v of fragment (p, q) of this lane: tile row / column.
+__device__ __forceinline__ int out_row(int wave, int lane, int p, int v) {
+  return (wave >> 1) * 64 + 16 * p + 4 * v + (lane >> 4);
+}
+__device__ __forceinline__ int out_col(int wave, int lane, int q) { return (wave & 1) * 64 + 16 * q + (lane & 15); }
+
 // C tile (128 x 128) = sum_k op(A)[i][k] B[k][j] over this split's k range.
 // A_KMAJOR: A stored k x m (TN form); otherwise m x k (NN form).  B is k x n.
-template <bool A_KMAJOR>
+template <bool A_KMAJOR, bool VEC>
 __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
   int ti, tj, split;
   if (g.upper_only) {
@@ -172,37 +236,39 @@ __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
     split = blockIdx.z;
   }
   if (g.upper_only && ti > tj) return;
-  __shared__ double sA[2][GK][GLD];
-  __shared__ double sB[2][GK][GLD];
+  __shared__ __attribute__((aligned(16))) double sA[2 * GBUF];
+  __shared__ __attribute__((aligned(16))) double sB[2 * GBUF];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t i0 = static_cast<int64_t>(ti) * GT, j0 = static_cast<int64_t>(tj) * GT;
   const int64_t kbeg = static_cast<int64_t>(split) * g.kper;
   int64_t kend = kbeg + g.kper;
   if (kend > g.k) kend = g.k;
   if (g.b_upper && kend > j0 + GT) kend = j0 + GT;
-  double acc[8][8];
+  d4 acc[4][4];
 #pragma unroll
-  for (int p = 0; p < 8; ++p)
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
-  tile_mma<A_KMAJOR, true>(g.A, g.lda, g.B, g.ldb, g.m, g.n, kbeg, kend, i0, j0, sA, sB, acc);
+    for (int q = 0; q < 4; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+  tile_mma<A_KMAJOR, true, VEC>(g.A, g.lda, g.B, g.ldb, g.m, g.n, kbeg, kend, i0, j0, sA, sB, acc);
 #pragma unroll
-  for (int p = 0; p < 8; ++p) {
-    const int64_t i = i0 + wave * 32 + 4 * p + (lane >> 4);
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t j = j0 + 16 * q + (lane & 15);
-      if (i < g.m && j < g.n) {
-        if (g.part != nullptr) {
-          g.part[(static_cast<int64_t>(split) * g.m + i) * g.n + j] = acc[p][q];
-        } else {
-          double v = g.alpha * acc[p][q];
-          if (g.beta != 0.0) v += g.beta * g.C[i * g.ldc + j];
-          g.C[i * g.ldc + j] = v;
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + out_row(wave, lane, p, v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = j0 + out_col(wave, lane, q);
+        if (i < g.m && j < g.n) {
+          if (g.part != nullptr) {
+            g.part[(static_cast<int64_t>(split) * g.m + i) * g.n + j] = acc[p][q][v];
+          } else {
+            double val = g.alpha * acc[p][q][v];
+            if (g.beta != 0.0) val += g.beta * g.C[i * g.ldc + j];
+            g.C[i * g.ldc + j] = val;
+          }
         }
       }
     }
-  }
 }
 
 // Gradient onto the stored blocks (block-sparse "SDDMM"):
@@ -224,32 +290,35 @@ struct SddmmArgs {
   const double* alpha_dev;   // optional device factor (e.g. a recurrence coefficient)
 };
 
+template <bool VEC>
 __global__ __launch_bounds__(GNT, 2) void sddmm_kernel(SddmmArgs g) {
-  __shared__ double sA[2][GK][GLD];
-  __shared__ double sB[2][GK][GLD];
+  __shared__ __attribute__((aligned(16))) double sA[2 * GBUF];
+  __shared__ __attribute__((aligned(16))) double sB[2 * GBUF];
   const int blk = blockIdx.x;
   const int K = blk / g.S;
   const int Kp = g.nbr[blk];
   const int m = g.J[K], n = g.J[Kp];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double acc[8][8];
+  d4 acc[4][4];
 #pragma unroll
-  for (int p = 0; p < 8; ++p)
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[p][q] = 0.0;
-  tile_mma<false, false>(g.A + g.rowoff[K] * g.lda, g.lda, g.B + g.rowoff[Kp] * g.ldb, g.ldb, m, n, 0,
-                         g.ns, 0, 0, sA, sB, acc);
+    for (int q = 0; q < 4; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+  tile_mma<false, false, VEC>(g.A + g.rowoff[K] * g.lda, g.lda, g.B + g.rowoff[Kp] * g.ldb, g.ldb, m, n, 0,
+                              g.ns, 0, 0, sA, sB, acc);
   double* C = g.Hbar + g.hoff[blk];
   const double alpha = g.alpha * (g.alpha_dev ? *g.alpha_dev : 1.0);
 #pragma unroll
-  for (int p = 0; p < 8; ++p) {
-    const int i = wave * 32 + 4 * p + (lane >> 4);
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int j = 16 * q + (lane & 15);
-      if (i < m && j < n) C[i * n + j] += alpha * acc[p][q];
+    for (int v = 0; v < 4; ++v) {
+      const int i = out_row(wave, lane, p, v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = out_col(wave, lane, q);
+        if (i < m && j < n) C[i * n + j] += alpha * acc[p][q][v];
+      }
     }
-  }
 }
 
 __global__ void split_reduce_kernel(const double* part, int splits, int64_t m, int64_t n,
@@ -498,6 +567,9 @@ unsigned grid1(int64_t total) {
   return static_cast<unsigned>(g);
 }
 
+// operand rows can be read as aligned 16-byte pairs
+bool vec_ok(const double* X, int64_t ld) { return (ld % 2) == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0; }
+
 int choose_splits(int64_t tiles, int64_t k) {
   int64_t s = ceil_div(2048, tiles > 0 ? tiles : 1);
   const int64_t maxs = ceil_div(k, 1024);
@@ -536,7 +608,10 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
     g.tri_tiles = static_cast<int>(tn * (tn + 1) / 2);
     grid = dim3(static_cast<unsigned>(g.tri_tiles * splits), 1, 1);
   }
-  gemm_kernel<true><<<grid, GNT, 0, st>>>(g);
+  if (vec_ok(A, lda) && vec_ok(B, ldb))
+    gemm_kernel<true, true><<<grid, GNT, 0, st>>>(g);
+  else
+    gemm_kernel<true, false><<<grid, GNT, 0, st>>>(g);
   CHEFSI_LAUNCHED("gemm_tn");
   if (splits > 1) {
     split_reduce_kernel<<<grid1(m * n), 256, 0, st>>>(d_split_ws, splits, m, n, alpha, beta, C, ldc, upper_only);
@@ -554,7 +629,10 @@ int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, round_up(k > 0 ? k : 1, GK), nullptr, false, b_upper,
              0, 0};
   dim3 grid(static_cast<unsigned>(tn), static_cast<unsigned>(tm), 1);
-  gemm_kernel<false><<<grid, GNT, 0, st>>>(g);
+  if (vec_ok(A, lda) && vec_ok(B, ldb))
+    gemm_kernel<false, true><<<grid, GNT, 0, st>>>(g);
+  else
+    gemm_kernel<false, false><<<grid, GNT, 0, st>>>(g);
   CHEFSI_LAUNCHED("gemm_nn");
   return CHEFSI_OK;
 }
@@ -620,7 +698,10 @@ int sddmm_accumulate(const Plan& p, const double* A, int64_t lda, const double* 
                      double alpha, const double* d_alpha, double* d_Hbar, hipStream_t st) {
   if (ns <= 0) return CHEFSI_OK;
   SddmmArgs g{A, lda, B, ldb, d_Hbar, p.d_hoff, p.d_nbr, p.d_J, p.d_rowoff, p.stencil, ns, alpha, d_alpha};
-  sddmm_kernel<<<static_cast<unsigned>(p.M * p.stencil), GNT, 0, st>>>(g);
+  if (vec_ok(A, lda) && vec_ok(B, ldb))
+    sddmm_kernel<true><<<static_cast<unsigned>(p.M * p.stencil), GNT, 0, st>>>(g);
+  else
+    sddmm_kernel<false><<<static_cast<unsigned>(p.M * p.stencil), GNT, 0, st>>>(g);
   CHEFSI_LAUNCHED("sddmm");
   return CHEFSI_OK;
 }
