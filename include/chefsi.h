@@ -174,7 +174,11 @@ int chefsi_rayleigh_ritz(chefsi_plan plan, const double* d_H, const double* d_Yh
  * given; otherwise step 1 runs as in chefsi_bounds with d_v0 and
  * lanczos_steps, warm (a, a0 from d_ritz on entry) if `warm` != 0, cold
  * otherwise.  filter_dtype as in chefsi_filter; passes as in
- * chefsi_orthonormalize.  Outputs: d_X (new Ritz vectors), d_ritz (ns),
+ * chefsi_orthonormalize.  With passes = 2 the second Cholesky-QR pass only
+ * factors (U_2 from Yhat_1^T Yhat_1) and the Rayleigh-Ritz step uses
+ * Hhat = U_2^{-T} (Yhat_1^T H Yhat_1) U_2^{-1} and X = Yhat_1 (U_2^{-1} Q),
+ * equal to the two-pass result in exact arithmetic; d_X holds Yhat_1 in
+ * between.  Outputs: d_X (new Ritz vectors), d_ritz (ns),
  * d_resid (ns, may be NULL), d_bounds_out (3, may be NULL: the bounds used),
  * stats (host, may be NULL: per-stage event times).  Synchronises the stream
  * once at the end to read status words. */

@@ -245,6 +245,55 @@ int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout
   return CHEFSI_OK;
 }
 
+// Sweep form of CholeskyQR2 followed by Rayleigh-Ritz.  The second pass only
+// factors: Yhat1 = Y U1^{-1} is formed (into Y1out), U2 from Yhat1^T Yhat1,
+// and T2 = U2^{-1} is kept.  Rayleigh-Ritz then works on Yhat1 with
+//   Hhat = T2^T (Yhat1^T H Yhat1) T2,   X = Yhat1 (T2 Q),
+// which equals the two-pass result in exact arithmetic and saves the N x N_s
+// product Yhat1 T2.
+int run_orth_factor2(int64_t n, int ns, const double* Y, int64_t ldy, double* Y1out, int64_t ld1, double* T2,
+                     const OrthWs& o, hipStream_t st) {
+  CHEFSI_TRY(launch_fill_int(o.status, 1, 0, st));
+  CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y, ldy, Y, ldy, 0.0, o.S, ns, true, o.split, o.split_elems, st));
+  CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
+  CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
+  CHEFSI_TRY(upper_inverse(o.S, ns, o.T, o.Wt, st));
+  CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, Y, ldy, o.T, ns, 0.0, Y1out, ld1, st, true));
+  CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y1out, ld1, Y1out, ld1, 0.0, o.S, ns, true, o.split, o.split_elems, st));
+  CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
+  CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
+  CHEFSI_TRY(upper_inverse(o.S, ns, T2, o.Wt, st));
+  return CHEFSI_OK;
+}
+
+// Rayleigh-Ritz on Yhat1 (in X, overwritten by the rotated block) with the
+// second-pass factor T2; Ybuf (N x ns) receives the rotation before it is
+// copied into X.
+int run_rr_factor2(Plan& p, const void* panel64, double* X, int64_t ldx, int ns, const double* T2, double* Ybuf,
+                   double* ritz, double* resid, const RrWs& r, hipStream_t st) {
+  CHEFSI_TRY(launch_const_coef(1.0, 0.0, r.coef, st));
+  StepIO io{X, ldx, true, nullptr, 0, true, r.W, ns, true};
+  CHEFSI_TRY(launch_step(p, panel64, CHEFSI_F64, r.coef, io, ns, st));
+  CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, X, ldx, r.W, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
+  CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
+  // Hhat = T2^T Hhat1 T2 (upper triangle, mirrored)
+  CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, r.Hh, ns, T2, ns, 0.0, r.Q, ns, st, true));
+  CHEFSI_TRY(gemm_tn(ns, ns, ns, 1.0, T2, ns, r.Q, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
+  CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
+  CHEFSI_TRY(launch_fill_int(r.info, 1, 0, st));
+  CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.eig, r.eig_bytes, st));
+  CHEFSI_TRY(launch_eigvec_fix(r.Hh, ns, ns, r.Q, ns, st));
+  // X = Yhat1 (T2 Q)
+  CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, T2, ns, r.Q, ns, 0.0, r.Hh, ns, st));
+  CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, X, ldx, r.Hh, ns, 0.0, Ybuf, ns, st));
+  CHEFSI_TRY(launch_copy_f64(Ybuf, ns, X, ldx, p.N, ns, st));
+  if (resid != nullptr) {
+    CHEFSI_TRY(launch_resid_partial(p, panel64, X, ldx, ritz, ns, r.part, st));
+    CHEFSI_TRY(launch_colsum_sqrt(r.part, p.M, ns, resid, st));
+  }
+  return CHEFSI_OK;
+}
+
 int run_rr(Plan& p, const void* panel64, const double* Yh, int64_t ldy, int ns, double* Xn,
            int64_t ldx, double* ritz, double* resid, double* Qout, const RrWs& r, hipStream_t st) {
   CHEFSI_TRY(launch_const_coef(1.0, 0.0, r.coef, st));
@@ -298,12 +347,12 @@ int guarded(F&& f) {
 }
 
 size_t sweep_bytes(Plan& p, int ns, int dtype, int passes, int k) {
-  (void)passes;
   Carver c(nullptr, 0);
   c.take<double>(p.panel_elems);                        // FP64 panel
   c.take<double>(p.N * static_cast<int64_t>(ns));       // filtered block
   c.take<double>(8);                                    // bounds
   c.take<int>(8);                                       // status words
+  if (passes == 2) c.take<double>(static_cast<int64_t>(ns) * ns);   // T2
   const size_t base = c.used;
   Carver cf(nullptr, 0);
   FilterWs f;
@@ -892,6 +941,7 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
       double* Y = c.take<double>(p.N * static_cast<int64_t>(ns));
       double* bnd = c.take<double>(8);
       int* status = c.take<int>(8);
+      double* T2 = passes == 2 ? c.take<double>(static_cast<int64_t>(ns) * ns) : nullptr;
       char* rest = static_cast<char*>(ws) + c.used;
       const size_t rest_bytes = ws_bytes - c.used;
       CHEFSI_TRY(mark(0));
@@ -926,7 +976,10 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         OrthWs o;
         carve_orth(co, p.N, ns, o);
         o.status = status;
-        CHEFSI_TRY(run_orth(p.N, ns, Y, ns, passes, nullptr, o, st));
+        if (passes == 2)
+          CHEFSI_TRY(run_orth_factor2(p.N, ns, Y, ns, d_X, ldx, T2, o, st));   // Yhat1 -> X
+        else
+          CHEFSI_TRY(run_orth(p.N, ns, Y, ns, passes, nullptr, o, st));
       }
       CHEFSI_TRY(mark(4));
       // steps 4-5: Rayleigh-Ritz and rotation
@@ -935,7 +988,10 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         RrWs r;
         CHEFSI_TRY(carve_rr(cr, p, ns, false, r));
         r.info = status + 1;
-        CHEFSI_TRY(run_rr(p, panel64, Y, ns, ns, d_X, ldx, d_ritz, d_resid, nullptr, r, st));
+        if (passes == 2)
+          CHEFSI_TRY(run_rr_factor2(p, panel64, d_X, ldx, ns, T2, Y, d_ritz, d_resid, r, st));
+        else
+          CHEFSI_TRY(run_rr(p, panel64, Y, ns, ns, d_X, ldx, d_ritz, d_resid, nullptr, r, st));
       }
       CHEFSI_TRY(mark(5));
       if (d_bounds_out)
