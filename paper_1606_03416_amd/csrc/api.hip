@@ -227,7 +227,7 @@ int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout
     const int64_t ldd = (dst == Y) ? ldy : ns;
     CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, src, lds, src, lds, 0.0, o.S, ns, true, o.split, o.split_elems, st));
     CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
-    CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
+    CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, o.Wt, st));
     CHEFSI_TRY(launch_copy_f64(o.S, ns, Us[pass], ns, ns, ns, st));
     CHEFSI_TRY(upper_inverse(o.S, ns, o.T, o.Wt, st));
     CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, src, lds, o.T, ns, 0.0, dst, ldd, st, true));
@@ -256,12 +256,12 @@ int run_orth_factor2(int64_t n, int ns, const double* Y, int64_t ldy, double* Y1
   CHEFSI_TRY(launch_fill_int(o.status, 1, 0, st));
   CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y, ldy, Y, ldy, 0.0, o.S, ns, true, o.split, o.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
-  CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
+  CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, o.Wt, st));
   CHEFSI_TRY(upper_inverse(o.S, ns, o.T, o.Wt, st));
   CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, Y, ldy, o.T, ns, 0.0, Y1out, ld1, st, true));
   CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y1out, ld1, Y1out, ld1, 0.0, o.S, ns, true, o.split, o.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
-  CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, st));
+  CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, o.Wt, st));
   CHEFSI_TRY(upper_inverse(o.S, ns, T2, o.Wt, st));
   return CHEFSI_OK;
 }
@@ -1083,7 +1083,7 @@ int chefsi_loss_backward(chefsi_plan plan, const double* d_H, int m, double a, d
       double* Y = Qp[pass];
       CHEFSI_TRY(gemm_tn(ns, ns, N, 1.0, Y, ns, Y, ns, 0.0, w.S, ns, true, w.split, w.split_elems, st));
       CHEFSI_TRY(launch_symmetrize(w.S, ns, ns, 1, st));
-      CHEFSI_TRY(cholesky_upper(w.S, ns, ns, w.status, st));
+      CHEFSI_TRY(cholesky_upper(w.S, ns, ns, w.status, w.Mb, st));
       CHEFSI_TRY(trsm_right_upper(Y, ns, N, w.S, ns, ns, st));
       CHEFSI_TRY(launch_copy_f64(w.S, ns, Up[pass], ns, ns, ns, st));
     }

@@ -169,7 +169,8 @@ int upper_inverse(const double* U, int n, double* T, double* W, hipStream_t st);
 size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k);
 // mode 0: (A + A^T)/2; 1: upper -> lower; 2: lower -> upper.
 int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st);
-int cholesky_upper(double* S, int64_t lds, int n, int* d_status, hipStream_t st);
+// d_scr: device scratch of at least min(n, 64)^2 doubles.
+int cholesky_upper(double* S, int64_t lds, int n, int* d_status, double* d_scr, hipStream_t st);
 int trsm_right_upper(double* Y, int64_t ldy, int64_t nrows, const double* U, int64_t ldu, int n,
                      hipStream_t st);
 // Solve X L = Y in place (L lower triangular, n x n row-major).

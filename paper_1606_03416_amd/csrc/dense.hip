@@ -357,20 +357,24 @@ __global__ void symmetrize_kernel(double* A, int64_t lda, int n, int mode) {
   }
 }
 
-// Unblocked Cholesky of one nb x nb diagonal block (upper, in place), in LDS.
+// Unblocked Cholesky of one nb x nb diagonal block (upper, in place) and the
+// inverse of the factor, in LDS, one wave: thread t owns column t.  The
+// factor is written back to S, its inverse to T (w x w, row stride w).
 constexpr int CB = 64;
-__global__ __launch_bounds__(256) void potf2_kernel(double* S, int64_t lds, int b0, int w, int* status) {
+__global__ __launch_bounds__(64) void potf2_inv_kernel(double* S, int64_t lds, int b0, int w, double* T,
+                                                       int* status) {
   __shared__ double A[CB][CB + 1];
+  __shared__ double Ti[CB][CB + 1];
   __shared__ int bad;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int t = tid; t < w * w; t += 256) {
-    const int r = t / w, c = t - (t / w) * w;
-    A[r][c] = (r <= c) ? S[static_cast<int64_t>(b0 + r) * lds + b0 + c] : 0.0;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  for (int r = 0; r < CB; ++r) {
+    A[r][t] = (t < w && r <= t) ? S[static_cast<int64_t>(b0 + r) * lds + b0 + t] : 0.0;
+    Ti[r][t] = 0.0;
   }
   __syncthreads();
   for (int j = 0; j < w; ++j) {
-    if (tid == 0) {
+    if (t == j) {
       const double d = A[j][j];
       if (!(d > 0.0) || !isfinite(d)) {
         bad = 1;
@@ -380,49 +384,31 @@ __global__ __launch_bounds__(256) void potf2_kernel(double* S, int64_t lds, int 
       }
     }
     __syncthreads();
-    const double piv = A[j][j];
-    for (int c = j + 1 + tid; c < w; c += 256) A[j][c] /= piv;
+    if (t > j && t < w) A[j][t] /= A[j][j];
     __syncthreads();
-    const int rem = w - j - 1;
-    for (int t = tid; t < rem * rem; t += 256) {
-      const int r = j + 1 + t / rem, c = j + 1 + (t - (t / rem) * rem);
-      if (r <= c) A[r][c] -= A[j][r] * A[j][c];
+    if (t > j && t < w) {
+      const double ajt = A[j][t];
+      for (int r = j + 1; r <= t; ++r) A[r][t] -= A[j][r] * ajt;
     }
     __syncthreads();
   }
-  for (int t = tid; t < w * w; t += 256) {
-    const int r = t / w, c = t - (t / w) * w;
-    S[static_cast<int64_t>(b0 + r) * lds + b0 + c] = (r <= c) ? A[r][c] : 0.0;
-  }
-  if (tid == 0 && bad) atomicExch(status, 1);
-}
-
-// Panel of the blocked Cholesky: rows b0..b0+w of columns c >= b0+w:
-// solve U_bb^T X = S_panel (forward substitution), 64 columns per work-group.
-__global__ __launch_bounds__(64) void chol_panel_kernel(double* S, int64_t lds, int b0, int w, int n) {
-  __shared__ double U[CB][CB + 1];
-  __shared__ double X[CB][CB + 1];
-  const int tid = threadIdx.x;
-  const int c0 = b0 + w + blockIdx.x * 64;
-  for (int t = tid; t < w * w; t += 64) {
-    const int r = t / w, c = t - (t / w) * w;
-    U[r][c] = S[static_cast<int64_t>(b0 + r) * lds + b0 + c];
-  }
-  for (int r = 0; r < w; ++r) {
-    const int c = c0 + tid;
-    X[r][tid] = (c < n) ? S[static_cast<int64_t>(b0 + r) * lds + c] : 0.0;
+  // column t of U^{-1} by back substitution
+  if (t < w) {
+    Ti[t][t] = 1.0 / A[t][t];
+    for (int i = t - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int k = i + 1; k <= t; ++k) acc += A[i][k] * Ti[k][t];
+      Ti[i][t] = -acc / A[i][i];
+    }
   }
   __syncthreads();
-  for (int r = 0; r < w; ++r) {
-    double acc = X[r][tid];
-    for (int q = 0; q < r; ++q) acc -= U[q][r] * X[q][tid];
-    X[r][tid] = acc / U[r][r];
+  for (int r = 0; r < CB; ++r) {
+    if (r < w && t < w) {
+      S[static_cast<int64_t>(b0 + r) * lds + b0 + t] = (r <= t) ? A[r][t] : 0.0;
+      T[r * w + t] = Ti[r][t];
+    }
   }
-  __syncthreads();
-  for (int r = 0; r < w; ++r) {
-    const int c = c0 + tid;
-    if (c < n) S[static_cast<int64_t>(b0 + r) * lds + c] = X[r][tid];
-  }
+  if (t == 0 && bad) atomicExch(status, 1);
 }
 
 __global__ void zero_lower_kernel(double* A, int64_t lda, int n) {
@@ -643,16 +629,18 @@ int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st) {
   return CHEFSI_OK;
 }
 
-int cholesky_upper(double* S, int64_t lds, int n, int* d_status, hipStream_t st) {
+int cholesky_upper(double* S, int64_t lds, int n, int* d_status, double* d_scr, hipStream_t st) {
+  // blocked right-looking: factor and invert the diagonal block, panel
+  // U12 = U11^{-T} S12 as one GEMM (in place: each work-group reads all of its
+  // columns before it writes them), trailing update S22 -= U12^T U12 (upper)
   for (int b0 = 0; b0 < n; b0 += CB) {
     const int w = (n - b0) < CB ? (n - b0) : CB;
-    potf2_kernel<<<1, 256, 0, st>>>(S, lds, b0, w, d_status);
-    CHEFSI_LAUNCHED("potf2");
+    potf2_inv_kernel<<<1, CB, 0, st>>>(S, lds, b0, w, d_scr, d_status);
+    CHEFSI_LAUNCHED("potf2_inv");
     const int rest = n - b0 - w;
     if (rest > 0) {
-      chol_panel_kernel<<<static_cast<unsigned>(ceil_div(rest, 64)), 64, 0, st>>>(S, lds, b0, w, n);
-      CHEFSI_LAUNCHED("chol_panel");
       double* P = S + static_cast<int64_t>(b0) * lds + b0 + w;
+      CHEFSI_TRY(gemm_tn(w, rest, w, 1.0, d_scr, w, P, lds, 0.0, P, lds, false, nullptr, 0, st));
       double* T = S + static_cast<int64_t>(b0 + w) * lds + b0 + w;
       CHEFSI_TRY(gemm_tn(rest, rest, w, -1.0, P, lds, P, lds, 1.0, T, lds, true, nullptr, 0, st));
     }

@@ -184,61 +184,116 @@ __global__ void lz_check_stop(LanczosState* stt, int j) {
   }
 }
 
-// Eigenpairs of the tridiagonal T (order n <= 64) by cyclic Jacobi on one
-// thread, then the bounds policy.  ritz == nullptr selects the first-cycle rule.
-__global__ void lanczos_bounds_kernel(const LanczosState* stt, const double* ritz, int ns,
-                                      double frac, double* bounds) {
-  __shared__ double T[kMaxLanczos][kMaxLanczos];
-  __shared__ double V[kMaxLanczos][kMaxLanczos];
-  if (threadIdx.x != 0) return;
+// Eigenpairs of the tridiagonal T (order n <= 64) by parallel Jacobi: each
+// round rotates n/2 disjoint (p, q) pairs of a round-robin tournament, so a
+// sweep of n-1 rounds meets every pair once; thread t applies the rotations to
+// row / column t.  Then the bounds policy on thread 0.  ritz == nullptr
+// selects the first-cycle rule.
+__global__ __launch_bounds__(64) void lanczos_bounds_kernel(const LanczosState* stt, const double* ritz, int ns,
+                                                            double frac, double* bounds) {
+  __shared__ double T[kMaxLanczos][kMaxLanczos + 1];
+  __shared__ double V[kMaxLanczos][kMaxLanczos + 1];
+  __shared__ double cs[kMaxLanczos / 2][2];
+  __shared__ int pq[kMaxLanczos / 2][2];
+  __shared__ int done;
+  const int t = threadIdx.x;
   const int n = stt->steps;
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      T[i][j] = 0.0;
-      V[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-  for (int i = 0; i < n; ++i) T[i][i] = stt->alpha[i];
-  for (int i = 0; i + 1 < n; ++i) {
-    T[i][i + 1] = stt->beta[i];
-    T[i + 1][i] = stt->beta[i];
+  const int m = (n + 1) & ~1;   // players incl. an idle one when n is odd
+  for (int j = 0; j < kMaxLanczos; ++j) {
+    T[t][j] = 0.0;
+    V[t][j] = (t == j) ? 1.0 : 0.0;
   }
+  __syncthreads();
+  if (t < n) {
+    T[t][t] = stt->alpha[t];
+    if (t + 1 < n) {
+      T[t][t + 1] = stt->beta[t];
+      T[t + 1][t] = stt->beta[t];
+    }
+  }
+  __syncthreads();
   double fro = 0.0;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) fro += T[i][j] * T[i][j];
   fro = sqrt(fro);
   for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
-    double off = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j)
-        if (i != j) off += T[i][j] * T[i][j];
-    if (sqrt(off) <= 1e-15 * fro) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = T[p][q];
-        if (fabs(apq) <= 1e-300) continue;
-        const double tau = (T[q][q] - T[p][p]) / (2.0 * apq);
-        const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                      : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        for (int r = 0; r < n; ++r) {
-          const double xp = T[r][p], xq = T[r][q];
-          T[r][p] = c * xp - s * xq;
-          T[r][q] = s * xp + c * xq;
+    if (t == 0) {
+      double off = 0.0;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+          if (i != j) off += T[i][j] * T[i][j];
+      done = sqrt(off) <= 1e-15 * fro;
+    }
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < m - 1; ++r) {
+      if (t < m / 2) {
+        // position i of the circle holds player ((i + r) % (m - 1)) + 1; player 0 is fixed
+        int p, q;
+        if (t == 0) {
+          p = 0;
+          q = (r % (m - 1)) + 1;
+        } else {
+          p = ((t + r) % (m - 1)) + 1;
+          q = ((m - 1 - t + r) % (m - 1)) + 1;
         }
-        for (int r = 0; r < n; ++r) {
-          const double xp = T[p][r], xq = T[q][r];
-          T[p][r] = c * xp - s * xq;
-          T[q][r] = s * xp + c * xq;
+        if (p > q) {
+          const int x = p;
+          p = q;
+          q = x;
         }
-        T[p][q] = 0.0;
-        T[q][p] = 0.0;
-        for (int r = 0; r < n; ++r) {
-          const double xp = V[r][p], xq = V[r][q];
-          V[r][p] = c * xp - s * xq;
-          V[r][q] = s * xp + c * xq;
+        double c = 1.0, sn = 0.0;
+        if (q < n) {
+          const double apq = T[p][q];
+          if (fabs(apq) > 1e-300) {
+            const double tau = (T[q][q] - T[p][p]) / (2.0 * apq);
+            const double tt = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                           : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            sn = tt * c;
+          }
+        }
+        cs[t][0] = c;
+        cs[t][1] = sn;
+        pq[t][0] = p;
+        pq[t][1] = q < n ? q : p;   // idle pair: identity on p
+      }
+      __syncthreads();
+      // T <- T J and V <- V J on row t
+      if (t < n) {
+        for (int k = 0; k < m / 2; ++k) {
+          const int p = pq[k][0], q = pq[k][1];
+          if (p == q) continue;
+          const double c = cs[k][0], sn = cs[k][1];
+          const double xp = T[t][p], xq = T[t][q];
+          T[t][p] = c * xp - sn * xq;
+          T[t][q] = sn * xp + c * xq;
+          const double vp = V[t][p], vq = V[t][q];
+          V[t][p] = c * vp - sn * vq;
+          V[t][q] = sn * vp + c * vq;
         }
       }
+      __syncthreads();
+      // T <- J^T T on column t
+      if (t < n) {
+        for (int k = 0; k < m / 2; ++k) {
+          const int p = pq[k][0], q = pq[k][1];
+          if (p == q) continue;
+          const double c = cs[k][0], sn = cs[k][1];
+          const double xp = T[p][t], xq = T[q][t];
+          T[p][t] = c * xp - sn * xq;
+          T[q][t] = sn * xp + c * xq;
+        }
+      }
+      __syncthreads();
+      if (t < m / 2 && pq[t][0] != pq[t][1]) {
+        T[pq[t][0]][pq[t][1]] = 0.0;
+        T[pq[t][1]][pq[t][0]] = 0.0;
+      }
+      __syncthreads();
+    }
   }
+  if (t != 0) return;
   // ascending order of the diagonal (stable selection)
   int idx[kMaxLanczos];
   for (int i = 0; i < n; ++i) idx[i] = i;
