@@ -357,55 +357,57 @@ __global__ void symmetrize_kernel(double* A, int64_t lda, int n, int mode) {
   }
 }
 
-// Unblocked Cholesky of one nb x nb diagonal block (upper, in place) and the
-// inverse of the factor, in LDS, one wave: thread t owns column t.  The
-// factor is written back to S, its inverse to T (w x w, row stride w).
+// Lane l's value of a wave-uniform read (v_readlane), for a double.
+__device__ __forceinline__ double rdlane(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(x), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(x >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Unblocked Cholesky of one w x w diagonal block (upper, in place) and the
+// inverse of the factor, in registers of one wave: lane t holds column t of
+// the block (padded to 64 with the identity) and, afterwards, column t of the
+// inverse.  Entries of other columns are read with v_readlane.  The factor is
+// written back to S, its inverse to T (w x w, row stride w).
 constexpr int CB = 64;
 __global__ __launch_bounds__(64) void potf2_inv_kernel(double* S, int64_t lds, int b0, int w, double* T,
                                                        int* status) {
-  __shared__ double A[CB][CB + 1];
-  __shared__ double Ti[CB][CB + 1];
-  __shared__ int bad;
   const int t = threadIdx.x;
-  if (t == 0) bad = 0;
-  for (int r = 0; r < CB; ++r) {
-    A[r][t] = (t < w && r <= t) ? S[static_cast<int64_t>(b0 + r) * lds + b0 + t] : 0.0;
-    Ti[r][t] = 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    if (t == j) {
-      const double d = A[j][j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        A[j][j] = __builtin_nan("");
-      } else {
-        A[j][j] = sqrt(d);
-      }
+  double a[CB];
+#pragma unroll
+  for (int r = 0; r < CB; ++r)
+    a[r] = (t < w && r <= t) ? S[static_cast<int64_t>(b0 + r) * lds + b0 + t] : (r == t ? 1.0 : 0.0);
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const double d = rdlane(a[j], j);
+    double piv = sqrt(d);
+    if (!(d > 0.0) || !isfinite(d)) {
+      bad = true;
+      piv = __builtin_nan("");
     }
-    __syncthreads();
-    if (t > j && t < w) A[j][t] /= A[j][j];
-    __syncthreads();
-    if (t > j && t < w) {
-      const double ajt = A[j][t];
-      for (int r = j + 1; r <= t; ++r) A[r][t] -= A[j][r] * ajt;
-    }
-    __syncthreads();
-  }
-  // column t of U^{-1} by back substitution
-  if (t < w) {
-    Ti[t][t] = 1.0 / A[t][t];
-    for (int i = t - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int k = i + 1; k <= t; ++k) acc += A[i][k] * Ti[k][t];
-      Ti[i][t] = -acc / A[i][i];
+    a[j] = (t == j) ? piv : (t > j ? a[j] / piv : a[j]);
+#pragma unroll
+    for (int r = j + 1; r < CB; ++r) {
+      const double ajr = rdlane(a[j], r);
+      a[r] = (t >= r) ? a[r] - ajr * a[j] : a[r];
     }
   }
-  __syncthreads();
+  // column t of U^{-1}: T[i][t] = (delta_it - sum_{k>i} U[i][k] T[k][t]) / U[i][i]
+  double ti[CB];
+#pragma unroll
+  for (int i = CB - 1; i >= 0; --i) {
+    double acc = (t == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = i + 1; k < CB; ++k) acc -= rdlane(a[i], k) * ti[k];
+    ti[i] = acc / rdlane(a[i], i);
+  }
+#pragma unroll
   for (int r = 0; r < CB; ++r) {
     if (r < w && t < w) {
-      S[static_cast<int64_t>(b0 + r) * lds + b0 + t] = (r <= t) ? A[r][t] : 0.0;
-      T[r * w + t] = Ti[r][t];
+      S[static_cast<int64_t>(b0 + r) * lds + b0 + t] = (r <= t) ? a[r] : 0.0;
+      T[r * w + t] = ti[r];
     }
   }
   if (t == 0 && bad) atomicExch(status, 1);
