@@ -97,6 +97,13 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
+#ifndef CHEFSI_STEP_NT
+#define CHEFSI_STEP_NT 0
+#endif
+#ifndef CHEFSI_STEP_CG
+#define CHEFSI_STEP_CG 4
+#endif
+
 // Operand staging shared by both arithmetic paths: the k-major panel chunk
 // (KC x JP) and the gathered neighbour rows (KC x TN) of the input block.
 template <typename TC, int RB, int LDA>
@@ -118,7 +125,13 @@ struct Stage {
     const int tid = threadIdx.x;
     const TC* pa = panel + static_cast<int64_t>(c) * (KC * JP);
 #pragma unroll
-    for (int q = 0; q < AQ; ++q) ra[q] = pa[tid + NT * q];
+    for (int q = 0; q < AQ; ++q) {
+#if CHEFSI_STEP_NT
+      ra[q] = __builtin_nontemporal_load(pa + tid + NT * q);
+#else
+      ra[q] = pa[tid + NT * q];
+#endif
+    }
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
       const int row = brow0 + (NT / TN) * q;
@@ -296,12 +309,27 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
   // column-tile major: the work-groups in flight share one column slab of X
   const int ct = id / a.M;
   const int e = id - ct * a.M;
-#else
+#elif CHEFSI_STEP_ORDER == 1
   // element major: the column tiles of one element run together (its H panel
   // is read from HBM once per step)
   const int nct = (a.ns + TN - 1) / TN;
   const int e = id / nct;
   const int ct = id - e * nct;
+#else
+  // groups of CHEFSI_STEP_CG column tiles of one element run together, the
+  // groups column-major
+  constexpr int CG = CHEFSI_STEP_CG;
+  const int nct = (a.ns + TN - 1) / TN;
+  const int ngrp = (nct + CG - 1) / CG;
+  int g = id / (a.M * CG);
+  int rem = id - g * (a.M * CG);
+  int e = rem / CG;
+  int ct = g * CG + (rem - e * CG);
+  if (g == ngrp - 1 && nct % CG != 0) {   // last, partial group
+    const int cg = nct - g * CG;
+    e = rem / cg;
+    ct = g * CG + (rem - e * cg);
+  }
 #endif
   const int K = a.order[e];
   if constexpr (UNIFORM_RB > 0) {
@@ -543,6 +571,231 @@ __global__ __launch_bounds__(256) void to_tiles_b16_kernel(const double* X, int6
       *reinterpret_cast<uint4*>(out + (G * ns + c) * 8) = make_uint4(w[0], w[1], w[2], w[3]);
     }
   }
+}
+
+// ---------------------------------------------------------------- FP64 path
+// v_mfma_f64_16x16x4f64 (lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// output v of lane l is D[4v + l/16][l%16]).  A work-group takes one element
+// and 64*NCF columns (128 by default); wave w owns columns 16*NCF*w .. +16*NCF
+// and all of the element's rows, as RB x NCF sixteen-square fragments.  Operands are staged
+// through LDS in chunks of FKC reduction rows with 16-byte loads; the k-major
+// LDS rows are padded so that the two k rows a half-wave reads fall on
+// disjoint halves of the banks.
+#ifndef CHEFSI_F64_KC
+#define CHEFSI_F64_KC 8
+#endif
+#ifndef CHEFSI_F64_NCF
+#define CHEFSI_F64_NCF 2
+#endif
+constexpr int FKC = CHEFSI_F64_KC;
+
+template <int RB>
+constexpr int f64_lda() { return RB * 16 + ((RB & 1) ? 0 : 16); }
+
+template <int EPI, int RB, int NCF, int LDAM>
+__device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, double* sA, double* sB, int32_t* sK) {
+  constexpr int JP = RB * 16;
+  constexpr int LDA = f64_lda<RB>();
+  constexpr int TNF = 64 * NCF;
+  constexpr int LDB = TNF + 16;
+  constexpr int ASZ = FKC * LDAM, BSZ = FKC * LDB;
+  constexpr int AV = (FKC * JP / 2 + NT - 1) / NT;   // 16-byte loads of the panel chunk per thread
+  constexpr int BROWS = 2 * NT / TNF;                // gathered rows per load round
+  constexpr int BV = FKC / BROWS;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ns = a.ns;
+  {
+    const int32_t* km = a.kmap + a.koff[K];
+    const int kp = a.kpad[K];
+    for (int t = tid; t < kp; t += NT) sK[t] = km[t];
+  }
+  const double* panel = static_cast<const double*>(a.panel) + a.poff[K];
+  const double* in = static_cast<const double*>(a.in);
+  const int64_t ldi = a.ldi;
+  const int j0 = ct * TNF;
+  const int nch = a.kpad[K] / FKC;
+  const bool vec = ((ldi & 1) == 0) && ((reinterpret_cast<uintptr_t>(in) & 15u) == 0);
+  const int bcp = tid % (TNF / 2);
+  const int brow = tid / (TNF / 2);
+  const int bcol = j0 + 2 * bcp;
+  __syncthreads();
+
+  double2 ra[AV], rb[BV];
+  auto gload = [&](int c) {
+    const double* pa = panel + static_cast<int64_t>(c) * (FKC * JP);
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int idx = tid + NT * v;
+      if (idx < FKC * JP / 2) ra[v] = *reinterpret_cast<const double2*>(pa + 2 * idx);
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int g = sK[c * FKC + v * BROWS + brow];
+      double2 x = make_double2(0.0, 0.0);
+      if (g >= 0) {
+        const double* src = in + static_cast<int64_t>(g) * ldi + bcol;
+        if (vec && bcol + 1 < ns) {
+          x = *reinterpret_cast<const double2*>(src);
+        } else {
+          if (bcol < ns) x.x = src[0];
+          if (bcol + 1 < ns) x.y = src[1];
+        }
+      }
+      rb[v] = x;
+    }
+  };
+  auto sstore = [&](double* A, double* B) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int idx = tid + NT * v;
+      if (idx < FKC * JP / 2) {
+        const int e = 2 * idx;
+        *reinterpret_cast<double2*>(A + (e / JP) * LDA + (e % JP)) = ra[v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) *reinterpret_cast<double2*>(B + (v * BROWS + brow) * LDB + 2 * bcp) = rb[v];
+  };
+
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[RB][NCF];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int q = 0; q < NCF; ++q) acc[r][q] = d4{0.0, 0.0, 0.0, 0.0};
+  const int cb = wave * (16 * NCF);
+  gload(0);
+  sstore(sA, sB);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) gload(c + 1);
+    const double* A = sA + buf * ASZ;
+    const double* B = sB + buf * BSZ;
+#pragma unroll
+    for (int kk = 0; kk < FKC / 4; ++kk) {
+      const int kr = 4 * kk + (lane >> 4);
+      double av[RB], bv[NCF];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) av[r] = A[kr * LDA + 16 * r + (lane & 15)];
+#pragma unroll
+      for (int q = 0; q < NCF; ++q) bv[q] = B[kr * LDB + cb + 16 * q + (lane & 15)];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < NCF; ++q) acc[r][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[q], acc[r][q], 0, 0, 0);
+    }
+    if (c + 1 < nch) sstore(sA + (buf ^ 1) * ASZ, sB + (buf ^ 1) * BSZ);
+    __syncthreads();
+  }
+
+  const int JK = a.J[K];
+  const int64_t g0 = a.rowoff[K];
+  if constexpr (EPI == 0) {
+    const double alpha = a.coef[0], beta = a.coef[1], cc = a.coef[2];
+    const double* prev = static_cast<const double*>(a.prev);
+    double* out = static_cast<double*>(a.out);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * r + 4 * v + (lane >> 4);
+#pragma unroll
+        for (int q = 0; q < NCF; ++q) {
+          const int j = j0 + cb + 16 * q + (lane & 15);
+          if (i < JK && j < ns) {
+            const int64_t g = g0 + i;
+            double y = alpha * (acc[r][q][v] - cc * in[g * ldi + j]);
+            if (prev != nullptr) y -= beta * prev[g * a.ldp + j];
+            out[g * a.ldo + j] = y;
+          }
+        }
+      }
+  } else {
+    // residual partial sums over the element's rows: sum_i (H x - theta x)_i^2;
+    // each wave owns whole columns, so the sum needs no cross-wave step
+#pragma unroll
+    for (int q = 0; q < NCF; ++q) {
+      const int j = j0 + cb + 16 * q + (lane & 15);
+      const double th = (j < ns) ? a.theta[j] : 0.0;
+      double sum = 0.0;
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * r + 4 * v + (lane >> 4);
+          if (i < JK && j < ns) {
+            const double d = acc[r][q][v] - th * in[(g0 + i) * ldi + j];
+            sum += d * d;
+          }
+        }
+      sum += __shfl_xor(sum, 16);
+      sum += __shfl_xor(sum, 32);
+      if (lane < 16 && j < ns) a.part[static_cast<int64_t>(K) * ns + j] = sum;
+    }
+  }
+}
+
+// UNIFORM_RB > 0: every element has UNIFORM_RB row blocks; 0: switch per element.
+template <int EPI, int UNIFORM_RB, int NCF>
+#ifndef CHEFSI_F64_LB
+#define CHEFSI_F64_LB 2
+#endif
+__global__ __launch_bounds__(NT, CHEFSI_F64_LB) void step_kernel_f64(StepArgs a) {
+  constexpr int MAXRB = UNIFORM_RB > 0 ? UNIFORM_RB : 8;
+  constexpr int LDAM = f64_lda<MAXRB>();
+  __shared__ __attribute__((aligned(16))) double sA[2 * FKC * LDAM];
+  __shared__ __attribute__((aligned(16))) double sB[2 * FKC * (64 * NCF + 16)];
+  __shared__ int32_t sK[7 * kMaxJ];
+  const int id = xcd_linear(blockIdx.x, gridDim.x);
+  // groups of two column tiles of one element run together (its panel is
+  // reused from L2), the groups column-major
+  const int nct = (a.ns + 64 * NCF - 1) / (64 * NCF);
+  const int g = id / (a.M * 2);
+  const int rem = id - g * (a.M * 2);
+  const int cg = (2 * g + 2 <= nct) ? 2 : 1;
+  const int e = rem / cg;
+  const int ct = 2 * g + (rem - e * cg);
+  const int K = a.order[e];
+  if constexpr (UNIFORM_RB > 0) {
+    step_body_f64<EPI, UNIFORM_RB, NCF, LDAM>(a, K, ct, sA, sB, sK);
+  } else {
+    switch (a.rbv[K]) {
+      case 1: step_body_f64<EPI, 1, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
+      case 2: step_body_f64<EPI, 2, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
+      case 3: step_body_f64<EPI, 3, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
+      case 4: step_body_f64<EPI, 4, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
+      case 5: step_body_f64<EPI, 5, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
+      case 6: step_body_f64<EPI, 6, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
+      case 7: step_body_f64<EPI, 7, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
+      default: step_body_f64<EPI, 8, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
+    }
+  }
+}
+
+template <int EPI>
+int dispatch_step_f64(const Plan& p, const StepArgs& a, int ns, hipStream_t st) {
+  // 64*NCF columns per work-group (at most 128 when an element has > 64 rows)
+  const int ncf = (p.uniform && p.maxRB <= 4) ? CHEFSI_F64_NCF : (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2);
+  const int64_t nwg = ceil_div(ns, 64 * ncf) * p.M;
+  if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
+  dim3 grid(static_cast<unsigned>(nwg)), block(NT);
+  if (p.uniform) {
+    switch (p.maxRB) {
+      case 1: step_kernel_f64<EPI, 1, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
+      case 2: step_kernel_f64<EPI, 2, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
+      case 3: step_kernel_f64<EPI, 3, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
+      case 4: step_kernel_f64<EPI, 4, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
+      case 5: step_kernel_f64<EPI, 5, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a); break;
+      case 6: step_kernel_f64<EPI, 6, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a); break;
+      case 7: step_kernel_f64<EPI, 7, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a); break;
+      default: step_kernel_f64<EPI, 8, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a); break;
+    }
+  } else {
+    step_kernel_f64<EPI, 0, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a);
+  }
+  CHEFSI_LAUNCHED("cheb_step_f64");
+  return CHEFSI_OK;
 }
 
 template <typename TC, typename TOUT, int EPI>
@@ -835,7 +1088,7 @@ int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_c
   if (dtype == CHEFSI_F64) {
     if (!io.in_f64 || (io.prev && !io.prev_f64) || !io.out_f64)
       return fail(CHEFSI_ERR_ARG, "step: FP64 step needs FP64 operands");
-    return dispatch_step<double, double, 0>(p, a, ns, st);
+    return dispatch_step_f64<0>(p, a, ns, st);
   }
   if (dtype == CHEFSI_F32) {
     if (io.in_f64 || (io.prev && io.prev_f64))
@@ -898,7 +1151,7 @@ int launch_resid_partial(const Plan& p, const void* d_panel, const double* d_X, 
   a.ldi = ldx;
   a.theta = d_theta;
   a.part = d_part;
-  return dispatch_step<double, double, 1>(p, a, ns, st);
+  return dispatch_step_f64<1>(p, a, ns, st);
 }
 
 int launch_colsum_sqrt(const double* d_part, int rows, int ns, double* d_out, hipStream_t st) {
