@@ -161,43 +161,46 @@ __device__ __forceinline__ void tile_mma(const double* A, int64_t lda, const dou
       load_chunk<BK, VEC>(B, ldb, j0, n, kc, kend, rb);
     }
   };
+  auto rd = [&](const double* SA, const double* SB, int kk, double (&av)[4], double (&bv)[4]) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) av[p] = frag<AK>(SA, kk, ib + 16 * p, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bv[q] = frag<BK>(SB, kk, jb + 16 * q, lane);
+  };
+  auto mm = [&](const double (&av)[4], const double (&bv)[4]) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] = mma64(av[p], bv[q], acc[p][q]);
+  };
+  double a0[4], b0[4], a1[4], b1[4];
   if (nch > 0) {
     gload(0);
     store_chunk<AK>(sA, ra);
     store_chunk<BK>(sB, rb);
   }
   __syncthreads();
+  if (nch > 0) rd(sA, sB, 0, a0, b0);
+  // the last reduction step of a chunk runs after the barrier, behind the
+  // LDS reads of the next chunk's first step
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
     if (c + 1 < nch) gload(c + 1);
     const double* SA = sA + buf * GBUF;
     const double* SB = sB + buf * GBUF;
-    double a0[4], b0[4], a1[4], b1[4];
-    auto rd = [&](int kk, double (&av)[4], double (&bv)[4]) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p) av[p] = frag<AK>(SA, kk, ib + 16 * p, lane);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bv[q] = frag<BK>(SB, kk, jb + 16 * q, lane);
-    };
-    auto mm = [&](const double (&av)[4], const double (&bv)[4]) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = mma64(av[p], bv[q], acc[p][q]);
-    };
-    rd(0, a0, b0);
-    rd(1, a1, b1);
+    rd(SA, SB, 1, a1, b1);
     mm(a0, b0);
-    rd(2, a0, b0);
+    rd(SA, SB, 2, a0, b0);
     mm(a1, b1);
-    rd(3, a1, b1);
+    rd(SA, SB, 3, a1, b1);
     mm(a0, b0);
-    mm(a1, b1);
     if (c + 1 < nch) {
       store_chunk<AK>(sA + (buf ^ 1) * GBUF, ra);
       store_chunk<BK>(sB + (buf ^ 1) * GBUF, rb);
     }
     __syncthreads();
+    if (c + 1 < nch) rd(sA + (buf ^ 1) * GBUF, sB + (buf ^ 1) * GBUF, 0, a0, b0);
+    mm(a1, b1);
   }
 }
 

@@ -664,29 +664,36 @@ __device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, 
 #pragma unroll
     for (int q = 0; q < NCF; ++q) acc[r][q] = d4{0.0, 0.0, 0.0, 0.0};
   const int cb = wave * (16 * NCF);
+  auto rd = [&](const double* A, const double* B, int kk, double (&av)[RB], double (&bv)[NCF]) {
+    const int kr = 4 * kk + (lane >> 4);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) av[r] = A[kr * LDA + 16 * r + (lane & 15)];
+#pragma unroll
+    for (int q = 0; q < NCF; ++q) bv[q] = B[kr * LDB + cb + 16 * q + (lane & 15)];
+  };
+  auto mm = [&](const double (&av)[RB], const double (&bv)[NCF]) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < NCF; ++q) acc[r][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[q], acc[r][q], 0, 0, 0);
+  };
+  static_assert(FKC == 8, "two reduction steps per chunk");
+  double a0[RB], b0[NCF], a1[RB], b1[NCF];
   gload(0);
   sstore(sA, sB);
   __syncthreads();
+  if (nch > 0) rd(sA, sB, 0, a0, b0);
+  // the second reduction step of a chunk runs after the barrier, behind the
+  // LDS reads of the next chunk's first step
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
     if (c + 1 < nch) gload(c + 1);
-    const double* A = sA + buf * ASZ;
-    const double* B = sB + buf * BSZ;
-#pragma unroll
-    for (int kk = 0; kk < FKC / 4; ++kk) {
-      const int kr = 4 * kk + (lane >> 4);
-      double av[RB], bv[NCF];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) av[r] = A[kr * LDA + 16 * r + (lane & 15)];
-#pragma unroll
-      for (int q = 0; q < NCF; ++q) bv[q] = B[kr * LDB + cb + 16 * q + (lane & 15)];
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int q = 0; q < NCF; ++q) acc[r][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[q], acc[r][q], 0, 0, 0);
-    }
+    rd(sA + buf * ASZ, sB + buf * BSZ, 1, a1, b1);
+    mm(a0, b0);
     if (c + 1 < nch) sstore(sA + (buf ^ 1) * ASZ, sB + (buf ^ 1) * BSZ);
     __syncthreads();
+    if (c + 1 < nch) rd(sA + (buf ^ 1) * ASZ, sB + (buf ^ 1) * BSZ, 0, a0, b0);
+    mm(a1, b1);
   }
 
   const int JK = a.J[K];
