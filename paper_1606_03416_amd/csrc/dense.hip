@@ -373,17 +373,21 @@ __device__ __forceinline__ double rdlane(double v, int l) {
 // the block (padded to 64 with the identity) and, afterwards, column t of the
 // inverse.  Entries of other columns are read with v_readlane.  The factor is
 // written back to S, its inverse to T (w x w, row stride w).
-constexpr int CB = 64;
+constexpr int CB = 64;   // diagonal blocks of the row-wise triangular solves
+#ifndef CHEFSI_CHOL_CB
+#define CHEFSI_CHOL_CB 32
+#endif
+constexpr int HB = CHEFSI_CHOL_CB;   // diagonal block of the blocked Cholesky (<= 64: one lane per column)
 __global__ __launch_bounds__(64) void potf2_inv_kernel(double* S, int64_t lds, int b0, int w, double* T,
                                                        int* status) {
   const int t = threadIdx.x;
-  double a[CB];
+  double a[HB];
 #pragma unroll
-  for (int r = 0; r < CB; ++r)
+  for (int r = 0; r < HB; ++r)
     a[r] = (t < w && r <= t) ? S[static_cast<int64_t>(b0 + r) * lds + b0 + t] : (r == t ? 1.0 : 0.0);
   bool bad = false;
 #pragma unroll
-  for (int j = 0; j < CB; ++j) {
+  for (int j = 0; j < HB; ++j) {
     const double d = rdlane(a[j], j);
     double piv = sqrt(d);
     if (!(d > 0.0) || !isfinite(d)) {
@@ -392,22 +396,22 @@ __global__ __launch_bounds__(64) void potf2_inv_kernel(double* S, int64_t lds, i
     }
     a[j] = (t == j) ? piv : (t > j ? a[j] / piv : a[j]);
 #pragma unroll
-    for (int r = j + 1; r < CB; ++r) {
+    for (int r = j + 1; r < HB; ++r) {
       const double ajr = rdlane(a[j], r);
       a[r] = (t >= r) ? a[r] - ajr * a[j] : a[r];
     }
   }
   // column t of U^{-1}: T[i][t] = (delta_it - sum_{k>i} U[i][k] T[k][t]) / U[i][i]
-  double ti[CB];
+  double ti[HB];
 #pragma unroll
-  for (int i = CB - 1; i >= 0; --i) {
+  for (int i = HB - 1; i >= 0; --i) {
     double acc = (t == i) ? 1.0 : 0.0;
 #pragma unroll
-    for (int k = i + 1; k < CB; ++k) acc -= rdlane(a[i], k) * ti[k];
+    for (int k = i + 1; k < HB; ++k) acc -= rdlane(a[i], k) * ti[k];
     ti[i] = acc / rdlane(a[i], i);
   }
 #pragma unroll
-  for (int r = 0; r < CB; ++r) {
+  for (int r = 0; r < HB; ++r) {
     if (r < w && t < w) {
       S[static_cast<int64_t>(b0 + r) * lds + b0 + t] = (r <= t) ? a[r] : 0.0;
       T[r * w + t] = ti[r];
@@ -638,9 +642,9 @@ int cholesky_upper(double* S, int64_t lds, int n, int* d_status, double* d_scr, 
   // blocked right-looking: factor and invert the diagonal block, panel
   // U12 = U11^{-T} S12 as one GEMM (in place: each work-group reads all of its
   // columns before it writes them), trailing update S22 -= U12^T U12 (upper)
-  for (int b0 = 0; b0 < n; b0 += CB) {
-    const int w = (n - b0) < CB ? (n - b0) : CB;
-    potf2_inv_kernel<<<1, CB, 0, st>>>(S, lds, b0, w, d_scr, d_status);
+  for (int b0 = 0; b0 < n; b0 += HB) {
+    const int w = (n - b0) < HB ? (n - b0) : HB;
+    potf2_inv_kernel<<<1, 64, 0, st>>>(S, lds, b0, w, d_scr, d_status);
     CHEFSI_LAUNCHED("potf2_inv");
     const int rest = n - b0 - w;
     if (rest > 0) {
