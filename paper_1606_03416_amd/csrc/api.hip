@@ -649,7 +649,7 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
 #endif
     std::vector<int32_t> order;
     order.reserve(M);
-    if (CHEFSI_ELEM_ORDER >= 1 && (p->uniform || CHEFSI_ELEM_ORDER >= 2)) {
+    if (CHEFSI_ELEM_ORDER >= 1) {
       const int BX = std::min(nx, 4), BY = std::min(ny, 4);
       for (int by = 0; by < ny; by += BY)
         for (int bx = 0; bx < nx; bx += BX)
@@ -659,12 +659,19 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
     } else {
       order.resize(M);
       std::iota(order.begin(), order.end(), 0);
-      // mixed block sizes: heaviest work-groups first
-      if (!p->uniform) {
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-          return static_cast<int64_t>(p->rb[x]) * p->kpad[x] > static_cast<int64_t>(p->rb[y]) * p->kpad[y];
-        });
+    }
+    // mixed block sizes: grouped by row-block count (one launch per group),
+    // the walk order kept within a group
+    if (!p->uniform)
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return p->rb[x] > p->rb[y]; });
+    for (int e = 0; e < M; ++e) {
+      const int rb = p->rb[order[e]];
+      if (p->grp_rb.empty() || p->grp_rb.back() != rb) {
+        p->grp_rb.push_back(rb);
+        p->grp_start.push_back(e);
+        p->grp_count.push_back(0);
       }
+      ++p->grp_count.back();
     }
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;

@@ -64,7 +64,10 @@ struct Plan {
   int32_t* d_nbr = nullptr;     // [M*S]
   int32_t* d_rb = nullptr;      // [M] row blocks (ceil(J/16))
   int32_t* d_kpad = nullptr;    // [M] reduction rows padded to kPadK
-  int32_t* d_order = nullptr;   // [M] element processing order (heaviest first)
+  int32_t* d_order = nullptr;   // [M] element processing order, grouped by row-block count
+  // launch groups of the step kernels: elements order[start .. start+count)
+  // all have rb row blocks (one group for uniform plans)
+  std::vector<int> grp_rb, grp_start, grp_count;
   int64_t* d_rowoff = nullptr;  // [M+1]
   int64_t* d_hoff = nullptr;    // [M*S] block offsets in block-list layout
   int64_t* d_poff = nullptr;    // [M] panel offsets (elements)

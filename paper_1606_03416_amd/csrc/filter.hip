@@ -26,20 +26,6 @@ template <typename TC>
 struct Mfma;
 
 template <>
-struct Mfma<double> {
-  typedef double acc_t __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // output element q of a lane sits in row 4q + lane/16 (column lane%16)
-  static __device__ __forceinline__ int row(int lane, int q) { return 4 * q + (lane >> 4); }
-#ifndef CHEFSI_STEP_PAD64
-#define CHEFSI_STEP_PAD64 2
-#endif
-  static constexpr int pad = CHEFSI_STEP_PAD64;
-};
-
-template <>
 struct Mfma<float> {
   typedef float acc_t __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
@@ -81,13 +67,6 @@ __device__ __forceinline__ int xcd_linear(int b, int nwg) {
   return x * q + (x < r ? x : r) + i;
 }
 
-// FP64 MFMA 4x4x4 (4 blocks) with the A operand replicated over the blocks:
-// lane l supplies A[l%4][l/16] and B[l/16][l%16] and receives D[l/16][l%16].
-// On gfx950 this shape sustains a much higher FP64 rate than 16x16x4.
-__device__ __forceinline__ double mma4(double a, double b, double c) {
-  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-}
-
 // float <-> bf16 (round to nearest even; NaN stays NaN)
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -97,14 +76,8 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
-#ifndef CHEFSI_STEP_NT
-#define CHEFSI_STEP_NT 0
-#endif
-#ifndef CHEFSI_STEP_CG
-#define CHEFSI_STEP_CG 4
-#endif
 
-// Operand staging shared by both arithmetic paths: the k-major panel chunk
+// Operand staging of the FP32 path: the k-major panel chunk
 // (KC x JP) and the gathered neighbour rows (KC x TN) of the input block.
 template <typename TC, int RB, int LDA>
 struct Stage {
@@ -125,13 +98,7 @@ struct Stage {
     const int tid = threadIdx.x;
     const TC* pa = panel + static_cast<int64_t>(c) * (KC * JP);
 #pragma unroll
-    for (int q = 0; q < AQ; ++q) {
-#if CHEFSI_STEP_NT
-      ra[q] = __builtin_nontemporal_load(pa + tid + NT * q);
-#else
-      ra[q] = pa[tid + NT * q];
-#endif
-    }
+    for (int q = 0; q < AQ; ++q) ra[q] = pa[tid + NT * q];
 #pragma unroll
     for (int q = 0; q < BQ; ++q) {
       const int row = brow0 + (NT / TN) * q;
@@ -151,17 +118,18 @@ struct Stage {
   }
 };
 
-template <typename TC, typename TOUT, int RB, int EPI, int LDA>
-__device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* sA, TC* sB, int32_t* sK) {
-  using ST = Stage<TC, RB, LDA>;
+// FP32 step: v_mfma_f32_16x16x4f32 with FP32 accumulation; wave w owns
+// columns 32w .. 32w+31 and all rows, RB x 2 sixteen-square fragments.
+template <typename TOUT, int RB, int LDA>
+__device__ __forceinline__ void step_body_f32(const StepArgs& a, int K, int ct, float* sA, float* sB, int32_t* sK) {
+  using ST = Stage<float, RB, LDA>;
   constexpr int LDB = ST::LDB;
-  constexpr bool F64 = std::is_same<TC, double>::value;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int ns = a.ns;
   ST st;
-  st.panel = static_cast<const TC*>(a.panel) + a.poff[K];
+  st.panel = static_cast<const float*>(a.panel) + a.poff[K];
   // the global row of every concatenated neighbour row, staged once in LDS so
   // that the operand prefetch needs no dependent global load
   {
@@ -170,7 +138,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* 
     for (int t = tid; t < kp; t += NT) sK[t] = km[t];
   }
   st.kmap = sK;
-  st.in = static_cast<const TC*>(a.in);
+  st.in = static_cast<const float*>(a.in);
   st.ldi = a.ldi;
   st.j0 = ct * TN;
   st.bcol = tid & (TN - 1);
@@ -180,17 +148,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* 
   const int nch = a.kpad[K] / KC;
   __syncthreads();
 
-  // FP64: wave w owns rows 4*RB*w .. +4*RB (RB four-row fragments) and all 128
-  // columns (8 sixteen-column fragments), one accumulator value per fragment.
-  // FP32: wave w owns columns 32w .. 32w+31 and all rows, 16x16x4 fragments.
-  constexpr int NA = RB;
-  constexpr int NB = F64 ? 8 : 2;
-  using acc_t = typename std::conditional<F64, double, typename Mfma<float>::acc_t>::type;
-  acc_t acc[NA][NB];
+  using acc_t = typename Mfma<float>::acc_t;
+  acc_t acc[RB][2];
 #pragma unroll
-  for (int r = 0; r < NA; ++r)
+  for (int r = 0; r < RB; ++r)
 #pragma unroll
-    for (int c2 = 0; c2 < NB; ++c2) acc[r][c2] = acc_t{};
+    for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = acc_t{};
 
   st.gload(0);
   st.sstore(sA, sB);
@@ -198,154 +161,64 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int K, int ct, TC* 
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
     if (c + 1 < nch) st.gload(c + 1);
-    const TC* A = sA + buf * (KC * LDA);
-    const TC* B = sB + buf * (KC * LDB);
+    const float* A = sA + buf * (KC * LDA);
+    const float* B = sB + buf * (KC * LDB);
 #pragma unroll
     for (int kk = 0; kk < KC / 4; ++kk) {
       const int krow = kk * 4 + (lane >> 4);
-      TC av[NA], bv[NB];
-      if constexpr (F64) {
+      float av[RB], bv[2];
 #pragma unroll
-        for (int r = 0; r < NA; ++r) av[r] = A[krow * LDA + wave * 4 * RB + 4 * r + (lane & 3)];
+      for (int r = 0; r < RB; ++r) av[r] = A[krow * LDA + r * 16 + (lane & 15)];
 #pragma unroll
-        for (int c2 = 0; c2 < NB; ++c2) bv[c2] = B[krow * LDB + 16 * c2 + (lane & 15)];
+      for (int c2 = 0; c2 < 2; ++c2) bv[c2] = B[krow * LDB + wave * 32 + c2 * 16 + (lane & 15)];
 #pragma unroll
-        for (int r = 0; r < NA; ++r)
+      for (int r = 0; r < RB; ++r)
 #pragma unroll
-          for (int c2 = 0; c2 < NB; ++c2) acc[r][c2] = mma4(av[r], bv[c2], acc[r][c2]);
-      } else {
-#pragma unroll
-        for (int r = 0; r < NA; ++r) av[r] = A[krow * LDA + r * 16 + (lane & 15)];
-#pragma unroll
-        for (int c2 = 0; c2 < NB; ++c2) bv[c2] = B[krow * LDB + wave * 32 + c2 * 16 + (lane & 15)];
-#pragma unroll
-        for (int r = 0; r < NA; ++r)
-#pragma unroll
-          for (int c2 = 0; c2 < NB; ++c2) acc[r][c2] = Mfma<float>::mma(av[r], bv[c2], acc[r][c2]);
-      }
+        for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = Mfma<float>::mma(av[r], bv[c2], acc[r][c2]);
     }
     if (c + 1 < nch) st.sstore(sA + (buf ^ 1) * (KC * LDA), sB + (buf ^ 1) * (KC * LDB));
     __syncthreads();
   }
 
-  // (row, col, value) of every accumulator element held by this lane
-  auto for_each = [&](auto&& f) {
-#pragma unroll
-    for (int r = 0; r < NA; ++r)
-#pragma unroll
-      for (int c2 = 0; c2 < NB; ++c2) {
-        if constexpr (F64) {
-          f(wave * 4 * RB + 4 * r + (lane >> 4), j0 + 16 * c2 + (lane & 15), acc[r][c2]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            f(r * 16 + Mfma<float>::row(lane, q), j0 + wave * 32 + c2 * 16 + (lane & 15), acc[r][c2][q]);
-        }
-      }
-  };
-
   const int JK = a.J[K];
   const int64_t g0 = a.rowoff[K];
-  const TC* in = st.in;
+  const float* in = st.in;
   const int64_t ldi = st.ldi;
-  if constexpr (EPI == 0) {
-    const TC alpha = static_cast<TC>(a.coef[0]);
-    const TC beta = static_cast<TC>(a.coef[1]);
-    const TC cc = static_cast<TC>(a.coef[2]);
-    const TC* prev = static_cast<const TC*>(a.prev);
-    TOUT* out = static_cast<TOUT*>(a.out);
-    for_each([&](int i, int j, TC v0) {
-      if (i < JK && j < ns) {
-        const int64_t g = g0 + i;
-        TC v = alpha * (v0 - cc * in[g * ldi + j]);
-        if (prev != nullptr) v -= beta * prev[g * a.ldp + j];
-        out[g * a.ldo + j] = static_cast<TOUT>(v);
-      }
-    });
-  } else {
-    // residual partial sums over the element's rows: sum_i (H x - theta x)_i^2
-    static_assert(F64, "residual epilogue is FP64");
-    double* red = reinterpret_cast<double*>(sB);   // free after the main loop
+  const float alpha = static_cast<float>(a.coef[0]);
+  const float beta = static_cast<float>(a.coef[1]);
+  const float cc = static_cast<float>(a.coef[2]);
+  const float* prev = static_cast<const float*>(a.prev);
+  TOUT* out = static_cast<TOUT*>(a.out);
 #pragma unroll
-    for (int c2 = 0; c2 < NB; ++c2) {
-      const int jl = 16 * c2 + (lane & 15);
-      const int j = j0 + jl;
-      const double th = (j < ns) ? a.theta[j] : 0.0;
-      double s = 0.0;
+  for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int r = 0; r < NA; ++r) {
-        const int i = wave * 4 * RB + 4 * r + (lane >> 4);
+    for (int c2 = 0; c2 < 2; ++c2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = r * 16 + Mfma<float>::row(lane, q);
+        const int j = j0 + wave * 32 + c2 * 16 + (lane & 15);
         if (i < JK && j < ns) {
-          const double v = static_cast<double>(acc[r][c2]) - th * static_cast<double>(in[(g0 + i) * ldi + j]);
-          s += v * v;
+          const int64_t g = g0 + i;
+          float v = alpha * (acc[r][c2][q] - cc * in[g * ldi + j]);
+          if (prev != nullptr) v -= beta * prev[g * a.ldp + j];
+          out[g * a.ldo + j] = static_cast<TOUT>(v);
         }
       }
-      s += __shfl_xor(s, 16);
-      s += __shfl_xor(s, 32);
-      if (lane < 16) red[wave * TN + jl] = s;
-    }
-    __syncthreads();
-    if (tid < TN && j0 + tid < ns) {
-      const double s = red[tid] + red[TN + tid] + red[2 * TN + tid] + red[3 * TN + tid];
-      a.part[static_cast<int64_t>(K) * ns + j0 + tid] = s;
-    }
-  }
 }
 
-// UNIFORM_RB > 0: every element has UNIFORM_RB row blocks; 0: switch per element.
-template <typename TC, typename TOUT, int EPI, int UNIFORM_RB>
-__global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
-  constexpr int MAXRB = UNIFORM_RB > 0 ? UNIFORM_RB : 8;
-  constexpr int LDA = MAXRB * 16 + Mfma<TC>::pad;
-  constexpr int LDB = TN + Mfma<TC>::pad;
-  __shared__ TC sA[2 * KC * LDA];
-  __shared__ TC sB[2 * KC * LDB];
+// One launch covers elements with RB row blocks (order[0 .. M)).
+template <typename TOUT, int RB>
+__global__ __launch_bounds__(NT) void step_kernel_f32(StepArgs a) {
+  constexpr int LDA = RB * 16 + Mfma<float>::pad;
+  constexpr int LDB = TN + Mfma<float>::pad;
+  __shared__ float sA[2 * KC * LDA];
+  __shared__ float sB[2 * KC * LDB];
   __shared__ int32_t sK[7 * kMaxJ];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
-#ifndef CHEFSI_STEP_ORDER
-#define CHEFSI_STEP_ORDER 0
-#endif
-#if CHEFSI_STEP_ORDER == 0
   // column-tile major: the work-groups in flight share one column slab of X
   const int ct = id / a.M;
   const int e = id - ct * a.M;
-#elif CHEFSI_STEP_ORDER == 1
-  // element major: the column tiles of one element run together (its H panel
-  // is read from HBM once per step)
-  const int nct = (a.ns + TN - 1) / TN;
-  const int e = id / nct;
-  const int ct = id - e * nct;
-#else
-  // groups of CHEFSI_STEP_CG column tiles of one element run together, the
-  // groups column-major
-  constexpr int CG = CHEFSI_STEP_CG;
-  const int nct = (a.ns + TN - 1) / TN;
-  const int ngrp = (nct + CG - 1) / CG;
-  int g = id / (a.M * CG);
-  int rem = id - g * (a.M * CG);
-  int e = rem / CG;
-  int ct = g * CG + (rem - e * CG);
-  if (g == ngrp - 1 && nct % CG != 0) {   // last, partial group
-    const int cg = nct - g * CG;
-    e = rem / cg;
-    ct = g * CG + (rem - e * cg);
-  }
-#endif
-  const int K = a.order[e];
-  if constexpr (UNIFORM_RB > 0) {
-    step_body<TC, TOUT, UNIFORM_RB, EPI, LDA>(a, K, ct, sA, sB, sK);
-  } else {
-    switch (a.rbv[K]) {
-      case 1: step_body<TC, TOUT, 1, EPI, LDA>(a, K, ct, sA, sB, sK); break;
-      case 2: step_body<TC, TOUT, 2, EPI, LDA>(a, K, ct, sA, sB, sK); break;
-      case 3: step_body<TC, TOUT, 3, EPI, LDA>(a, K, ct, sA, sB, sK); break;
-      case 4: step_body<TC, TOUT, 4, EPI, LDA>(a, K, ct, sA, sB, sK); break;
-      case 5: step_body<TC, TOUT, 5, EPI, LDA>(a, K, ct, sA, sB, sK); break;
-      case 6: step_body<TC, TOUT, 6, EPI, LDA>(a, K, ct, sA, sB, sK); break;
-      case 7: step_body<TC, TOUT, 7, EPI, LDA>(a, K, ct, sA, sB, sK); break;
-      default: step_body<TC, TOUT, 8, EPI, LDA>(a, K, ct, sA, sB, sK); break;
-    }
-  }
+  step_body_f32<TOUT, RB, LDA>(a, a.order[e], ct, sA, sB, sK);
 }
 
 // ---------------------------------------------------------------- BF16 path
@@ -371,9 +244,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #ifndef CHEFSI_B16_WAVES
 #define CHEFSI_B16_WAVES 4
 #endif
-constexpr int BNC = CHEFSI_B16_NC;     // 16-column fragments per wave
 constexpr int BNT = 64 * CHEFSI_B16_WAVES;  // threads per work-group
-constexpr int BTN = CHEFSI_B16_WAVES * 16 * BNC;  // columns per work-group
+// 16-column fragments per wave: CHEFSI_B16_NC for elements of <= 64 rows,
+// 2 for larger ones (register budget)
+template <int RB>
+constexpr int b16_nc() { return RB <= 4 ? CHEFSI_B16_NC : 2; }
 
 struct StepArgsB {
   const uint16_t* panel;
@@ -398,6 +273,8 @@ struct StepArgsB {
 template <bool F64OUT, int RB>
 __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct, int32_t* sG) {
   constexpr int JP = RB * 16;
+  constexpr int BNC = b16_nc<RB>();
+  constexpr int BTN = CHEFSI_B16_WAVES * 16 * BNC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q = lane >> 4, l16 = lane & 15;
   const int ngrp = a.kpad8[K] >> 3;
@@ -498,33 +375,24 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
 #ifndef CHEFSI_B16_WPE
 #define CHEFSI_B16_WPE 3
 #endif
-template <bool F64OUT, int UNIFORM_RB>
-__global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(CHEFSI_B16_WPE))) void step_kernel_b16(StepArgsB a) {
+template <bool F64OUT, int RB>
+__global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(RB <= 4 ? CHEFSI_B16_WPE : 2))) void step_kernel_b16(StepArgsB a) {
   __shared__ int32_t sG[7 * kMaxJ / 8];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
   const int ct = id / a.M;
   const int e = id - ct * a.M;
-  const int K = a.order[e];
-  if constexpr (UNIFORM_RB > 0) {
-    step_body_b16<F64OUT, UNIFORM_RB>(a, K, ct, sG);
-  } else {
-    switch (a.rbv[K]) {
-      case 1: step_body_b16<F64OUT, 1>(a, K, ct, sG); break;
-      case 2: step_body_b16<F64OUT, 2>(a, K, ct, sG); break;
-      case 3: step_body_b16<F64OUT, 3>(a, K, ct, sG); break;
-      case 4: step_body_b16<F64OUT, 4>(a, K, ct, sG); break;
-      case 5: step_body_b16<F64OUT, 5>(a, K, ct, sG); break;
-      case 6: step_body_b16<F64OUT, 6>(a, K, ct, sG); break;
-      case 7: step_body_b16<F64OUT, 7>(a, K, ct, sG); break;
-      default: step_body_b16<F64OUT, 8>(a, K, ct, sG); break;
-    }
-  }
+  step_body_b16<F64OUT, RB>(a, a.order[e], ct, sG);
 }
 
 template <bool F64OUT>
-void dispatch_step_b16(const Plan& p, const StepArgsB& a, dim3 grid, hipStream_t st) {
-  if (p.uniform) {
-    switch (p.maxRB) {
+void dispatch_step_b16(const Plan& p, StepArgsB a, int ns, hipStream_t st) {
+  // one launch per row-block class of elements
+  for (size_t gi = 0; gi < p.grp_rb.size(); ++gi) {
+    a.order = p.d_order + p.grp_start[gi];
+    a.M = p.grp_count[gi];
+    const int btn = CHEFSI_B16_WAVES * 16 * (p.grp_rb[gi] <= 4 ? CHEFSI_B16_NC : 2);
+    dim3 grid(static_cast<unsigned>(ceil_div(ns, btn) * a.M));
+    switch (p.grp_rb[gi]) {
       case 1: step_kernel_b16<F64OUT, 1><<<grid, BNT, 0, st>>>(a); break;
       case 2: step_kernel_b16<F64OUT, 2><<<grid, BNT, 0, st>>>(a); break;
       case 3: step_kernel_b16<F64OUT, 3><<<grid, BNT, 0, st>>>(a); break;
@@ -534,8 +402,6 @@ void dispatch_step_b16(const Plan& p, const StepArgsB& a, dim3 grid, hipStream_t
       case 7: step_kernel_b16<F64OUT, 7><<<grid, BNT, 0, st>>>(a); break;
       default: step_kernel_b16<F64OUT, 8><<<grid, BNT, 0, st>>>(a); break;
     }
-  } else {
-    step_kernel_b16<F64OUT, 0><<<grid, BNT, 0, st>>>(a);
   }
 }
 
@@ -588,6 +454,9 @@ __global__ __launch_bounds__(256) void to_tiles_b16_kernel(const double* X, int6
 #define CHEFSI_F64_NCF 2
 #endif
 constexpr int FKC = CHEFSI_F64_KC;
+#ifndef CHEFSI_F64_LB
+#define CHEFSI_F64_LB 2
+#endif
 
 template <int RB>
 constexpr int f64_lda() { return RB * 16 + ((RB & 1) ? 0 : 16); }
@@ -620,14 +489,15 @@ __device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, 
   const int bcol = j0 + 2 * bcp;
   __syncthreads();
 
-  double2 ra[AV], rb[BV];
+  static_assert(AV >= 1 && AV <= 2, "panel chunk of at most two 16-byte loads per thread");
+  // panel chunk: this thread's 16-byte pieces tid and tid + NT (the second
+  // only when the chunk has that many; clamped to a valid address otherwise)
+  constexpr int APC = FKC * JP / 2;
+  double2 ra0, ra1, rb[BV];
   auto gload = [&](int c) {
     const double* pa = panel + static_cast<int64_t>(c) * (FKC * JP);
-#pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int idx = tid + NT * v;
-      if (idx < FKC * JP / 2) ra[v] = *reinterpret_cast<const double2*>(pa + 2 * idx);
-    }
+    ra0 = *reinterpret_cast<const double2*>(pa + 2 * min(tid, APC - 1));
+    if constexpr (AV == 2) ra1 = *reinterpret_cast<const double2*>(pa + 2 * min(tid + NT, APC - 1));
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int g = sK[c * FKC + v * BROWS + brow];
@@ -645,13 +515,10 @@ __device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, 
     }
   };
   auto sstore = [&](double* A, double* B) {
-#pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int idx = tid + NT * v;
-      if (idx < FKC * JP / 2) {
-        const int e = 2 * idx;
-        *reinterpret_cast<double2*>(A + (e / JP) * LDA + (e % JP)) = ra[v];
-      }
+    if (tid < APC) *reinterpret_cast<double2*>(A + ((2 * tid) / JP) * LDA + (2 * tid) % JP) = ra0;
+    if constexpr (AV == 2) {
+      const int i1 = tid + NT;
+      if (i1 < APC) *reinterpret_cast<double2*>(A + ((2 * i1) / JP) * LDA + (2 * i1) % JP) = ra1;
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) *reinterpret_cast<double2*>(B + (v * BROWS + brow) * LDB + 2 * bcp) = rb[v];
@@ -743,15 +610,10 @@ __device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, 
   }
 }
 
-// UNIFORM_RB > 0: every element has UNIFORM_RB row blocks; 0: switch per element.
-template <int EPI, int UNIFORM_RB, int NCF>
-#ifndef CHEFSI_F64_LB
-#define CHEFSI_F64_LB 2
-#endif
+template <int EPI, int RB, int NCF>
 __global__ __launch_bounds__(NT, CHEFSI_F64_LB) void step_kernel_f64(StepArgs a) {
-  constexpr int MAXRB = UNIFORM_RB > 0 ? UNIFORM_RB : 8;
-  constexpr int LDAM = f64_lda<MAXRB>();
-  __shared__ __attribute__((aligned(16))) double sA[2 * FKC * LDAM];
+  constexpr int LDA = f64_lda<RB>();
+  __shared__ __attribute__((aligned(16))) double sA[2 * FKC * LDA];
   __shared__ __attribute__((aligned(16))) double sB[2 * FKC * (64 * NCF + 16)];
   __shared__ int32_t sK[7 * kMaxJ];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
@@ -763,67 +625,56 @@ __global__ __launch_bounds__(NT, CHEFSI_F64_LB) void step_kernel_f64(StepArgs a)
   const int cg = (2 * g + 2 <= nct) ? 2 : 1;
   const int e = rem / cg;
   const int ct = 2 * g + (rem - e * cg);
-  const int K = a.order[e];
-  if constexpr (UNIFORM_RB > 0) {
-    step_body_f64<EPI, UNIFORM_RB, NCF, LDAM>(a, K, ct, sA, sB, sK);
-  } else {
-    switch (a.rbv[K]) {
-      case 1: step_body_f64<EPI, 1, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
-      case 2: step_body_f64<EPI, 2, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
-      case 3: step_body_f64<EPI, 3, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
-      case 4: step_body_f64<EPI, 4, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
-      case 5: step_body_f64<EPI, 5, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
-      case 6: step_body_f64<EPI, 6, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
-      case 7: step_body_f64<EPI, 7, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
-      default: step_body_f64<EPI, 8, NCF, LDAM>(a, K, ct, sA, sB, sK); break;
-    }
-  }
+  step_body_f64<EPI, RB, NCF, LDA>(a, a.order[e], ct, sA, sB, sK);
 }
 
 template <int EPI>
-int dispatch_step_f64(const Plan& p, const StepArgs& a, int ns, hipStream_t st) {
-  // 64*NCF columns per work-group (at most 128 when an element has > 64 rows)
-  const int ncf = (p.uniform && p.maxRB <= 4) ? CHEFSI_F64_NCF : (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2);
-  const int64_t nwg = ceil_div(ns, 64 * ncf) * p.M;
-  if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
-  dim3 grid(static_cast<unsigned>(nwg)), block(NT);
-  if (p.uniform) {
-    switch (p.maxRB) {
+int dispatch_step_f64(const Plan& p, StepArgs a, int ns, hipStream_t st) {
+  // one launch per row-block class: 64*NCF columns per work-group, at most
+  // 128 for elements with more than 64 rows
+  for (size_t gi = 0; gi < p.grp_rb.size(); ++gi) {
+    const int rb = p.grp_rb[gi];
+    a.order = p.d_order + p.grp_start[gi];
+    a.M = p.grp_count[gi];
+    const int ncf = rb <= 4 ? CHEFSI_F64_NCF : (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2);
+    const int64_t nwg = ceil_div(ns, 64 * ncf) * a.M;
+    if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
+    dim3 grid(static_cast<unsigned>(nwg)), block(NT);
+    constexpr int N2 = CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2;
+    switch (rb) {
       case 1: step_kernel_f64<EPI, 1, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
       case 2: step_kernel_f64<EPI, 2, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
       case 3: step_kernel_f64<EPI, 3, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
       case 4: step_kernel_f64<EPI, 4, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
-      case 5: step_kernel_f64<EPI, 5, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a); break;
-      case 6: step_kernel_f64<EPI, 6, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a); break;
-      case 7: step_kernel_f64<EPI, 7, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a); break;
-      default: step_kernel_f64<EPI, 8, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a); break;
+      case 5: step_kernel_f64<EPI, 5, N2><<<grid, block, 0, st>>>(a); break;
+      case 6: step_kernel_f64<EPI, 6, N2><<<grid, block, 0, st>>>(a); break;
+      case 7: step_kernel_f64<EPI, 7, N2><<<grid, block, 0, st>>>(a); break;
+      default: step_kernel_f64<EPI, 8, N2><<<grid, block, 0, st>>>(a); break;
     }
-  } else {
-    step_kernel_f64<EPI, 0, (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2)><<<grid, block, 0, st>>>(a);
   }
   CHEFSI_LAUNCHED("cheb_step_f64");
   return CHEFSI_OK;
 }
 
-template <typename TC, typename TOUT, int EPI>
-int dispatch_step(const Plan& p, const StepArgs& a, int ns, hipStream_t st) {
-  const int64_t nct = ceil_div(ns, TN);
-  const int64_t nwg = nct * p.M;
-  if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
-  dim3 grid(static_cast<unsigned>(nwg)), block(NT);
-  if (p.uniform) {
-    switch (p.maxRB) {
-      case 1: step_kernel<TC, TOUT, EPI, 1><<<grid, block, 0, st>>>(a); break;
-      case 2: step_kernel<TC, TOUT, EPI, 2><<<grid, block, 0, st>>>(a); break;
-      case 3: step_kernel<TC, TOUT, EPI, 3><<<grid, block, 0, st>>>(a); break;
-      case 4: step_kernel<TC, TOUT, EPI, 4><<<grid, block, 0, st>>>(a); break;
-      case 5: step_kernel<TC, TOUT, EPI, 5><<<grid, block, 0, st>>>(a); break;
-      case 6: step_kernel<TC, TOUT, EPI, 6><<<grid, block, 0, st>>>(a); break;
-      case 7: step_kernel<TC, TOUT, EPI, 7><<<grid, block, 0, st>>>(a); break;
-      default: step_kernel<TC, TOUT, EPI, 8><<<grid, block, 0, st>>>(a); break;
+template <typename TOUT>
+int dispatch_step_f32(const Plan& p, StepArgs a, int ns, hipStream_t st) {
+  // one launch per row-block class of elements
+  for (size_t gi = 0; gi < p.grp_rb.size(); ++gi) {
+    a.order = p.d_order + p.grp_start[gi];
+    a.M = p.grp_count[gi];
+    const int64_t nwg = ceil_div(ns, TN) * a.M;
+    if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
+    dim3 grid(static_cast<unsigned>(nwg)), block(NT);
+    switch (p.grp_rb[gi]) {
+      case 1: step_kernel_f32<TOUT, 1><<<grid, block, 0, st>>>(a); break;
+      case 2: step_kernel_f32<TOUT, 2><<<grid, block, 0, st>>>(a); break;
+      case 3: step_kernel_f32<TOUT, 3><<<grid, block, 0, st>>>(a); break;
+      case 4: step_kernel_f32<TOUT, 4><<<grid, block, 0, st>>>(a); break;
+      case 5: step_kernel_f32<TOUT, 5><<<grid, block, 0, st>>>(a); break;
+      case 6: step_kernel_f32<TOUT, 6><<<grid, block, 0, st>>>(a); break;
+      case 7: step_kernel_f32<TOUT, 7><<<grid, block, 0, st>>>(a); break;
+      default: step_kernel_f32<TOUT, 8><<<grid, block, 0, st>>>(a); break;
     }
-  } else {
-    step_kernel<TC, TOUT, EPI, 0><<<grid, block, 0, st>>>(a);
   }
   CHEFSI_LAUNCHED("cheb_step");
   return CHEFSI_OK;
@@ -1100,8 +951,8 @@ int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_c
   if (dtype == CHEFSI_F32) {
     if (io.in_f64 || (io.prev && io.prev_f64))
       return fail(CHEFSI_ERR_ARG, "step: FP32 step needs FP32 inputs");
-    if (io.out_f64) return dispatch_step<float, double, 0>(p, a, ns, st);
-    return dispatch_step<float, float, 0>(p, a, ns, st);
+    if (io.out_f64) return dispatch_step_f32<double>(p, a, ns, st);
+    return dispatch_step_f32<float>(p, a, ns, st);
   }
   return fail(CHEFSI_ERR_UNSUPPORTED, "step: dtype");
 }
@@ -1113,8 +964,7 @@ int launch_step_b16(const Plan& p, const void* d_panel8, const double* d_coef, c
   if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(prev) | reinterpret_cast<uintptr_t>(d_panel8)) & 15u)
     return fail(CHEFSI_ERR_ARG, "step: BF16 buffers must be 16-byte aligned");
   if (!out_f64 && (reinterpret_cast<uintptr_t>(out) & 7u)) return fail(CHEFSI_ERR_ARG, "step: BF16 output alignment");
-  const int64_t nwg = ceil_div(ns, BTN) * p.M;
-  if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
+  if (ceil_div(ns, 32) * p.M > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
   StepArgsB a{};
   a.panel = static_cast<const uint16_t*>(d_panel8);
   a.poff8 = p.d_poff8;
@@ -1133,11 +983,10 @@ int launch_step_b16(const Plan& p, const void* d_panel8, const double* d_coef, c
   a.ldo = ldo;
   a.ns = ns;
   a.M = p.M;
-  dim3 grid(static_cast<unsigned>(nwg));
   if (out_f64)
-    dispatch_step_b16<true>(p, a, grid, st);
+    dispatch_step_b16<true>(p, a, ns, st);
   else
-    dispatch_step_b16<false>(p, a, grid, st);
+    dispatch_step_b16<false>(p, a, ns, st);
   CHEFSI_LAUNCHED("cheb_step_b16");
   return CHEFSI_OK;
 }
