@@ -40,8 +40,7 @@ int fail(int code, const std::string& msg);
 // ---------------------------------------------------------------- sizes
 constexpr int kMaxJ = 128;          // largest ALB count per element supported
 constexpr int kMaxLanczos = 64;     // largest Lanczos step count
-constexpr int kStepTN = 128;        // columns per work-group of the step kernel
-constexpr int kStepKC = 16;         // reduction rows staged per LDS chunk (FP64/FP32)
+constexpr int kStepKC = 16;         // reduction rows of an element padded to this (FP64/FP32 chunks)
 constexpr int kPadK = 32;           // reduction rows of an element padded to this (BF16 chunk)
 
 __host__ __device__ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }

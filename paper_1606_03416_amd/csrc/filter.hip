@@ -1,15 +1,16 @@
 // Chebyshev filter hot path for gfx950: block-sparse H^DG x multivector with
 // the three-term recurrence fused into the epilogue.
 //
-// One work-group computes the rows of one element K for kStepTN = 128
-// columns.  Its reduction runs over the concatenation of the stencil
-// neighbours' rows (eq. matvec_3: y_K = sum_{K' in N(K)} H_{K;K'} x_{K'}),
-// staged through LDS in chunks of kStepKC rows: the packed panel of H (k-major,
-// written once per call by the repack kernel) and the gathered neighbour rows
-// of the input block.  Four waves split the 128 columns; each wave keeps
-// RB x 2 MFMA 16x16 accumulators (RB = ceil(J_K/16)).  The recurrence
+// One work-group computes the rows of one element K for a tile of columns.
+// Its reduction runs over the concatenation of the stencil neighbours' rows
+// (eq. matvec_3: y_K = sum_{K' in N(K)} H_{K;K'} x_{K'}): the packed panel of
+// H (written once per call by the repack kernel) against the gathered
+// neighbour rows of the input block, on MFMA.  The recurrence
 // Y_{k+1} = alpha_k (H Y_k - c Y_k) - beta_k Y_{k-1} is applied in the
-// epilogue, so a step reads Y_k, Y_{k-1} and writes Y_{k+1} once.
+// epilogue, so a step reads Y_k, Y_{k-1} and writes Y_{k+1} once.  FP64 and
+// FP32 stage both operands through LDS; BF16 keeps its multivectors in 8-row
+// tiles and loads MFMA operands directly.  Elements are launched in classes of
+// equal row-block count (ceil(J_K/16)), one launch per class.
 #include <type_traits>
 
 #include "common.h"
@@ -18,23 +19,7 @@ namespace chefsi {
 
 namespace {
 
-constexpr int TN = kStepTN;
-constexpr int KC = kStepKC;
 constexpr int NT = 256;
-
-template <typename TC>
-struct Mfma;
-
-template <>
-struct Mfma<float> {
-  typedef float acc_t __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  // output element q of a lane sits in row 4(lane/16) + q (column lane%16)
-  static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
-  static constexpr int pad = 4;
-};
 
 struct StepArgs {
   const void* panel;
@@ -76,150 +61,6 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
-
-// Operand staging of the FP32 path: the k-major panel chunk
-// (KC x JP) and the gathered neighbour rows (KC x TN) of the input block.
-template <typename TC, int RB, int LDA>
-struct Stage {
-  static constexpr int JP = RB * 16;
-  static constexpr int LDB = TN + Mfma<TC>::pad;
-  static constexpr int AQ = (KC * JP) / NT;
-  static constexpr int BQ = (KC * TN) / NT;
-  TC ra[AQ];
-  TC rb[BQ];
-  const TC* panel;
-  const int32_t* kmap;   // LDS copy of the element's row map
-  const TC* in;
-  int64_t ldi;
-  int j0, bcol, brow0;
-  bool col_ok;
-
-  __device__ __forceinline__ void gload(int c) {
-    const int tid = threadIdx.x;
-    const TC* pa = panel + static_cast<int64_t>(c) * (KC * JP);
-#pragma unroll
-    for (int q = 0; q < AQ; ++q) ra[q] = pa[tid + NT * q];
-#pragma unroll
-    for (int q = 0; q < BQ; ++q) {
-      const int row = brow0 + (NT / TN) * q;
-      const int g = kmap[c * KC + row];
-      rb[q] = (g >= 0 && col_ok) ? in[static_cast<int64_t>(g) * ldi + j0 + bcol] : TC(0);
-    }
-  }
-  __device__ __forceinline__ void sstore(TC* A, TC* B) {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int q = 0; q < AQ; ++q) {
-      const int e = tid + NT * q;
-      A[(e / JP) * LDA + (e % JP)] = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < BQ; ++q) B[(brow0 + (NT / TN) * q) * LDB + bcol] = rb[q];
-  }
-};
-
-// FP32 step: v_mfma_f32_16x16x4f32 with FP32 accumulation; wave w owns
-// columns 32w .. 32w+31 and all rows, RB x 2 sixteen-square fragments.
-template <typename TOUT, int RB, int LDA>
-__device__ __forceinline__ void step_body_f32(const StepArgs& a, int K, int ct, float* sA, float* sB, int32_t* sK) {
-  using ST = Stage<float, RB, LDA>;
-  constexpr int LDB = ST::LDB;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int ns = a.ns;
-  ST st;
-  st.panel = static_cast<const float*>(a.panel) + a.poff[K];
-  // the global row of every concatenated neighbour row, staged once in LDS so
-  // that the operand prefetch needs no dependent global load
-  {
-    const int32_t* km = a.kmap + a.koff[K];
-    const int kp = a.kpad[K];
-    for (int t = tid; t < kp; t += NT) sK[t] = km[t];
-  }
-  st.kmap = sK;
-  st.in = static_cast<const float*>(a.in);
-  st.ldi = a.ldi;
-  st.j0 = ct * TN;
-  st.bcol = tid & (TN - 1);
-  st.brow0 = tid / TN;
-  st.col_ok = (st.j0 + st.bcol) < ns;
-  const int j0 = st.j0;
-  const int nch = a.kpad[K] / KC;
-  __syncthreads();
-
-  using acc_t = typename Mfma<float>::acc_t;
-  acc_t acc[RB][2];
-#pragma unroll
-  for (int r = 0; r < RB; ++r)
-#pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = acc_t{};
-
-  st.gload(0);
-  st.sstore(sA, sB);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) st.gload(c + 1);
-    const float* A = sA + buf * (KC * LDA);
-    const float* B = sB + buf * (KC * LDB);
-#pragma unroll
-    for (int kk = 0; kk < KC / 4; ++kk) {
-      const int krow = kk * 4 + (lane >> 4);
-      float av[RB], bv[2];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) av[r] = A[krow * LDA + r * 16 + (lane & 15)];
-#pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) bv[c2] = B[krow * LDB + wave * 32 + c2 * 16 + (lane & 15)];
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int c2 = 0; c2 < 2; ++c2) acc[r][c2] = Mfma<float>::mma(av[r], bv[c2], acc[r][c2]);
-    }
-    if (c + 1 < nch) st.sstore(sA + (buf ^ 1) * (KC * LDA), sB + (buf ^ 1) * (KC * LDB));
-    __syncthreads();
-  }
-
-  const int JK = a.J[K];
-  const int64_t g0 = a.rowoff[K];
-  const float* in = st.in;
-  const int64_t ldi = st.ldi;
-  const float alpha = static_cast<float>(a.coef[0]);
-  const float beta = static_cast<float>(a.coef[1]);
-  const float cc = static_cast<float>(a.coef[2]);
-  const float* prev = static_cast<const float*>(a.prev);
-  TOUT* out = static_cast<TOUT*>(a.out);
-#pragma unroll
-  for (int r = 0; r < RB; ++r)
-#pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = r * 16 + Mfma<float>::row(lane, q);
-        const int j = j0 + wave * 32 + c2 * 16 + (lane & 15);
-        if (i < JK && j < ns) {
-          const int64_t g = g0 + i;
-          float v = alpha * (acc[r][c2][q] - cc * in[g * ldi + j]);
-          if (prev != nullptr) v -= beta * prev[g * a.ldp + j];
-          out[g * a.ldo + j] = static_cast<TOUT>(v);
-        }
-      }
-}
-
-// One launch covers elements with RB row blocks (order[0 .. M)).
-template <typename TOUT, int RB>
-__global__ __launch_bounds__(NT) void step_kernel_f32(StepArgs a) {
-  constexpr int LDA = RB * 16 + Mfma<float>::pad;
-  constexpr int LDB = TN + Mfma<float>::pad;
-  __shared__ float sA[2 * KC * LDA];
-  __shared__ float sB[2 * KC * LDB];
-  __shared__ int32_t sK[7 * kMaxJ];
-  const int id = xcd_linear(blockIdx.x, gridDim.x);
-  // column-tile major: the work-groups in flight share one column slab of X
-  const int ct = id / a.M;
-  const int e = id - ct * a.M;
-  step_body_f32<TOUT, RB, LDA>(a, a.order[e], ct, sA, sB, sK);
-}
 
 // ---------------------------------------------------------------- BF16 path
 // BF16 storage and MFMA operands (v_mfma_f32_16x16x32_bf16), FP32
@@ -439,38 +280,71 @@ __global__ __launch_bounds__(256) void to_tiles_b16_kernel(const double* X, int6
   }
 }
 
-// ---------------------------------------------------------------- FP64 path
-// v_mfma_f64_16x16x4f64 (lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// output v of lane l is D[4v + l/16][l%16]).  A work-group takes one element
-// and 64*NCF columns (128 by default); wave w owns columns 16*NCF*w .. +16*NCF
-// and all of the element's rows, as RB x NCF sixteen-square fragments.  Operands are staged
-// through LDS in chunks of FKC reduction rows with 16-byte loads; the k-major
-// LDS rows are padded so that the two k rows a half-wave reads fall on
-// disjoint halves of the banks.
-#ifndef CHEFSI_F64_KC
-#define CHEFSI_F64_KC 8
-#endif
-#ifndef CHEFSI_F64_NCF
-#define CHEFSI_F64_NCF 2
-#endif
-constexpr int FKC = CHEFSI_F64_KC;
-#ifndef CHEFSI_F64_LB
-#define CHEFSI_F64_LB 2
-#endif
+// ------------------------------------------------------- FP64 / FP32 paths
+// v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; output v of lane l is D[4v + l/16][l%16] (FP64) or
+// D[4(l/16) + v][l%16] (FP32).  A work-group takes one element and 64*NCF
+// columns; wave w owns columns 16*NCF*w .. +16*NCF and all of the element's
+// rows, as RB x NCF sixteen-square fragments.  Operands are staged through LDS
+// in chunks of KC reduction rows with 16-byte loads; the k-major LDS rows are
+// padded so that the k rows one wave reads fall on disjoint banks.  The last
+// reduction step of a chunk runs after the barrier, behind the LDS reads of
+// the next chunk's first step.
+template <typename TC>
+struct MT;
 
-template <int RB>
-constexpr int f64_lda() { return RB * 16 + ((RB & 1) ? 0 : 16); }
+template <>
+struct MT<double> {
+  typedef double2 V;                     // one 16-byte load
+  static constexpr int W = 2;            // elements per load
+  static constexpr int KC = 8;           // reduction rows per LDS chunk
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+  // row strides: 2*ld = 32 (mod 64) banks
+  static constexpr int lda(int rb) { return rb * 16 + ((rb & 1) ? 0 : 16); }
+  static constexpr int ldb(int tn) { return tn + 16; }
+  static __device__ __forceinline__ V zero() { return make_double2(0.0, 0.0); }
+  static __device__ __forceinline__ void set(V& x, int e, double v) { (e == 0 ? x.x : x.y) = v; }
+};
 
-template <int EPI, int RB, int NCF, int LDAM>
-__device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, double* sA, double* sB, int32_t* sK) {
+template <>
+struct MT<float> {
+  typedef float4 V;
+  static constexpr int W = 4;
+  static constexpr int KC = 16;
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  // row strides: ld = 16 (mod 64) banks
+  static constexpr int lda(int rb) { return rb * 16 + (((16 - rb * 16) % 64) + 64) % 64; }
+  static constexpr int ldb(int tn) { return tn + 16; }
+  static __device__ __forceinline__ V zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  static __device__ __forceinline__ void set(V& x, int e, float v) {
+    (e == 0 ? x.x : e == 1 ? x.y : e == 2 ? x.z : x.w) = v;
+  }
+};
+
+template <typename TC, typename TOUT, int EPI, int RB, int NCF>
+__device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, TC* sA, TC* sB, int32_t* sK) {
+  using T = MT<TC>;
+  using V = typename T::V;
+  constexpr int KC2 = T::KC, W = T::W;
   constexpr int JP = RB * 16;
-  constexpr int LDA = f64_lda<RB>();
+  constexpr int LDA = T::lda(RB);
   constexpr int TNF = 64 * NCF;
-  constexpr int LDB = TNF + 16;
-  constexpr int ASZ = FKC * LDAM, BSZ = FKC * LDB;
-  constexpr int AV = (FKC * JP / 2 + NT - 1) / NT;   // 16-byte loads of the panel chunk per thread
-  constexpr int BROWS = 2 * NT / TNF;                // gathered rows per load round
-  constexpr int BV = FKC / BROWS;
+  constexpr int LDB = T::ldb(TNF);
+  constexpr int ASZ = KC2 * LDA, BSZ = KC2 * LDB;
+  constexpr int APC = KC2 * JP / W;                  // 16-byte pieces of a panel chunk
+  constexpr int AV = (APC + NT - 1) / NT;
+  constexpr int BROWS = NT * W / TNF;                // gathered rows per load round
+  constexpr int BV = KC2 / BROWS;
+  constexpr int S = KC2 / 4;                         // reduction steps per chunk
+  static_assert(AV >= 1 && AV <= 2 && BV >= 1 && S % 2 == 0, "chunk shape");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ns = a.ns;
   {
@@ -478,116 +352,117 @@ __device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, 
     const int kp = a.kpad[K];
     for (int t = tid; t < kp; t += NT) sK[t] = km[t];
   }
-  const double* panel = static_cast<const double*>(a.panel) + a.poff[K];
-  const double* in = static_cast<const double*>(a.in);
+  const TC* panel = static_cast<const TC*>(a.panel) + a.poff[K];
+  const TC* in = static_cast<const TC*>(a.in);
   const int64_t ldi = a.ldi;
   const int j0 = ct * TNF;
-  const int nch = a.kpad[K] / FKC;
-  const bool vec = ((ldi & 1) == 0) && ((reinterpret_cast<uintptr_t>(in) & 15u) == 0);
-  const int bcp = tid % (TNF / 2);
-  const int brow = tid / (TNF / 2);
-  const int bcol = j0 + 2 * bcp;
+  const int nch = a.kpad[K] / KC2;
+  const bool vec = (ldi % W) == 0 && (reinterpret_cast<uintptr_t>(in) & 15u) == 0;
+  const int bcp = tid % (TNF / W);
+  const int brow = tid / (TNF / W);
+  const int bcol = j0 + W * bcp;
   __syncthreads();
 
-  static_assert(AV >= 1 && AV <= 2, "panel chunk of at most two 16-byte loads per thread");
-  // panel chunk: this thread's 16-byte pieces tid and tid + NT (the second
-  // only when the chunk has that many; clamped to a valid address otherwise)
-  constexpr int APC = FKC * JP / 2;
-  double2 ra0, ra1, rb[BV];
+  // panel chunk: this thread's pieces tid and tid + NT (the second only when
+  // the chunk has that many; clamped to a valid address otherwise)
+  V ra0, ra1, rb[BV];
   auto gload = [&](int c) {
-    const double* pa = panel + static_cast<int64_t>(c) * (FKC * JP);
-    ra0 = *reinterpret_cast<const double2*>(pa + 2 * min(tid, APC - 1));
-    if constexpr (AV == 2) ra1 = *reinterpret_cast<const double2*>(pa + 2 * min(tid + NT, APC - 1));
+    const TC* pa = panel + static_cast<int64_t>(c) * (KC2 * JP);
+    ra0 = *reinterpret_cast<const V*>(pa + W * min(tid, APC - 1));
+    if constexpr (AV == 2) ra1 = *reinterpret_cast<const V*>(pa + W * min(tid + NT, APC - 1));
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
-      const int g = sK[c * FKC + v * BROWS + brow];
-      double2 x = make_double2(0.0, 0.0);
+      const int g = sK[c * KC2 + v * BROWS + brow];
+      V x = T::zero();
       if (g >= 0) {
-        const double* src = in + static_cast<int64_t>(g) * ldi + bcol;
-        if (vec && bcol + 1 < ns) {
-          x = *reinterpret_cast<const double2*>(src);
+        const TC* src = in + static_cast<int64_t>(g) * ldi + bcol;
+        if (vec && bcol + W - 1 < ns) {
+          x = *reinterpret_cast<const V*>(src);
         } else {
-          if (bcol < ns) x.x = src[0];
-          if (bcol + 1 < ns) x.y = src[1];
+#pragma unroll
+          for (int e = 0; e < W; ++e)
+            if (bcol + e < ns) T::set(x, e, src[e]);
         }
       }
       rb[v] = x;
     }
   };
-  auto sstore = [&](double* A, double* B) {
-    if (tid < APC) *reinterpret_cast<double2*>(A + ((2 * tid) / JP) * LDA + (2 * tid) % JP) = ra0;
+  auto sstore = [&](TC* A, TC* B) {
+    if (tid < APC) *reinterpret_cast<V*>(A + ((W * tid) / JP) * LDA + (W * tid) % JP) = ra0;
     if constexpr (AV == 2) {
       const int i1 = tid + NT;
-      if (i1 < APC) *reinterpret_cast<double2*>(A + ((2 * i1) / JP) * LDA + (2 * i1) % JP) = ra1;
+      if (i1 < APC) *reinterpret_cast<V*>(A + ((W * i1) / JP) * LDA + (W * i1) % JP) = ra1;
     }
 #pragma unroll
-    for (int v = 0; v < BV; ++v) *reinterpret_cast<double2*>(B + (v * BROWS + brow) * LDB + 2 * bcp) = rb[v];
+    for (int v = 0; v < BV; ++v) *reinterpret_cast<V*>(B + (v * BROWS + brow) * LDB + W * bcp) = rb[v];
   };
 
-  typedef double d4 __attribute__((ext_vector_type(4)));
-  d4 acc[RB][NCF];
+  using acc_t = typename T::acc_t;
+  acc_t acc[RB][NCF];
 #pragma unroll
   for (int r = 0; r < RB; ++r)
 #pragma unroll
-    for (int q = 0; q < NCF; ++q) acc[r][q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < NCF; ++q) acc[r][q] = acc_t{};
   const int cb = wave * (16 * NCF);
-  auto rd = [&](const double* A, const double* B, int kk, double (&av)[RB], double (&bv)[NCF]) {
+  TC fa[2][RB], fb[2][NCF];
+  auto rd = [&](const TC* A, const TC* B, int kk, int slot) {
     const int kr = 4 * kk + (lane >> 4);
 #pragma unroll
-    for (int r = 0; r < RB; ++r) av[r] = A[kr * LDA + 16 * r + (lane & 15)];
+    for (int r = 0; r < RB; ++r) fa[slot][r] = A[kr * LDA + 16 * r + (lane & 15)];
 #pragma unroll
-    for (int q = 0; q < NCF; ++q) bv[q] = B[kr * LDB + cb + 16 * q + (lane & 15)];
+    for (int q = 0; q < NCF; ++q) fb[slot][q] = B[kr * LDB + cb + 16 * q + (lane & 15)];
   };
-  auto mm = [&](const double (&av)[RB], const double (&bv)[NCF]) {
+  auto mm = [&](int slot) {
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int q = 0; q < NCF; ++q) acc[r][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[q], acc[r][q], 0, 0, 0);
+      for (int q = 0; q < NCF; ++q) acc[r][q] = T::mma(fa[slot][r], fb[slot][q], acc[r][q]);
   };
-  static_assert(FKC == 8, "two reduction steps per chunk");
-  double a0[RB], b0[NCF], a1[RB], b1[NCF];
   gload(0);
   sstore(sA, sB);
   __syncthreads();
-  if (nch > 0) rd(sA, sB, 0, a0, b0);
-  // the second reduction step of a chunk runs after the barrier, behind the
-  // LDS reads of the next chunk's first step
+  if (nch > 0) rd(sA, sB, 0, 0);
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
     if (c + 1 < nch) gload(c + 1);
-    rd(sA + buf * ASZ, sB + buf * BSZ, 1, a1, b1);
-    mm(a0, b0);
+#pragma unroll
+    for (int kk = 1; kk < S; ++kk) {
+      rd(sA + buf * ASZ, sB + buf * BSZ, kk, kk & 1);
+      mm((kk - 1) & 1);
+    }
     if (c + 1 < nch) sstore(sA + (buf ^ 1) * ASZ, sB + (buf ^ 1) * BSZ);
     __syncthreads();
-    if (c + 1 < nch) rd(sA + (buf ^ 1) * ASZ, sB + (buf ^ 1) * BSZ, 0, a0, b0);
-    mm(a1, b1);
+    if (c + 1 < nch) rd(sA + (buf ^ 1) * ASZ, sB + (buf ^ 1) * BSZ, 0, 0);
+    mm((S - 1) & 1);
   }
 
   const int JK = a.J[K];
   const int64_t g0 = a.rowoff[K];
   if constexpr (EPI == 0) {
-    const double alpha = a.coef[0], beta = a.coef[1], cc = a.coef[2];
-    const double* prev = static_cast<const double*>(a.prev);
-    double* out = static_cast<double*>(a.out);
+    const TC alpha = static_cast<TC>(a.coef[0]), beta = static_cast<TC>(a.coef[1]);
+    const TC cc = static_cast<TC>(a.coef[2]);
+    const TC* prev = static_cast<const TC*>(a.prev);
+    TOUT* out = static_cast<TOUT*>(a.out);
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = 16 * r + 4 * v + (lane >> 4);
+        const int i = 16 * r + T::row(lane, v);
 #pragma unroll
         for (int q = 0; q < NCF; ++q) {
           const int j = j0 + cb + 16 * q + (lane & 15);
           if (i < JK && j < ns) {
             const int64_t g = g0 + i;
-            double y = alpha * (acc[r][q][v] - cc * in[g * ldi + j]);
+            TC y = alpha * (acc[r][q][v] - cc * in[g * ldi + j]);
             if (prev != nullptr) y -= beta * prev[g * a.ldp + j];
-            out[g * a.ldo + j] = y;
+            out[g * a.ldo + j] = static_cast<TOUT>(y);
           }
         }
       }
   } else {
     // residual partial sums over the element's rows: sum_i (H x - theta x)_i^2;
     // each wave owns whole columns, so the sum needs no cross-wave step
+    static_assert(std::is_same<TC, double>::value, "residual epilogue is FP64");
 #pragma unroll
     for (int q = 0; q < NCF; ++q) {
       const int j = j0 + cb + 16 * q + (lane & 15);
@@ -597,7 +472,7 @@ __device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, 
       for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = 16 * r + 4 * v + (lane >> 4);
+          const int i = 16 * r + T::row(lane, v);
           if (i < JK && j < ns) {
             const double d = acc[r][q][v] - th * in[(g0 + i) * ldi + j];
             sum += d * d;
@@ -610,11 +485,14 @@ __device__ __forceinline__ void step_body_f64(const StepArgs& a, int K, int ct, 
   }
 }
 
-template <int EPI, int RB, int NCF>
-__global__ __launch_bounds__(NT, CHEFSI_F64_LB) void step_kernel_f64(StepArgs a) {
-  constexpr int LDA = f64_lda<RB>();
-  __shared__ __attribute__((aligned(16))) double sA[2 * FKC * LDA];
-  __shared__ __attribute__((aligned(16))) double sB[2 * FKC * (64 * NCF + 16)];
+#ifndef CHEFSI_MF_LB
+#define CHEFSI_MF_LB 2
+#endif
+template <typename TC, typename TOUT, int EPI, int RB, int NCF>
+__global__ __launch_bounds__(NT, CHEFSI_MF_LB) void step_kernel_mf(StepArgs a) {
+  using T = MT<TC>;
+  __shared__ __attribute__((aligned(16))) TC sA[2 * T::KC * T::lda(RB)];
+  __shared__ __attribute__((aligned(16))) TC sB[2 * T::KC * T::ldb(64 * NCF)];
   __shared__ int32_t sK[7 * kMaxJ];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
   // groups of two column tiles of one element run together (its panel is
@@ -625,55 +503,31 @@ __global__ __launch_bounds__(NT, CHEFSI_F64_LB) void step_kernel_f64(StepArgs a)
   const int cg = (2 * g + 2 <= nct) ? 2 : 1;
   const int e = rem / cg;
   const int ct = 2 * g + (rem - e * cg);
-  step_body_f64<EPI, RB, NCF, LDA>(a, a.order[e], ct, sA, sB, sK);
+  step_body_mf<TC, TOUT, EPI, RB, NCF>(a, a.order[e], ct, sA, sB, sK);
 }
 
-template <int EPI>
-int dispatch_step_f64(const Plan& p, StepArgs a, int ns, hipStream_t st) {
-  // one launch per row-block class: 64*NCF columns per work-group, at most
-  // 128 for elements with more than 64 rows
-  for (size_t gi = 0; gi < p.grp_rb.size(); ++gi) {
-    const int rb = p.grp_rb[gi];
-    a.order = p.d_order + p.grp_start[gi];
-    a.M = p.grp_count[gi];
-    const int ncf = rb <= 4 ? CHEFSI_F64_NCF : (CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2);
-    const int64_t nwg = ceil_div(ns, 64 * ncf) * a.M;
-    if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
-    dim3 grid(static_cast<unsigned>(nwg)), block(NT);
-    constexpr int N2 = CHEFSI_F64_NCF < 2 ? CHEFSI_F64_NCF : 2;
-    switch (rb) {
-      case 1: step_kernel_f64<EPI, 1, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
-      case 2: step_kernel_f64<EPI, 2, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
-      case 3: step_kernel_f64<EPI, 3, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
-      case 4: step_kernel_f64<EPI, 4, CHEFSI_F64_NCF><<<grid, block, 0, st>>>(a); break;
-      case 5: step_kernel_f64<EPI, 5, N2><<<grid, block, 0, st>>>(a); break;
-      case 6: step_kernel_f64<EPI, 6, N2><<<grid, block, 0, st>>>(a); break;
-      case 7: step_kernel_f64<EPI, 7, N2><<<grid, block, 0, st>>>(a); break;
-      default: step_kernel_f64<EPI, 8, N2><<<grid, block, 0, st>>>(a); break;
-    }
-  }
-  CHEFSI_LAUNCHED("cheb_step_f64");
-  return CHEFSI_OK;
-}
-
-template <typename TOUT>
-int dispatch_step_f32(const Plan& p, StepArgs a, int ns, hipStream_t st) {
-  // one launch per row-block class of elements
+#ifndef CHEFSI_MF_NCF
+#define CHEFSI_MF_NCF 2
+#endif
+template <typename TC, typename TOUT, int EPI>
+int dispatch_step_mf(const Plan& p, StepArgs a, int ns, hipStream_t st) {
+  // one launch per row-block class of elements, 64*NCF columns per work-group
+  constexpr int NCF = CHEFSI_MF_NCF;
   for (size_t gi = 0; gi < p.grp_rb.size(); ++gi) {
     a.order = p.d_order + p.grp_start[gi];
     a.M = p.grp_count[gi];
-    const int64_t nwg = ceil_div(ns, TN) * a.M;
+    const int64_t nwg = ceil_div(ns, 64 * NCF) * a.M;
     if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
     dim3 grid(static_cast<unsigned>(nwg)), block(NT);
     switch (p.grp_rb[gi]) {
-      case 1: step_kernel_f32<TOUT, 1><<<grid, block, 0, st>>>(a); break;
-      case 2: step_kernel_f32<TOUT, 2><<<grid, block, 0, st>>>(a); break;
-      case 3: step_kernel_f32<TOUT, 3><<<grid, block, 0, st>>>(a); break;
-      case 4: step_kernel_f32<TOUT, 4><<<grid, block, 0, st>>>(a); break;
-      case 5: step_kernel_f32<TOUT, 5><<<grid, block, 0, st>>>(a); break;
-      case 6: step_kernel_f32<TOUT, 6><<<grid, block, 0, st>>>(a); break;
-      case 7: step_kernel_f32<TOUT, 7><<<grid, block, 0, st>>>(a); break;
-      default: step_kernel_f32<TOUT, 8><<<grid, block, 0, st>>>(a); break;
+      case 1: step_kernel_mf<TC, TOUT, EPI, 1, NCF><<<grid, block, 0, st>>>(a); break;
+      case 2: step_kernel_mf<TC, TOUT, EPI, 2, NCF><<<grid, block, 0, st>>>(a); break;
+      case 3: step_kernel_mf<TC, TOUT, EPI, 3, NCF><<<grid, block, 0, st>>>(a); break;
+      case 4: step_kernel_mf<TC, TOUT, EPI, 4, NCF><<<grid, block, 0, st>>>(a); break;
+      case 5: step_kernel_mf<TC, TOUT, EPI, 5, NCF><<<grid, block, 0, st>>>(a); break;
+      case 6: step_kernel_mf<TC, TOUT, EPI, 6, NCF><<<grid, block, 0, st>>>(a); break;
+      case 7: step_kernel_mf<TC, TOUT, EPI, 7, NCF><<<grid, block, 0, st>>>(a); break;
+      default: step_kernel_mf<TC, TOUT, EPI, 8, NCF><<<grid, block, 0, st>>>(a); break;
     }
   }
   CHEFSI_LAUNCHED("cheb_step");
@@ -946,13 +800,13 @@ int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_c
   if (dtype == CHEFSI_F64) {
     if (!io.in_f64 || (io.prev && !io.prev_f64) || !io.out_f64)
       return fail(CHEFSI_ERR_ARG, "step: FP64 step needs FP64 operands");
-    return dispatch_step_f64<0>(p, a, ns, st);
+    return dispatch_step_mf<double, double, 0>(p, a, ns, st);
   }
   if (dtype == CHEFSI_F32) {
     if (io.in_f64 || (io.prev && io.prev_f64))
       return fail(CHEFSI_ERR_ARG, "step: FP32 step needs FP32 inputs");
-    if (io.out_f64) return dispatch_step_f32<double>(p, a, ns, st);
-    return dispatch_step_f32<float>(p, a, ns, st);
+    if (io.out_f64) return dispatch_step_mf<float, double, 0>(p, a, ns, st);
+    return dispatch_step_mf<float, float, 0>(p, a, ns, st);
   }
   return fail(CHEFSI_ERR_UNSUPPORTED, "step: dtype");
 }
@@ -1007,7 +861,7 @@ int launch_resid_partial(const Plan& p, const void* d_panel, const double* d_X, 
   a.ldi = ldx;
   a.theta = d_theta;
   a.part = d_part;
-  return dispatch_step_f64<1>(p, a, ns, st);
+  return dispatch_step_mf<double, double, 1>(p, a, ns, st);
 }
 
 int launch_colsum_sqrt(const double* d_part, int rows, int ns, double* d_out, hipStream_t st) {
