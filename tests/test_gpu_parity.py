@@ -93,6 +93,22 @@ def test_filter_diff_workload_block_mode(lib):
     assert relf(host(Y), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("ns,m", [(64, 10), (1, 3), (130, 7), (257, 2), (9, 1)])
+def test_filter_f32_shapes(lib, name, ns, m):
+    """FP32 storage and MFMA over every grid shape and ragged column count: the
+    error against the FP64 oracle is that of 24-bit mantissas."""
+    P = PROBLEMS[name]()
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    X = synth.make_start_block(P.J, ns)
+    a, b, a0 = 0.3, 5.5, -1.2
+    ref = oracle.chebyshev_filter(oracle.DenseOperator(H), X, m, a, b, a0)
+    plan = mkplan(lib, P)
+    Y = plan.filter(dev(P.packed()), dev(X), m, a, b, a0, dtype=lib.F32)
+    err = relf(host(Y), ref)
+    assert 1e-10 < err <= 1e-5
+
+
 def test_filter_f32_error_is_small(lib):
     P = synth.make_problem(synth.TINY)
     H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
