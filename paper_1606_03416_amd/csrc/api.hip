@@ -175,6 +175,7 @@ int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, 
       io.out = B[bo];
       io.ldo = LD[bo];
       io.out_f64 = true;
+      io.shifted = true;
       CHEFSI_TRY(launch_step(p, panel, dtype, coef + 3 * k, io, ns, st));
     }
     return CHEFSI_OK;
@@ -206,6 +207,7 @@ int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, 
     io.out = last ? static_cast<void*>(Y) : L[(k + 1) % 2];
     io.ldo = last ? ldy : ns;
     io.out_f64 = last;
+    io.shifted = true;
     CHEFSI_TRY(launch_step(p, panel, dtype, coef + 3 * k, io, ns, st));
   }
   return CHEFSI_OK;
@@ -356,7 +358,7 @@ size_t sweep_bytes(Plan& p, int ns, int dtype, int passes, int k) {
   const size_t base = c.used;
   Carver cf(nullptr, 0);
   FilterWs f;
-  carve_filter(cf, p, ns, dtype, dtype != CHEFSI_F64, f);
+  carve_filter(cf, p, ns, dtype, true, f);
   Carver co(nullptr, 0);
   OrthWs o;
   carve_orth(co, p.N, ns, o);
@@ -844,8 +846,7 @@ int chefsi_filter(chefsi_plan plan, const double* d_H, int m, double a, double b
     carve_filter(c, p, ns, dtype, true, f);
     CHEFSI_TRY(launch_set_bounds(a, b, a0, f.bounds, st));
     CHEFSI_TRY(launch_cheb_coef(f.bounds, m, f.coef, st));
-    if (m > 0)
-      CHEFSI_TRY(launch_repack(p, d_H, dtype, false, f.panel, st, dtype == CHEFSI_BF16 ? f.coef + 2 : nullptr));
+    if (m > 0) CHEFSI_TRY(launch_repack(p, d_H, dtype, false, f.panel, st, f.coef + 2));
     return run_filter(p, f.panel, dtype, f.coef, m, d_X, ldx, d_Y, ldy, ns, f, st);
   });
 }
@@ -965,14 +966,11 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
       {
         Carver cf(rest, rest_bytes);
         FilterWs f;
-        carve_filter(cf, p, ns, filter_dtype, filter_dtype != CHEFSI_F64, f);
-        const void* fpanel = panel64;
+        carve_filter(cf, p, ns, filter_dtype, true, f);
         CHEFSI_TRY(launch_cheb_coef(bnd, m, f.coef, st));
-        if (filter_dtype != CHEFSI_F64 && m > 0) {
-          CHEFSI_TRY(launch_repack(p, d_H, filter_dtype, false, f.panel, st,
-                                   filter_dtype == CHEFSI_BF16 ? f.coef + 2 : nullptr));
-          fpanel = f.panel;
-        }
+        // the filter's own panel carries H - cI (c of this call's bounds)
+        if (m > 0) CHEFSI_TRY(launch_repack(p, d_H, filter_dtype, false, f.panel, st, f.coef + 2));
+        const void* fpanel = f.panel;
         CHEFSI_TRY(mark(2));
         CHEFSI_TRY(run_filter(p, fpanel, filter_dtype, f.coef, m, d_X, ldx, Y, ns, ns, f, st));
       }

@@ -290,6 +290,12 @@ __global__ __launch_bounds__(256) void to_tiles_b16_kernel(const double* X, int6
 // padded so that the k rows one wave reads fall on disjoint banks.  The last
 // reduction step of a chunk runs after the barrier, behind the LDS reads of
 // the next chunk's first step.
+#ifndef CHEFSI_MF_KC64
+#define CHEFSI_MF_KC64 8
+#endif
+#ifndef CHEFSI_MF_KC32
+#define CHEFSI_MF_KC32 16
+#endif
 template <typename TC>
 struct MT;
 
@@ -297,7 +303,7 @@ template <>
 struct MT<double> {
   typedef double2 V;                     // one 16-byte load
   static constexpr int W = 2;            // elements per load
-  static constexpr int KC = 8;           // reduction rows per LDS chunk
+  static constexpr int KC = CHEFSI_MF_KC64;   // reduction rows per LDS chunk
   typedef double acc_t __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -314,7 +320,7 @@ template <>
 struct MT<float> {
   typedef float4 V;
   static constexpr int W = 4;
-  static constexpr int KC = 16;
+  static constexpr int KC = CHEFSI_MF_KC32;
   typedef float acc_t __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -438,7 +444,8 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
 
   const int JK = a.J[K];
   const int64_t g0 = a.rowoff[K];
-  if constexpr (EPI == 0) {
+  if constexpr (EPI == 0 || EPI == 2) {
+    // EPI 2: the panel carries H - cI
     const TC alpha = static_cast<TC>(a.coef[0]), beta = static_cast<TC>(a.coef[1]);
     const TC cc = static_cast<TC>(a.coef[2]);
     const TC* prev = static_cast<const TC*>(a.prev);
@@ -453,7 +460,7 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
           const int j = j0 + cb + 16 * q + (lane & 15);
           if (i < JK && j < ns) {
             const int64_t g = g0 + i;
-            TC y = alpha * (acc[r][q][v] - cc * in[g * ldi + j]);
+            TC y = (EPI == 2) ? alpha * acc[r][q][v] : alpha * (acc[r][q][v] - cc * in[g * ldi + j]);
             if (prev != nullptr) y -= beta * prev[g * a.ldp + j];
             out[g * a.ldo + j] = static_cast<TOUT>(y);
           }
@@ -763,7 +770,7 @@ int launch_const_coef3(double alpha, double beta, double c, double* d_coef, hipS
 int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h, void* d_panel,
                   hipStream_t st, const double* d_shift) {
   const unsigned fill_grid = grid_for(p.panel_elems);
-  RepackArgs ra{d_H, p.d_hoff, p.d_nbr, p.d_J, p.d_poff, p.d_rb, p.stencil, transpose_h, nullptr};
+  RepackArgs ra{d_H, p.d_hoff, p.d_nbr, p.d_J, p.d_poff, p.d_rb, p.stencil, transpose_h, d_shift};
   const int tiles = static_cast<int>(ceil_div(p.maxJ, 32) * ceil_div(p.maxJ, 32));
   dim3 grid(tiles, p.M * p.stencil);
   if (dtype == CHEFSI_F64) {
@@ -776,7 +783,6 @@ int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h,
     const unsigned fill8 = grid_for(p.panel8_elems);
     RepackArgs rb = ra;
     rb.poff = p.d_poff8;
-    rb.shift = d_shift;
     fill_kernel<uint16_t><<<fill8, 256, 0, st>>>(static_cast<uint16_t*>(d_panel), p.panel8_elems);
     repack_kernel<uint16_t, true><<<grid, 256, 0, st>>>(rb, static_cast<uint16_t*>(d_panel));
   } else {
@@ -800,11 +806,16 @@ int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_c
   if (dtype == CHEFSI_F64) {
     if (!io.in_f64 || (io.prev && !io.prev_f64) || !io.out_f64)
       return fail(CHEFSI_ERR_ARG, "step: FP64 step needs FP64 operands");
+    if (io.shifted) return dispatch_step_mf<double, double, 2>(p, a, ns, st);
     return dispatch_step_mf<double, double, 0>(p, a, ns, st);
   }
   if (dtype == CHEFSI_F32) {
     if (io.in_f64 || (io.prev && io.prev_f64))
       return fail(CHEFSI_ERR_ARG, "step: FP32 step needs FP32 inputs");
+    if (io.shifted) {
+      if (io.out_f64) return dispatch_step_mf<float, double, 2>(p, a, ns, st);
+      return dispatch_step_mf<float, float, 2>(p, a, ns, st);
+    }
     if (io.out_f64) return dispatch_step_mf<float, double, 0>(p, a, ns, st);
     return dispatch_step_mf<float, float, 0>(p, a, ns, st);
   }
