@@ -274,7 +274,7 @@ int run_orth_factor2(int64_t n, int ns, const double* Y, int64_t ldy, double* Y1
 int run_rr_factor2(Plan& p, const void* panel64, double* X, int64_t ldx, int ns, const double* T2, double* Ybuf,
                    double* ritz, double* resid, const RrWs& r, hipStream_t st) {
   CHEFSI_TRY(launch_const_coef(1.0, 0.0, r.coef, st));
-  StepIO io{X, ldx, true, nullptr, 0, true, r.W, ns, true};
+  StepIO io{X, ldx, true, nullptr, 0, true, r.W, ns, true, true};   // W = H Yhat1 (no c term)
   CHEFSI_TRY(launch_step(p, panel64, CHEFSI_F64, r.coef, io, ns, st));
   CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, X, ldx, r.W, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
@@ -299,7 +299,7 @@ int run_rr_factor2(Plan& p, const void* panel64, double* X, int64_t ldx, int ns,
 int run_rr(Plan& p, const void* panel64, const double* Yh, int64_t ldy, int ns, double* Xn,
            int64_t ldx, double* ritz, double* resid, double* Qout, const RrWs& r, hipStream_t st) {
   CHEFSI_TRY(launch_const_coef(1.0, 0.0, r.coef, st));
-  StepIO io{Yh, ldy, true, nullptr, 0, true, r.W, ns, true};
+  StepIO io{Yh, ldy, true, nullptr, 0, true, r.W, ns, true, true};   // W = H Yhat (no c term)
   CHEFSI_TRY(launch_step(p, panel64, CHEFSI_F64, r.coef, io, ns, st));
   // Hhat = Yhat^T (H Yhat) is symmetric: form its upper triangle and mirror it
   CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, Yh, ldy, r.W, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));

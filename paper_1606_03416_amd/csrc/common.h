@@ -132,7 +132,7 @@ struct StepIO {
   const void* in; int64_t ldi; bool in_f64;
   const void* prev; int64_t ldp; bool prev_f64;   // prev may be null
   void* out; int64_t ldo; bool out_f64;
-  bool shifted = false;   // the panel carries H - cI: out = alpha*(panel*in) - beta*prev
+  bool shifted = false;   // no c*in term: out = alpha*(panel*in) - beta*prev (the panel carries H - cI, or c = 0)
 };
 int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_coef,
                 const StepIO& io, int ns, hipStream_t st);

@@ -220,8 +220,18 @@ template <bool F64OUT, int RB>
 __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(RB <= 4 ? CHEFSI_B16_WPE : 2))) void step_kernel_b16(StepArgsB a) {
   __shared__ int32_t sG[7 * kMaxJ / 8];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
-  const int ct = id / a.M;
-  const int e = id - ct * a.M;
+#ifndef CHEFSI_B16_CG
+#define CHEFSI_B16_CG 1
+#endif
+  // groups of CG column tiles of one element run together (its panel is
+  // reused from L2), the groups column-major
+  constexpr int CG = CHEFSI_B16_CG;
+  const int nct = (a.ns + CHEFSI_B16_WAVES * 16 * b16_nc<RB>() - 1) / (CHEFSI_B16_WAVES * 16 * b16_nc<RB>());
+  const int g = id / (a.M * CG);
+  const int rem = id - g * (a.M * CG);
+  const int cg = (CG * g + CG <= nct) ? CG : nct - CG * g;
+  const int e = rem / cg;
+  const int ct = CG * g + (rem - e * cg);
   step_body_b16<F64OUT, RB>(a, a.order[e], ct, sG);
 }
 
