@@ -7,7 +7,7 @@
  * large-scale electronic structure calculations", arXiv:1606.03416) on a
  * block-sparse DG Hamiltonian held in GPU memory.
  *
- * Problem data (Sec. II A and Sec. II C 1 of the paper):
+ * Problem data (Sec. II A and Sec. II B 1 of the paper):
  *   - a periodic nx x ny x nz grid of M = nx*ny*nz elements, element id
  *     K = ix + nx*(iy + ny*iz);
  *   - J_K adaptive local basis functions in element K (alb_counts[K]);
@@ -91,7 +91,7 @@ const char* chefsi_version(void);
 const char* chefsi_last_error(void);
 
 /* ---------------------------------------------------------------- plan ----
- * Element grid, stencil and ALB counts (Sec. II A; Sec. II C 1, the element-
+ * Element grid, stencil and ALB counts (Sec. II A; Sec. II B 1, the element-
  * wise storage of H^DG).  alb_counts: host array of M int32, each in [1, 128].
  * stencil: 7 (self + 6 faces) or 5 (self + 4 in-plane faces).
  * Builds the neighbour, row-offset and block-offset tables, uploads them to

@@ -9,8 +9,12 @@ Everything here is float64 NumPy, written from the paper:
   * Algorithm 1 (the CheFSI cycle): bounds, Chebyshev filter, Cholesky-QR,
     Rayleigh-Ritz, subspace rotation;
   * eqs. matvec_1-matvec_3 (block-sparse H^DG times a block of vectors);
-  * Sec. II C 2 (Cholesky factorisation instead of QR/DGKS for the
+  * Sec. II B 2 (Cholesky factorisation instead of QR/DGKS for the
     orthonormalisation).
+After the cycle: Fermi-Dirac occupations and the diagonal density-matrix
+blocks (eq. densitymatrix, :mod:`oracle.density`), and the re-alignment of
+the coefficients to a new ALB basis (eqs. basis_rotation_1-3,
+:mod:`oracle.realign`).
 The adjoint (reverse-mode gradient) of one filter + Cholesky-QR +
 Rayleigh-Ritz pass is not in the paper; it follows the textbook reverse-mode
 rules stated in :mod:`oracle.adjoint`.
@@ -31,4 +35,10 @@ from .jacobi import jacobi_eigh  # noqa: F401
 from .adjoint import (  # noqa: F401
     filter_backward, cholesky_qr_backward, rayleigh_ritz_backward,
     loss_forward, loss_backward, restrict_to_pattern,
+)
+from .density import (  # noqa: F401
+    fermi_dirac, fermi_level, occupations, density_diag_blocks, density_dense, pack_blocks,
+)
+from .realign import (  # noqa: F401
+    overlap_blocks, realign, realign_dense, assemble_samples, element_samples,
 )

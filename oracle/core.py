@@ -243,7 +243,7 @@ def bounds_warm(ritz: np.ndarray, b: float):
 
 
 # ----------------------------------------------------------------------------
-# Cholesky-QR (Algorithm 1 step 3; Sec. II C 2)
+# Cholesky-QR (Algorithm 1 step 3; Sec. II B 2)
 # ----------------------------------------------------------------------------
 class NotPositiveDefinite(ArithmeticError):
     pass

@@ -30,10 +30,18 @@ in, Mezzadri 2007), symmetrised; off-diagonal blocks i.i.d. N(0, sigma^2).
 Packed ("block-list") layout handed to the library: for K = 0..M-1, for each
 slot s, the J_K x J_{K'_s} block in row-major order, back to back, float64.
 
+ALB samples for the basis re-alignment (Sec. II B 3): element K's J_K ALBs
+sampled on its own n_r grid points, V_K (n_r x J_K) with orthonormal columns
+(the DG basis is orthonormal), drawn as the first J_K columns of a Haar
+orthogonal n_r x n_r matrix; the next SCF step's basis is the orthonormalised
+V_K + delta G_K (G_K Gaussian), a nearby basis with a different span.  Stored
+element-major, each element as V_K^T (J_K rows of n_r samples), row-major.
+
 Random streams: numpy SeedSequence(base_seed, spawn_key=(purpose, K)), so any
 element's data can be regenerated on its own.  Purposes: 0 eigenvalues,
 1 Haar Q, 2 off-diagonal blocks, 3 start block X, 4 Lanczos start vector,
-5 mixed J_K draw, 6 finite-difference entry choice.
+5 mixed J_K draw, 6 finite-difference entry choice, 7 ALB samples,
+8 ALB change between SCF steps.
 """
 from __future__ import annotations
 
@@ -47,7 +55,15 @@ BASE_SEED = 1606
 # slot order: self, -x, +x, -y, +y, -z, +z
 SLOT_DIRS = ((0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1))
 
-PURPOSE_EIG, PURPOSE_HAAR, PURPOSE_OFFDIAG, PURPOSE_X0, PURPOSE_LANCZOS, PURPOSE_JDRAW, PURPOSE_FD = range(7)
+(PURPOSE_EIG, PURPOSE_HAAR, PURPOSE_OFFDIAG, PURPOSE_X0, PURPOSE_LANCZOS, PURPOSE_JDRAW, PURPOSE_FD,
+ PURPOSE_ALB, PURPOSE_ALB_STEP) = range(9)
+
+# Boltzmann constant in Hartree per kelvin (CODATA 2018) and the electronic
+# temperature of the paper's runs (Sec. III: 300 K Fermi-Dirac smearing).
+BOLTZMANN_HA_PER_K = 3.1668115634556e-6
+KT_300K = 300.0 * BOLTZMANN_HA_PER_K
+# Grid points per element for the ALB samples (an 8 x 8 x 8 element grid).
+NR_PER_ELEMENT = 512
 
 
 def rng_for(purpose: int, key: int = 0, base_seed: int = BASE_SEED) -> np.random.Generator:
@@ -264,3 +280,46 @@ def fd_entries(P: BlockProblem, count: int, base_seed: int = BASE_SEED):
         b = P.blocks[K][s]
         out.append((K, s, int(g.integers(0, b.shape[0])), int(g.integers(0, b.shape[1]))))
     return out
+
+
+def occupied_count(ns: int) -> float:
+    """Occupied orbital pairs N_e / 2 for an ns-state block: the lowest 3/4
+    of the states (the part a few cycles converge), the rest the buffer of
+    partially occupied and empty states."""
+    return 0.75 * ns
+
+
+def _orthonormal_columns(A: np.ndarray) -> np.ndarray:
+    q, r = np.linalg.qr(A)
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def make_alb_samples(J: np.ndarray, nr: int = NR_PER_ELEMENT, base_seed: int = BASE_SEED) -> np.ndarray:
+    """Packed V_K^T for every element (element-major, J_K x n_r each): the
+    first J_K columns of a Haar n_r x n_r orthogonal matrix."""
+    J = np.asarray(J)
+    if nr < int(J.max()):
+        raise ValueError("n_r must be at least the largest ALB count")
+    parts = []
+    for K in range(len(J)):
+        g = rng_for(PURPOSE_ALB, K, base_seed)
+        V = _orthonormal_columns(g.standard_normal((nr, int(J[K]))))
+        parts.append(V.T.ravel())
+    return np.concatenate(parts)
+
+
+def make_next_alb_samples(J: np.ndarray, V_packed: np.ndarray, nr: int = NR_PER_ELEMENT,
+                          delta: float = 0.05, base_seed: int = BASE_SEED) -> np.ndarray:
+    """The next SCF step's samples: orthonormalised V_K + delta G_K per
+    element, G_K ~ N(0, 1) (signs fixed so that the new basis stays close to
+    the old one)."""
+    J = np.asarray(J)
+    off = np.zeros(len(J) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(J)
+    parts = []
+    for K in range(len(J)):
+        V = np.asarray(V_packed[nr * off[K]:nr * off[K + 1]]).reshape(int(J[K]), nr).T
+        g = rng_for(PURPOSE_ALB_STEP, K, base_seed)
+        Vn = _orthonormal_columns(V + delta * g.standard_normal(V.shape))
+        parts.append(Vn.T.ravel())
+    return np.concatenate(parts)
