@@ -69,7 +69,8 @@ typedef enum {
   CHEFSI_OP_RAYLEIGH_RITZ = 3,
   CHEFSI_OP_SWEEP = 4,
   CHEFSI_OP_FILTER_BACKWARD = 5,
-  CHEFSI_OP_LOSS_BACKWARD = 6
+  CHEFSI_OP_LOSS_BACKWARD = 6,
+  CHEFSI_OP_DENSITY = 7
 } chefsi_op;
 
 typedef struct chefsi_plan_s* chefsi_plan;
@@ -103,6 +104,9 @@ void chefsi_plan_destroy(chefsi_plan plan);
 /* N = sum_K J_K, and the element count of H in block-list layout. */
 int64_t chefsi_plan_n(chefsi_plan plan);
 int64_t chefsi_plan_h_elems(chefsi_plan plan);
+/* sum_K J_K^2: the element count of a set of element blocks (density-matrix
+ * blocks, basis overlaps), stored row-major and back to back in element order. */
+int64_t chefsi_plan_block_elems(chefsi_plan plan);
 /* Element reached from K through slot s (the plan's table), or -1 on bad args. */
 int chefsi_plan_neighbour(chefsi_plan plan, int K, int s);
 
@@ -218,6 +222,46 @@ int chefsi_filter_backward(chefsi_plan plan, const double* d_H, int m, double a,
                            const double* d_Ybar, int64_t ldyb, int ns, double* d_Hbar,
                            double* d_Xbar, int64_t ldxb, void* ws, size_t ws_bytes,
                            void* stream);
+
+/* ------------------------------------------------------- occupations ----
+ * Fermi-Dirac occupations of the Ritz values (Sec. II A: occupations by
+ * Fermi-Dirac smearing; Sec. II B 2: the Ritz values give the Fermi energy and
+ * the occupation numbers).  f_i = 1/(1 + exp((theta_i - mu)/kT)) per spatial
+ * orbital (the spin factor 2 is left to the density), and the Fermi level mu
+ * satisfies sum_i f_i = n_occ (= N_e/2).  mu is found by bisection on
+ * [min theta - 50 kT, max theta + 50 kT], halving until the midpoint is no
+ * longer strictly inside the bracket (or 200 halvings), mu = the final
+ * midpoint.  d_ritz: ns float64 (device, any order); d_f: ns float64 (device,
+ * may equal d_ritz for an in-place update); d_mu: 1 float64 (device).
+ * Requires 0 < n_occ < ns and kT > 0 (finite).  A non-finite Ritz value gives
+ * NaN in d_f and d_mu.  Asynchronous; no workspace. */
+int chefsi_occupations(int ns, const double* d_ritz, double n_occ, double kT, double* d_f,
+                       double* d_mu, void* stream);
+
+/* ------------------------------------------------ density-matrix blocks ---
+ * Diagonal blocks of the density matrix (eq. densitymatrix with K = K'):
+ *   P_KK[j][j'] = sum_i f_i X[rowoff[K]+j][i] X[rowoff[K]+j'][i],
+ * one J_K x J_K block per element, which is all the electron density needs
+ * and is local to each element.  d_X: N x ns Ritz vectors (row stride ldx);
+ * d_f: ns weights (device; the occupations); d_P: chefsi_plan_block_elems()
+ * float64 (device), element K's block row-major at sum_{K'<K} J_K'^2, exactly
+ * symmetric.  d_P must not overlap d_X or d_f.  Workspace:
+ * chefsi_workspace_bytes(op = CHEFSI_OP_DENSITY, ns).  Asynchronous. */
+int chefsi_density_blocks(chefsi_plan plan, const double* d_X, int64_t ldx, int ns, const double* d_f,
+                          double* d_P, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------ realign -----
+ * Re-alignment of the coefficients to a changed ALB basis (Sec. II B 3,
+ * eqs. basis_rotation_1-3): X_K <- (V_new,K)^T V_old,K X_K for every element,
+ * in place on d_X (N x ns, row stride ldx).  V_K (nr x J_K) samples element
+ * K's J_K ALBs on its nr grid points; d_Vnew and d_Vold (device, N*nr float64
+ * each) hold, element after element, V_K^T row-major (row j = ALB j's nr
+ * samples), element K starting at nr * rowoff[K].  The ALB counts are the
+ * plan's for both bases.  d_X must not overlap d_Vnew or d_Vold (d_Vnew may
+ * equal d_Vold).  Workspace: chefsi_realign_workspace_bytes.  Asynchronous. */
+int chefsi_realign(chefsi_plan plan, int nr, const double* d_Vnew, const double* d_Vold, double* d_X,
+                   int64_t ldx, int ns, void* ws, size_t ws_bytes, void* stream);
+int chefsi_realign_workspace_bytes(chefsi_plan plan, int nr, size_t* bytes);
 
 #ifdef __cplusplus
 }

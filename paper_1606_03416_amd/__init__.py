@@ -11,9 +11,12 @@ this package loads the library and fails loudly if it is missing.
     U = chefsi.orthonormalize(Y, passes=2)             # step 3 (in place)
     Xn, ritz, resid, Q = plan.rayleigh_ritz(H, Y)      # steps 4-5
     plan.sweep(H, X, m, v0=v0, ritz=ritz, ...)         # steps 1-5
+    f, mu = chefsi.occupations(ritz, n_occ, kT)        # Fermi-Dirac occupations
+    P = plan.density_blocks(X, f)                      # diagonal density-matrix blocks
+    plan.realign(X, V_new, V_old, nr)                  # coefficients onto a new ALB basis
 """
 from ._binding import (  # noqa: F401
-    ChefsiError, Plan, orthonormalize, library_path, lib, ChefsiLoss, ChebFilter,
+    ChefsiError, Plan, orthonormalize, occupations, library_path, lib, ChefsiLoss, ChebFilter,
     F64, F32, BF16, OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP,
-    OP_FILTER_BACKWARD, OP_LOSS_BACKWARD, ERR_NOT_PD, ERR_ARG, ERR_WORKSPACE, ERR_EIG,
+    OP_FILTER_BACKWARD, OP_LOSS_BACKWARD, OP_DENSITY, ERR_NOT_PD, ERR_ARG, ERR_WORKSPACE, ERR_EIG,
 )

@@ -21,7 +21,8 @@ if not os.path.exists(library_path):
 lib = ctypes.CDLL(library_path)
 
 F64, F32, BF16 = 0, 1, 2
-OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP, OP_FILTER_BACKWARD, OP_LOSS_BACKWARD = range(7)
+(OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP, OP_FILTER_BACKWARD, OP_LOSS_BACKWARD,
+ OP_DENSITY) = range(8)
 ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_NOT_PD, ERR_EIG, ERR_NONFINITE, ERR_UNSUPPORTED = range(1, 8)
 
 _vp = ctypes.c_void_p
@@ -54,6 +55,7 @@ _sig("chefsi_plan_destroy", None, _vp)
 _sig("chefsi_plan_n", _i64, _vp)
 _sig("chefsi_plan_h_elems", _i64, _vp)
 _sig("chefsi_plan_neighbour", _i, _vp, _i, _i)
+_sig("chefsi_plan_block_elems", _i64, _vp)
 _sig("chefsi_workspace_bytes", _i, _vp, _i, _i, _i, _i, _i, ctypes.POINTER(_sz))
 _sig("chefsi_bounds", _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _dp, _vp, _sz, _vp)
 _sig("chefsi_filter", _i, _vp, _vp, _i, _d, _d, _d, _i, _vp, _i64, _vp, _i64, _i, _vp, _sz, _vp)
@@ -67,6 +69,10 @@ _sig("chefsi_loss_backward", _i, _vp, _vp, _i, _d, _d, _d, _i, _i, _i, _vp, _i64
 _sig("chefsi_backward_workspace_bytes", _i, _vp, _i, _i, _i, _i, _i, ctypes.POINTER(_sz))
 _sig("chefsi_filter_backward", _i, _vp, _vp, _i, _d, _d, _d, _i, _vp, _i64, _vp, _i64, _i, _vp, _vp,
      _i64, _vp, _sz, _vp)
+_sig("chefsi_occupations", _i, _i, _vp, _d, _d, _vp, _vp, _vp)
+_sig("chefsi_density_blocks", _i, _vp, _vp, _i64, _i, _vp, _vp, _vp, _sz, _vp)
+_sig("chefsi_realign", _i, _vp, _i, _vp, _vp, _vp, _i64, _i, _vp, _sz, _vp)
+_sig("chefsi_realign_workspace_bytes", _i, _vp, _i, ctypes.POINTER(_sz))
 
 
 class ChefsiError(RuntimeError):
@@ -115,6 +121,7 @@ class Plan:
                                       J.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         self.N = int(lib.chefsi_plan_n(self._h))
         self.h_elems = int(lib.chefsi_plan_h_elems(self._h))
+        self.block_elems = int(lib.chefsi_plan_block_elems(self._h))
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     def close(self):
@@ -248,6 +255,62 @@ class Plan:
                                           ldyb, ns, _p(Hbar), _p(Xbar), Xbar.stride(0), _p(ws), ws.numel(),
                                           _stream()))
         return Hbar, Xbar
+
+    # -- after the cycle: diagonal density-matrix blocks (eq. densitymatrix)
+    def density_blocks(self, X, f, out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+        """P_KK = X_K diag(f) X_K^T for every element, back to back (flat)."""
+        ldx = _mv(X, "X")
+        ns = X.shape[1]
+        _vec(f, "f", ns)
+        if out is None:
+            out = torch.empty(self.block_elems, dtype=torch.float64, device=X.device)
+        _vec(out, "out", self.block_elems)
+        need = self.workspace_bytes(OP_DENSITY, ns)
+        if ws is None or ws.numel() < need:
+            ws = _workspace(need, X.device)
+        _check(lib.chefsi_density_blocks(self._h, _p(X), ldx, ns, _p(f), _p(out), _p(ws), ws.numel(), _stream()))
+        return out
+
+    def split_blocks(self, P: torch.Tensor):
+        """Views J_K x J_K of a flat set of element blocks."""
+        out, pos = [], 0
+        for n in self.J.tolist():
+            out.append(P[pos:pos + n * n].view(n, n))
+            pos += n * n
+        return out
+
+    # -- before the next cycle: re-alignment to a changed basis (eq. basis_rotation_3)
+    def realign_workspace_bytes(self, nr: int) -> int:
+        out = _sz(0)
+        _check(lib.chefsi_realign_workspace_bytes(self._h, nr, ctypes.byref(out)))
+        return int(out.value)
+
+    def realign(self, X, V_new, V_old, nr: int, ws: Optional[torch.Tensor] = None):
+        """X_K <- V_new,K^T V_old,K X_K in place (V packed element-major as
+        V_K^T, J_K rows of nr samples each)."""
+        ldx = _mv(X, "X")
+        ns = X.shape[1]
+        _vec(V_new, "V_new", self.N * nr)
+        _vec(V_old, "V_old", self.N * nr)
+        need = self.realign_workspace_bytes(nr)
+        if ws is None or ws.numel() < need:
+            ws = _workspace(need, X.device)
+        _check(lib.chefsi_realign(self._h, nr, _p(V_new), _p(V_old), _p(X), ldx, ns, _p(ws), ws.numel(),
+                                  _stream()))
+        return X
+
+
+def occupations(ritz: torch.Tensor, n_occ: float, kT: float, out: Optional[torch.Tensor] = None):
+    """Fermi-Dirac occupations and Fermi level of the Ritz values: (f, mu),
+    both device tensors (sum f = n_occ)."""
+    ns = ritz.numel()
+    _vec(ritz, "ritz", ns)
+    if out is None:
+        out = torch.empty(ns, dtype=torch.float64, device=ritz.device)
+    _vec(out, "out", ns)
+    mu = torch.empty(1, dtype=torch.float64, device=ritz.device)
+    _check(lib.chefsi_occupations(ns, _p(ritz), float(n_occ), float(kT), _p(out), _p(mu), _stream()))
+    return out, mu
 
 
 class ChefsiLoss(torch.autograd.Function):

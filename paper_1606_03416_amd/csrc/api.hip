@@ -675,6 +675,9 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
       }
       ++p->grp_count.back();
     }
+    p->sqoff.assign(M + 1, 0);
+    for (int K = 0; K < M; ++K) p->sqoff[K + 1] = p->sqoff[K] + static_cast<int64_t>(p->J[K]) * p->J[K];
+    p->sqtot = p->sqoff[M];
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;
       return fail(CHEFSI_ERR_HIP, "hipGetDevice failed (no GPU?)");
@@ -704,6 +707,7 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
     rc |= up(&p->d_kgoff, p->kgoff);
     rc |= up(&p->d_kg8, kg8);
     rc |= up(&p->d_rowsrc8, rowsrc8);
+    rc |= up(&p->d_sqoff, p->sqoff);
     if (rc != CHEFSI_OK) {
       chefsi_plan_destroy(reinterpret_cast<chefsi_plan>(p));
       return fail(CHEFSI_ERR_HIP, "plan_create: device table upload failed");
@@ -718,7 +722,7 @@ void chefsi_plan_destroy(chefsi_plan plan) {
   Plan* p = P(plan);
   void* ptrs[] = {p->d_J, p->d_nbr, p->d_rb, p->d_kpad, p->d_order, p->d_rowoff,
                   p->d_hoff, p->d_poff, p->d_koff, p->d_kmap, p->d_kslot, p->d_rowoff8,
-                  p->d_poff8, p->d_kpad8, p->d_kgoff, p->d_kg8, p->d_rowsrc8};
+                  p->d_poff8, p->d_kpad8, p->d_kgoff, p->d_kg8, p->d_rowsrc8, p->d_sqoff};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   destroy_eig_handle(*p);
@@ -728,6 +732,8 @@ void chefsi_plan_destroy(chefsi_plan plan) {
 int64_t chefsi_plan_n(chefsi_plan plan) { return plan ? P(plan)->N : -1; }
 
 int64_t chefsi_plan_h_elems(chefsi_plan plan) { return plan ? P(plan)->h_elems : -1; }
+
+int64_t chefsi_plan_block_elems(chefsi_plan plan) { return plan ? P(plan)->sqtot : -1; }
 
 int chefsi_plan_neighbour(chefsi_plan plan, int K, int s) {
   if (!plan) return -1;
@@ -772,6 +778,12 @@ int chefsi_workspace_bytes(chefsi_plan plan, int op, int ns, int dtype, int pass
         Carver c(nullptr, 0);
         RrWs r;
         CHEFSI_TRY(carve_rr(c, p, ns, true, r));
+        *bytes = c.used;
+        return CHEFSI_OK;
+      }
+      case CHEFSI_OP_DENSITY: {
+        Carver c(nullptr, 0);
+        c.take<double>(static_cast<int64_t>(elem_nt_slices(p, ns)) * p.sqtot);
         *bytes = c.used;
         return CHEFSI_OK;
       }
@@ -1181,6 +1193,91 @@ int chefsi_filter_backward(chefsi_plan plan, const double* d_H, int m, double a,
                                     &ldl, st));
     CHEFSI_TRY(launch_copy_f64(d_Ybar, ldyb, w.LA, ns, p.N, ns, st));
     return reverse_sweep(p, m, stride, d_X, ldx, ns, w, d_Hbar, d_Xbar, ldxb, st);
+  });
+}
+
+// ------------------------------------------------- steps around the cycle
+
+int chefsi_occupations(int ns, const double* d_ritz, double n_occ, double kT, double* d_f, double* d_mu,
+                       void* stream) {
+  return guarded([&]() -> int {
+    if (ns < 1) return fail(CHEFSI_ERR_ARG, "ns must be >= 1");
+    if (d_ritz == nullptr || d_f == nullptr || d_mu == nullptr)
+      return fail(CHEFSI_ERR_ARG, "ritz, f or mu is NULL");
+    if (!(kT > 0.0) || !std::isfinite(kT)) return fail(CHEFSI_ERR_ARG, "kT must be positive and finite");
+    if (!(n_occ > 0.0 && n_occ < static_cast<double>(ns)))
+      return fail(CHEFSI_ERR_ARG, "n_occ must lie strictly between 0 and ns");
+    const size_t vb = static_cast<size_t>(ns) * sizeof(double);
+    if (overlaps(d_mu, sizeof(double), d_ritz, vb) || overlaps(d_mu, sizeof(double), d_f, vb))
+      return fail(CHEFSI_ERR_ARG, "mu overlaps ritz or f");
+    if (d_f != d_ritz && overlaps(d_f, vb, d_ritz, vb))
+      return fail(CHEFSI_ERR_ARG, "f partially overlaps ritz");
+    return launch_fermi(d_ritz, ns, n_occ, kT, d_f, d_mu, static_cast<hipStream_t>(stream));
+  });
+}
+
+int chefsi_density_blocks(chefsi_plan plan, const double* d_X, int64_t ldx, int ns, const double* d_f,
+                          double* d_P, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (ns < 0) return fail(CHEFSI_ERR_ARG, "ns must be >= 0");
+    if (d_P == nullptr) return fail(CHEFSI_ERR_ARG, "P is NULL");
+    if (ns > 0 && d_f == nullptr) return fail(CHEFSI_ERR_ARG, "f is NULL");
+    CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
+    const size_t pb = static_cast<size_t>(p.sqtot) * sizeof(double);
+    if (ns > 0 && (overlaps(d_P, pb, d_X, mv_bytes(p.N, ldx, ns, 8)) ||
+                   overlaps(d_P, pb, d_f, static_cast<size_t>(ns) * sizeof(double))))
+      return fail(CHEFSI_ERR_ARG, "P overlaps X or f");
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_workspace_bytes(plan, CHEFSI_OP_DENSITY, ns, 0, 1, 1, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ns == 0) return launch_fill(d_P, p.sqtot, 0.0, st);
+    Carver c(ws, ws_bytes);
+    double* part = c.take<double>(static_cast<int64_t>(elem_nt_slices(p, ns)) * p.sqtot);
+    return elem_nt(p, d_X, ldx, d_X, ldx, d_f, ns, true, part, d_P, st);
+  });
+}
+
+int chefsi_realign_workspace_bytes(chefsi_plan plan, int nr, size_t* bytes) {
+  return guarded([&]() -> int {
+    if (plan == nullptr || bytes == nullptr) return fail(CHEFSI_ERR_ARG, "plan/bytes is NULL");
+    if (nr < 1) return fail(CHEFSI_ERR_ARG, "nr must be >= 1");
+    Plan& p = *P(plan);
+    Carver c(nullptr, 0);
+    c.take<double>(p.sqtot);
+    c.take<double>(static_cast<int64_t>(elem_nt_slices(p, nr)) * p.sqtot);
+    *bytes = c.used;
+    return CHEFSI_OK;
+  });
+}
+
+int chefsi_realign(chefsi_plan plan, int nr, const double* d_Vnew, const double* d_Vold, double* d_X,
+                   int64_t ldx, int ns, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (nr < 1) return fail(CHEFSI_ERR_ARG, "nr must be >= 1");
+    if (ns < 0) return fail(CHEFSI_ERR_ARG, "ns must be >= 0");
+    if (d_Vnew == nullptr || d_Vold == nullptr) return fail(CHEFSI_ERR_ARG, "Vnew or Vold is NULL");
+    CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
+    const size_t vb = static_cast<size_t>(p.N) * nr * sizeof(double);
+    const size_t xb = mv_bytes(p.N, ldx, ns, 8);
+    if (ns > 0 && (overlaps(d_X, xb, d_Vnew, vb) || overlaps(d_X, xb, d_Vold, vb)))
+      return fail(CHEFSI_ERR_ARG, "X overlaps the ALB samples");
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_realign_workspace_bytes(plan, nr, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    if (ns == 0) return CHEFSI_OK;
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    double* R = c.take<double>(p.sqtot);
+    double* part = c.take<double>(static_cast<int64_t>(elem_nt_slices(p, nr)) * p.sqtot);
+    CHEFSI_TRY(elem_nt(p, d_Vnew, nr, d_Vold, nr, nullptr, nr, false, part, R, st));
+    return elem_apply(p, R, d_X, ldx, ns, st);
   });
 }
 

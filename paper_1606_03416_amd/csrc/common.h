@@ -86,6 +86,11 @@ struct Plan {
   int64_t* d_kgoff = nullptr;   // [M] offsets into d_kg8
   int32_t* d_kg8 = nullptr;     // [sum kpad8/8] 8-row tile of each reduction-row group (-1 pad)
   int32_t* d_rowsrc8 = nullptr; // [N8] source row of each padded row (-1 padding)
+  // element blocks J_K x J_K (density-matrix blocks, basis overlaps), row-major,
+  // back to back: element K's block starts at sqoff[K]; sqtot = sum_K J_K^2
+  std::vector<int64_t> sqoff;
+  int64_t sqtot = 0;
+  int64_t* d_sqoff = nullptr;   // [M+1]
   void* rocblas = nullptr;      // rocblas_handle for the dense eigensolver
   size_t eig_ws_cache_n = 0, eig_ws_cache_bytes = 0;
 };
@@ -206,5 +211,21 @@ int lanczos_bounds(const Plan& p, const void* d_panel64, const double* d_v0, int
                    hipStream_t st);
 int launch_warm_bounds(const double* d_ritz, int ns, const double* d_b_src, double* d_bounds,
                        hipStream_t st);
+
+// Steps around the cycle (post.hip).
+// Fermi level mu (sum_i f_i = n_occ) by bisection and occupations f (device).
+int launch_fermi(const double* d_theta, int ns, double n_occ, double kT, double* d_f, double* d_mu,
+                 hipStream_t st);
+// Slices the element products split a reduction of length L into; the
+// partial buffer of elem_nt holds elem_nt_slices(p, L) * p.sqtot doubles.
+int elem_nt_slices(const Plan& p, int64_t L);
+// C_K = A_K diag(w) B_K^T for every element (J_K x J_K, reduction over L
+// columns; A_K = rows rowoff[K].. of A with row stride lda; w may be null);
+// sym: B = A and C symmetric (only the upper part computed, then mirrored).
+// Result in d_out at sqoff[K]; d_part is the slice scratch.
+int elem_nt(const Plan& p, const double* A, int64_t lda, const double* B, int64_t ldb, const double* w,
+            int64_t L, bool sym, double* d_part, double* d_out, hipStream_t st);
+// X_K <- R_K X_K in place for every element (R_K at d_R + sqoff[K]).
+int elem_apply(const Plan& p, const double* d_R, double* X, int64_t ldx, int ns, hipStream_t st);
 
 }  // namespace chefsi

@@ -80,3 +80,27 @@ def test_null_plan_and_orthonormalize_checks(raw):
     assert raw.chefsi_orthonormalize(100, 10, dummy, 10, 2, None, ws, 1 << 30, None) == 3
     assert raw.chefsi_orthonormalize_workspace_bytes(100, 10, 2, ctypes.byref(out)) == 0
     assert out.value >= 3 * 10 * 10 * 8
+
+
+def test_post_cycle_entry_points_check_arguments_on_host(raw):
+    """Occupations, density blocks and re-alignment reject bad arguments
+    before any HIP call."""
+    d = ctypes.c_double
+    a = ctypes.c_void_p(0x10000)
+    f = ctypes.c_void_p(0x20000)
+    mu = ctypes.c_void_p(0x30000)
+    occ = raw.chefsi_occupations
+    occ.argtypes = [ctypes.c_int, ctypes.c_void_p, d, d, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert occ(0, a, d(0.5), d(1e-3), f, mu, None) == 1          # ns
+    assert occ(10, a, d(0.0), d(1e-3), f, mu, None) == 1         # n_occ at 0
+    assert occ(10, a, d(10.0), d(1e-3), f, mu, None) == 1        # n_occ at ns
+    assert occ(10, a, d(5.0), d(0.0), f, mu, None) == 1          # kT
+    assert occ(10, a, d(5.0), d(float("inf")), f, mu, None) == 1
+    assert occ(10, None, d(5.0), d(1e-3), f, mu, None) == 1      # NULL ritz
+    assert occ(10, a, d(5.0), d(1e-3), f, ctypes.c_void_p(0x10008), None) == 1   # mu inside ritz
+    assert occ(10, a, d(5.0), d(1e-3), ctypes.c_void_p(0x10008), mu, None) == 1  # f partly over ritz
+    assert raw.chefsi_density_blocks(None, a, 8, 8, f, mu, None, 0, None) == 1
+    assert raw.chefsi_realign(None, 8, a, f, mu, 8, 8, None, 0, None) == 1
+    out = ctypes.c_size_t(0)
+    assert raw.chefsi_realign_workspace_bytes(None, 8, ctypes.byref(out)) == 1
+    assert raw.chefsi_plan_block_elems(None) == -1
