@@ -29,7 +29,8 @@ from .core import (  # noqa: F401
     slot_neighbour, assemble_dense, DenseOperator, BlockOperator,
     chebyshev_coefficients, chebyshev_filter, lanczos, lanczos_upper_bound,
     bounds_cold, bounds_warm, cholesky_upper, solve_right_upper, cholesky_qr,
-    rayleigh_ritz, sign_normalize, sweep, chebyshev_T,
+    rayleigh_ritz, sign_normalize, sweep, chebyshev_T, cholqr_condition_bound,
+    auto_passes,
 )
 from .jacobi import jacobi_eigh  # noqa: F401
 from .adjoint import (  # noqa: F401

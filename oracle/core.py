@@ -273,25 +273,61 @@ def solve_right_upper(Y: np.ndarray, U: np.ndarray) -> np.ndarray:
     return Yh
 
 
+# One pass is kept when 10 eps B^2 <= 1e-13 for the condition bound B of the
+# first factor (a predicted orthogonality loss 10x below the 1e-12 target,
+# with a factor 10 over the observed eps kappa^2 behaviour).
+AUTO_LOSS_LIMIT = 1e-13
+AUTO_LOSS_FACTOR = 10.0
+
+
+def auto_passes(U1: np.ndarray) -> int:
+    """Passes chosen by passes = 0 (auto): 1 if 10 eps B^2 <= 1e-13 for
+    B = cholqr_condition_bound(U1), else 2."""
+    B = cholqr_condition_bound(U1)
+    return 1 if AUTO_LOSS_FACTOR * np.finfo(np.float64).eps * B * B <= AUTO_LOSS_LIMIT else 2
+
+
 def cholesky_qr(Y: np.ndarray, passes: int = 2):
     """S = Y^T Y, U^T U = S, solve Yhat U = Y (Algorithm 1 step 3).
 
     passes = 2 repeats the three steps on Yhat (CholeskyQR2, Fukaya et al.
-    2014): one pass loses orthogonality like eps * cond(Y)^2.  Returns Yhat,
-    the combined factor U = U_2 U_1 and the per-pass factors.
+    2014): one pass loses orthogonality like eps * cond(Y)^2.  passes = 0
+    factors once and repeats only if auto_passes says so.  Returns Yhat, the
+    combined factor U = U_2 U_1 and the per-pass factors.
     """
-    if passes not in (1, 2):
-        raise ValueError("passes must be 1 or 2")
+    if passes not in (0, 1, 2):
+        raise ValueError("passes must be 0 (auto), 1 or 2")
     Yh = np.asarray(Y, dtype=np.float64)
     Us = []
-    for _ in range(passes):
+    npass = passes if passes else 2
+    for i in range(npass):
         S = Yh.T @ Yh
         S = 0.5 * (S + S.T)
         U = cholesky_upper(S)
         Yh = solve_right_upper(Yh, U)
         Us.append(U)
-    Utot = Us[0] if passes == 1 else Us[1] @ Us[0]
+        if passes == 0 and i == 0 and auto_passes(U) == 1:
+            break
+    Utot = Us[0] if len(Us) == 1 else Us[1] @ Us[0]
     return Yh, Utot, Us
+
+
+def cholqr_condition_bound(U: np.ndarray) -> float:
+    """Upper bound on the 2-norm condition number of the column-equilibrated
+    block Y D^{-1} (D = column norms of Y) from its Cholesky factor U:
+    with U_e = U D^{-1} (D_j = norm of column j of U, which is ||y_j||) and
+    T_e = U_e^{-1}, kappa_2 <= sqrt(kappa_1 kappa_inf), where kappa_1 and
+    kappa_inf are the exact 1- and inf-norm condition numbers of U_e
+    (||A||_2^2 <= ||A||_1 ||A||_inf).  One Cholesky-QR pass loses
+    orthogonality like eps kappa_2^2 (Sec. II B 2 uses one pass); the bound
+    decides whether a second pass is needed."""
+    U = np.triu(np.asarray(U, dtype=np.float64))
+    d = np.sqrt(np.sum(U * U, axis=0))
+    Ue = U / d[None, :]
+    Te = np.linalg.inv(Ue)
+    k1 = np.abs(Ue).sum(axis=0).max() * np.abs(Te).sum(axis=0).max()
+    ki = np.abs(Ue).sum(axis=1).max() * np.abs(Te).sum(axis=1).max()
+    return float(math.sqrt(k1 * ki))
 
 
 # ----------------------------------------------------------------------------

@@ -471,3 +471,44 @@ def test_P10_detects_planted_adjoint_mistakes(monkeypatch):
         mp.setattr(oracle.adjoint.core, "chebyshev_coefficients", no_beta)
         bad = float(np.sum(oracle.loss_backward(op, cache)[1] * D))
     assert abs(bad - fd) > 1e-4 * max(1.0, abs(fd))
+
+
+# ------------------------------------------------ Cholesky-QR condition bound
+def test_cholqr_condition_bound_is_an_upper_bound():
+    """sqrt(kappa_1 kappa_inf) of the equilibrated factor is >= the 2-norm
+    condition number of the column-equilibrated block (LAPACK SVD), equals 1
+    for orthogonal columns of any scale, and tracks ill-conditioning."""
+    g = np.random.default_rng(21)
+    for N, n, spread in ((200, 30, 0.0), (300, 60, 3.0), (500, 40, 6.0)):
+        Y = g.standard_normal((N, n)) * 10.0 ** g.uniform(-spread, spread, n)[None, :]
+        U = np.linalg.cholesky(Y.T @ Y).T
+        Ye = Y / np.linalg.norm(Y, axis=0)[None, :]
+        s = np.linalg.svd(Ye, compute_uv=False)
+        k2 = s[0] / s[-1]
+        b = oracle.cholqr_condition_bound(U)
+        assert b >= k2 * (1 - 1e-12)
+        assert b <= n * k2
+    Q, _ = np.linalg.qr(g.standard_normal((100, 20)))
+    Ys = Q * 10.0 ** g.uniform(-5, 5, 20)[None, :]
+    assert abs(oracle.cholqr_condition_bound(np.linalg.cholesky(Ys.T @ Ys).T) - 1.0) <= 1e-10
+    # two nearly parallel columns: the bound grows like 1/angle
+    Y = g.standard_normal((100, 5))
+    Y[:, 4] = Y[:, 3] + 1e-6 * g.standard_normal(100)
+    assert oracle.cholqr_condition_bound(np.linalg.cholesky(Y.T @ Y).T) > 1e5
+
+
+def test_cholesky_qr_auto_passes():
+    """passes = 0 keeps one pass for a well-conditioned block (the result is
+    the one-pass result) and takes the second pass for an ill-conditioned one
+    (orthonormal to rounding either way)."""
+    g = np.random.default_rng(22)
+    Y = g.standard_normal((3000, 20)) * 10.0 ** g.uniform(-4, 4, 20)[None, :]
+    Yh0, _, Us0 = oracle.cholesky_qr(Y, 0)
+    Yh1, _, _ = oracle.cholesky_qr(Y, 1)
+    assert len(Us0) == 1 and np.array_equal(Yh0, Yh1)
+    assert np.linalg.norm(Yh0.T @ Yh0 - np.eye(20), 2) <= 1e-13
+    Z = g.standard_normal((300, 40))
+    Z[:, 7] = Z[:, 3] + 1e-5 * g.standard_normal(300)
+    Zh, _, Usz = oracle.cholesky_qr(Z, 0)
+    assert len(Usz) == 2
+    assert np.linalg.norm(Zh.T @ Zh - np.eye(40), 2) <= 1e-13
