@@ -4,13 +4,17 @@ A step is one full CheFSI cycle (Algorithm 1: Lanczos bounds, Chebyshev
 filter, Cholesky-QR, Rayleigh-Ritz, rotation + FP64 residuals) in FP64 on the
 bulk workload: periodic 12x12x12 elements, 64 ALBs each (N = 110,592), a
 7-block stencil, N_s = 4,096 states, filter degree m = 16, 20 Lanczos steps,
-CholeskyQR2.  Inputs are seeded synthetic blocks resident in HBM before timing.
+Cholesky-QR with the automatic pass count (one pass, as in the paper, when the
+first factor's condition bound shows it keeps orthonormality to 1e-12, else
+two).  Inputs are seeded synthetic blocks resident in HBM before timing.
 
 Printed: one JSON line with the sweep time (value), the filter TFLOP/s, the
 per-stage times, the roofline of the dominant kernel (the Chebyshev step),
 the mixed-precision comparison (2 FP32- or BF16-filter sweeps + 2 FP64 sweeps against
-4 FP64 sweeps from the same start, at the same final residual) and the CPU
-oracle baseline on a bounded sample.
+4 FP64 sweeps from the same start, at the same final residual), the steps
+around the cycle on its final Ritz pairs (Fermi-Dirac occupations at 300 K,
+diagonal density-matrix blocks, re-alignment to a changed ALB basis) with
+their rooflines, and the CPU oracle baseline on a bounded sample.
 """
 from __future__ import annotations
 
@@ -112,7 +116,8 @@ def cpu_baseline(w, P, X0, v0, passes, sample_cols):
         "value": full, "unit": "s per FP64 CheFSI sweep (extrapolated)", "cores": int(cores),
         "kind": "oracle",
         "sample": (f"one oracle sweep (block-sparse mode, Lanczos {w.lanczos_steps}, filter m={w.m}, "
-                   f"CholeskyQR{passes}, Rayleigh-Ritz) on the full {w.grid} grid with {sample_cols} of "
+                   f"Cholesky-QR passes={'auto' if passes == 0 else passes}, Rayleigh-Ritz) on the full {w.grid} "
+                   f"grid with {sample_cols} of "
                    f"{w.ns} columns plus an order-{n_eig} eigensolve, {sample_s:.1f} s in all; extrapolated: "
                    f"filter x{f:g}, Cholesky-QR and Rayleigh-Ritz products x{f * f:g}, eigensolve x{fe ** 3:g}"),
         "sample_stage_s": {k: round(v, 3) for k, v in t.items()},
@@ -172,15 +177,80 @@ def filter_mode(args, w, P, plan, H, X0d, chefsi, torch):
     print(json.dumps(out), flush=True)
 
 
+def timed_ms(torch, fn, reps):
+    """Average stream time of fn() over reps back-to-back calls (HIP events on
+    the current stream, one untimed call first)."""
+    st = torch.cuda.current_stream()
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def post_cycle(P, plan, X, ritz, chefsi, torch, reps=10):
+    """Steps around the cycle on its final Ritz pairs: occupations (Fermi level
+    by bisection, 300 K), diagonal density-matrix blocks P_KK = X_K diag(f) X_K^T,
+    and the re-alignment X_K <- V_new,K^T V_old,K X_K to a changed ALB basis
+    (n_r = 512 grid points per element).  Both element kernels are HBM-bound:
+    their minimum traffic reads X once (density) or reads and writes X once
+    (re-alignment), above the time of their FP64 MFMA work."""
+    ns = X.shape[1]
+    dev = X.device
+    J = np.asarray(P.J, dtype=np.int64)
+    sq = int(np.sum(J * J))
+    n_occ, kT = synth.occupied_count(ns), synth.KT_300K
+    f = torch.empty(ns, dtype=torch.float64, device=dev)
+    occ_ms = timed_ms(torch, lambda: chefsi.occupations(ritz, n_occ, kT, out=f), reps)
+    f, mu = chefsi.occupations(ritz, n_occ, kT, out=f)
+    Pb = torch.empty(plan.block_elems, dtype=torch.float64, device=dev)
+    wsd = torch.empty(max(plan.workspace_bytes(chefsi.OP_DENSITY, ns), 256), dtype=torch.uint8, device=dev)
+    dens_ms = timed_ms(torch, lambda: plan.density_blocks(X, f, out=Pb, ws=wsd), reps)
+    trace = float(sum(torch.trace(b).item() for b in plan.split_blocks(Pb)))
+    nr = synth.NR_PER_ELEMENT
+    V = synth.make_alb_samples(J, nr)
+    Vn = synth.make_next_alb_samples(J, V, nr)
+    Vd, Vnd = torch.from_numpy(V).to(dev), torch.from_numpy(Vn).to(dev)
+    del V, Vn
+    Xr = X.clone()
+    wsr = torch.empty(max(plan.realign_workspace_bytes(nr), 256), dtype=torch.uint8, device=dev)
+    real_ms = timed_ms(torch, lambda: plan.realign(Xr, Vnd, Vd, nr, ws=wsr), reps)
+    del Xr, Vd, Vnd
+
+    def roof(kernel, nbytes, flops, ms):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK, 4), "algorithmic_bytes": nbytes, "flops": flops,
+                "tflops": round(flops / (ms * 1e-3) / 1e12, 2), "ms": round(ms, 4)}
+
+    N = P.N
+    return {
+        "n_occ": n_occ, "kT_hartree": kT, "fermi_level": float(mu.item()), "sum_f": float(f.sum().item()),
+        "trace_P": trace, "nr": nr,
+        "occupations_ms": round(occ_ms, 4),
+        # unique entries of the symmetric blocks: ns * sum J_K (J_K + 1) flops
+        "density": roof("elem_nt (P_KK = X_K diag(f) X_K^T, FP64 MFMA) + slice sum",
+                        8 * (N * ns + ns + sq), float(ns * np.sum(J * (J + 1))), dens_ms),
+        "realign": roof("elem_nt (R_K = V_new,K^T V_old,K) + elem_apply (X_K <- R_K X_K, FP64 MFMA)",
+                        8 * (2 * N * ns + 2 * N * nr + 2 * sq), float(2 * (nr + ns) * sq), real_ms),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bulk", choices=["tiny", "diff", "bulk", "sheet"])
-    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--passes", type=int, default=0, choices=[0, 1, 2],
+                    help="Cholesky-QR passes: 1, 2 (CholeskyQR2) or 0 (automatic, by the first factor's "
+                         "condition bound)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-post", action="store_true", help="skip the steps around the cycle")
     ap.add_argument("--cpu-cols", type=int, default=256)
     ap.add_argument("--mode", default="sweep", choices=["sweep", "filter"],
                     help="filter: time only the FP64 Chebyshev filter (the dominant kernel), "
@@ -237,7 +307,9 @@ def main():
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
     log(f"timed {args.steps} sweeps: {ms_per_step:.1f} ms/sweep")
 
-    fl = sweep_flops(P, ns, m, args.passes, w.lanczos_steps)
+    taken = [int(s.pop("cholqr_passes")) for s in stats_all]
+    conds = [float(s.pop("cholqr_cond_bound")) for s in stats_all]
+    fl = sweep_flops(P, ns, m, float(np.mean(taken)), w.lanczos_steps)
     f_step = filter_flops_per_step(P, ns)
     avg = {k: float(np.mean([s[k] for s in stats_all])) for k in stats_all[0]}
     step_ms = avg["filter_steps_ms"] / m
@@ -255,7 +327,9 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.grid), "stencil": w.stencil, "alb_per_element": w.nb,
                    "N": P.N, "ns": ns, "filter_degree": m, "lanczos_steps": w.lanczos_steps,
-                   "cholqr_passes": args.passes, "parallelism": "single GPU"},
+                   "cholqr_passes": "auto" if args.passes == 0 else args.passes, "parallelism": "single GPU"},
+        "cholqr_passes_taken": taken,
+        "cholqr_cond_bound": [round(c, 3) for c in conds],
         "filter_tflops": round(filter_tflops, 2),
         "sweep_algorithmic_tflops": round(sweep_tflops, 2),
         "stage_ms": {k: round(v, 3) for k, v in avg.items()},
@@ -268,6 +342,11 @@ def main():
         "final_max_resid_wanted": float(resid.max().item()) if resid is not None else None,
     }
 
+    if not args.no_post:
+        log("steps around the cycle: occupations, density-matrix blocks, re-alignment")
+        result["post"] = post_cycle(P, plan, X, ritz, chefsi, torch)
+        log(f"post: {result['post']}")
+
     if not args.no_mixed:
         k = 3 * ns // 4
         runs = {}
@@ -276,15 +355,18 @@ def main():
         for label, dts in plans:
             Xm = X0d.clone()
             rz = None
-            times, ftimes = [], []
+            times, ftimes, npass = [], [], []
             for i, dt in enumerate(dts):
                 rz, rs, _, st = one(dt, rz is not None, Xm, rz)
                 times.append(st["total_ms"])
+                npass.append(int(st["cholqr_passes"]))
                 ftimes.append(st["filter_steps_ms"])
             runs[label] = {"sweep_ms": [round(t, 2) for t in times], "filter_steps_ms": [round(t, 2) for t in ftimes],
+                           "cholqr_passes": npass,
                            "ritz": rz.cpu().numpy(), "max_resid": float(rs[:k].max().item())}
             del Xm
-            log(f"{label}: sweeps {runs[label]['sweep_ms']} ms, max resid {runs[label]['max_resid']:.3e}")
+            log(f"{label}: sweeps {runs[label]['sweep_ms']} ms, passes {npass}, "
+                f"max resid {runs[label]['max_resid']:.3e}")
         r64 = runs["f64x4"]
         s = float(max(abs(bnd[2].item()), abs(bnd[1].item())))
         f64_filter_tflops = fl["filter"] / (np.mean(r64["filter_steps_ms"]) * 1e-3) / 1e12
@@ -292,6 +374,7 @@ def main():
             "protocol": "same X0: 4 FP64 sweeps vs 2 low-precision-filter sweeps + 2 FP64 sweeps; Ritz error = "
                         "max FP64 residual over the lowest 3/4 N_s",
             "f64_total_ms": round(sum(r64["sweep_ms"]), 2),
+            "f64_cholqr_passes": r64["cholqr_passes"],
             "f64_filter_tflops": round(f64_filter_tflops, 2),
             "f64_max_resid": r64["max_resid"],
         }
@@ -300,6 +383,7 @@ def main():
             lowp_tflops = fl["filter"] / (np.mean(rmx["filter_steps_ms"][:2]) * 1e-3) / 1e12
             result["mixed"][tag] = {
                 "mixed_total_ms": round(sum(rmx["sweep_ms"]), 2),
+                "cholqr_passes": rmx["cholqr_passes"],
                 "speedup_total": round(sum(r64["sweep_ms"]) / sum(rmx["sweep_ms"]), 3),
                 "speedup_lowp_sweep": round(np.mean(r64["sweep_ms"][:2]) / np.mean(rmx["sweep_ms"][:2]), 3),
                 "speedup_filter": round(lowp_tflops / f64_filter_tflops, 3),

@@ -77,7 +77,9 @@ typedef struct chefsi_plan_s* chefsi_plan;
 
 /* Per-stage device times of one chefsi_sweep call, in milliseconds, measured
  * with HIP events on the call's stream.  filter_steps_ms covers only the m
- * Chebyshev step launches (the dominant kernel). */
+ * Chebyshev step launches (the dominant kernel).  cholqr_passes is the number
+ * of Cholesky-QR passes the call took (1 or 2) and cholqr_cond_bound the
+ * condition bound of its first factor (see chefsi_sweep). */
 typedef struct {
   double bounds_ms;
   double filter_ms;
@@ -85,6 +87,8 @@ typedef struct {
   double orthonormalize_ms;
   double rayleigh_ritz_ms;
   double total_ms;
+  double cholqr_passes;
+  double cholqr_cond_bound;
 } chefsi_stats;
 
 /* Library version string and the last error message of this thread. */
@@ -152,7 +156,9 @@ int chefsi_filter(chefsi_plan plan, const double* d_H, int m, double a, double b
 /* ------------------------------------------------------- orthonormalize ---
  * Algorithm 1 step 3 (Cholesky-QR): S = Y^T Y, U^T U = S, solve Yhat U = Y,
  * in place on d_Y (n x ns, float64).  passes = 2 repeats it once on Yhat
- * (CholeskyQR2); d_U (ns x ns row-major, may be NULL) receives U_2 U_1 (or U_1).
+ * (CholeskyQR2); passes = 0 repeats it only when the first factor's condition
+ * bound asks for it (the rule of chefsi_sweep; one extra synchronisation).
+ * d_U (ns x ns row-major, may be NULL) receives U_2 U_1 (or U_1).
  * Returns CHEFSI_ERR_NOT_PD if a pivot was <= 0 or not finite.  Synchronises
  * the stream to read the pivot status. */
 int chefsi_orthonormalize(int64_t n, int ns, double* d_Y, int64_t ldy, int passes,
@@ -177,15 +183,22 @@ int chefsi_rayleigh_ritz(chefsi_plan plan, const double* d_H, const double* d_Yh
  * Bounds: if d_bounds_in (device, a, b, a0) is non-NULL they are used as
  * given; otherwise step 1 runs as in chefsi_bounds with d_v0 and
  * lanczos_steps, warm (a, a0 from d_ritz on entry) if `warm` != 0, cold
- * otherwise.  filter_dtype as in chefsi_filter; passes as in
- * chefsi_orthonormalize.  With passes = 2 the second Cholesky-QR pass only
- * factors (U_2 from Yhat_1^T Yhat_1) and the Rayleigh-Ritz step uses
- * Hhat = U_2^{-T} (Yhat_1^T H Yhat_1) U_2^{-1} and X = Yhat_1 (U_2^{-1} Q),
- * equal to the two-pass result in exact arithmetic; d_X holds Yhat_1 in
- * between.  Outputs: d_X (new Ritz vectors), d_ritz (ns),
- * d_resid (ns, may be NULL), d_bounds_out (3, may be NULL: the bounds used),
- * stats (host, may be NULL: per-stage event times).  Synchronises the stream
- * once at the end to read status words. */
+ * otherwise.  filter_dtype as in chefsi_filter.
+ * passes: 1 = one Cholesky-QR pass (as in the paper), 2 = CholeskyQR2,
+ * 0 = automatic: one pass when the first factor U_1 shows it is enough, i.e.
+ * 10 eps B^2 <= 1e-13 for B = sqrt(k_1 k_inf), k_1 and k_inf the 1- and
+ * inf-norm condition numbers of U_1 D^{-1} (D = column norms of the filtered
+ * block Y), an upper bound on the 2-norm condition number of the
+ * column-equilibrated Y (one pass loses orthogonality like eps kappa^2);
+ * otherwise two.  The last factor is folded into Rayleigh-Ritz: with B the
+ * block before that factor (Y after one pass, Yhat_1 = Y U_1^{-1} after two)
+ * and T = U_last^{-1}, Hhat = T^T (B^T H B) T and X = B (T Q), equal to
+ * Rayleigh-Ritz on the orthonormalised block in exact arithmetic.
+ * Outputs: d_X (new Ritz vectors), d_ritz (ns), d_resid (ns, may be NULL),
+ * d_bounds_out (3, may be NULL: the bounds used), stats (host, may be NULL:
+ * per-stage event times, passes taken, condition bound).  Synchronises the
+ * stream once at the end to read status words, and with passes = 0 also once
+ * after the first factor to read its condition bound. */
 int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, int passes,
                  int lanczos_steps, const double* d_v0, const double* d_bounds_in, int warm,
                  double* d_X, int64_t ldx, int ns, double* d_ritz, double* d_resid,

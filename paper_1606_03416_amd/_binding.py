@@ -35,7 +35,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 class Stats(ctypes.Structure):
     _fields_ = [("bounds_ms", _d), ("filter_ms", _d), ("filter_steps_ms", _d),
-                ("orthonormalize_ms", _d), ("rayleigh_ritz_ms", _d), ("total_ms", _d)]
+                ("orthonormalize_ms", _d), ("rayleigh_ritz_ms", _d), ("total_ms", _d),
+                ("cholqr_passes", _d), ("cholqr_cond_bound", _d)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

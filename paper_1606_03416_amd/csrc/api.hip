@@ -104,6 +104,8 @@ struct OrthWs {
   double* split;
   size_t split_elems;
   int* status;
+  double* cond;   // condition bound of the first factor (1 double)
+  double* cscr;   // its scratch
 };
 
 void carve_orth(Carver& c, int64_t n, int ns, OrthWs& o) {
@@ -117,6 +119,8 @@ void carve_orth(Carver& c, int64_t n, int ns, OrthWs& o) {
   o.split_elems = gemm_tn_split_ws_elems(ns, ns, n);
   o.split = o.split_elems ? c.take<double>(static_cast<int64_t>(o.split_elems)) : nullptr;
   o.status = c.take<int>(4);
+  o.cond = c.take<double>(8);
+  o.cscr = c.take<double>(static_cast<int64_t>(cholqr_cond_scratch_elems(ns)));
 }
 
 struct RrWs {
@@ -213,19 +217,33 @@ int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, 
   return CHEFSI_OK;
 }
 
+// passes = 0 (auto): one pass is kept when 10 eps B^2 <= 1e-13 for the
+// condition bound B of the first factor (B >= kappa_2 of the
+// column-equilibrated block; one pass loses orthogonality like eps kappa^2).
+constexpr double kAutoLossLimit = 1e-13;
+constexpr double kAutoLossFactor = 10.0;
+
+int auto_passes_from_bound(double B) {
+  const double eps = 2.220446049250313e-16;
+  return (kAutoLossFactor * eps * B * B <= kAutoLossLimit) ? 1 : 2;
+}
+
 // Cholesky-QR, `passes` times: S = Y^T Y (upper triangle, mirrored),
 // U^T U = S, and Yhat = Y U^{-1} as one GEMM with the triangular inverse
 // (its zero part skipped).  The passes alternate between Y and o.B so that
-// the result ends in Y.
+// the result ends in Y.  passes = 0: the second pass runs only if the first
+// factor's condition bound asks for it (auto_passes_from_bound), which reads
+// the bound on the host (one stream synchronisation).
 int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout, const OrthWs& o,
              hipStream_t st) {
   CHEFSI_TRY(launch_fill_int(o.status, 1, 0, st));
   double* Us[2] = {o.U1, o.U2};
   double* src = Y;
   int64_t lds = ldy;
-  for (int pass = 0; pass < passes; ++pass) {
-    const bool last = (pass == passes - 1);
-    double* dst = (passes == 2 && last) ? Y : o.B;
+  int used = passes ? passes : 2;
+  for (int pass = 0; pass < used; ++pass) {
+    const bool last = (pass == used - 1);
+    double* dst = (used == 2 && last) ? Y : o.B;
     const int64_t ldd = (dst == Y) ? ldy : ns;
     CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, src, lds, src, lds, 0.0, o.S, ns, true, o.split, o.split_elems, st));
     CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
@@ -235,10 +253,17 @@ int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout
     CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, src, lds, o.T, ns, 0.0, dst, ldd, st, true));
     src = dst;
     lds = ldd;
+    if (passes == 0 && pass == 0) {
+      CHEFSI_TRY(cholqr_cond_bound(o.S, o.T, ns, o.cscr, o.cond, st));
+      double h = 0.0;
+      CHEFSI_HIP(hipMemcpyAsync(&h, o.cond, sizeof(double), hipMemcpyDeviceToHost, st));
+      CHEFSI_HIP(hipStreamSynchronize(st));
+      used = auto_passes_from_bound(h);
+    }
   }
   if (src != Y) CHEFSI_TRY(launch_copy_f64(src, lds, Y, ldy, n, ns, st));
   if (Uout != nullptr) {
-    if (passes == 1) {
+    if (used == 1) {
       CHEFSI_TRY(launch_copy_f64(o.U1, ns, Uout, ns, ns, ns, st));
     } else {
       CHEFSI_TRY(trmm_upper_upper(o.U2, o.U1, Uout, ns, st));
@@ -247,48 +272,57 @@ int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout
   return CHEFSI_OK;
 }
 
-// Sweep form of CholeskyQR2 followed by Rayleigh-Ritz.  The second pass only
-// factors: Yhat1 = Y U1^{-1} is formed (into Y1out), U2 from Yhat1^T Yhat1,
-// and T2 = U2^{-1} is kept.  Rayleigh-Ritz then works on Yhat1 with
-//   Hhat = T2^T (Yhat1^T H Yhat1) T2,   X = Yhat1 (T2 Q),
-// which equals the two-pass result in exact arithmetic and saves the N x N_s
-// product Yhat1 T2.
-int run_orth_factor2(int64_t n, int ns, const double* Y, int64_t ldy, double* Y1out, int64_t ld1, double* T2,
-                     const OrthWs& o, hipStream_t st) {
+// Cholesky-QR inside a sweep.  The first factor: S = Y^T Y (upper triangle,
+// mirrored), U1^T U1 = S (U1 left in o.S), T = U1^{-1}.
+int run_orth_factor1(int64_t n, int ns, const double* Y, int64_t ldy, double* T, const OrthWs& o,
+                     hipStream_t st) {
   CHEFSI_TRY(launch_fill_int(o.status, 1, 0, st));
   CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y, ldy, Y, ldy, 0.0, o.S, ns, true, o.split, o.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
   CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, o.Wt, st));
-  CHEFSI_TRY(upper_inverse(o.S, ns, o.T, o.Wt, st));
-  CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, Y, ldy, o.T, ns, 0.0, Y1out, ld1, st, true));
+  return upper_inverse(o.S, ns, T, o.Wt, st);
+}
+
+// The second pass of CholeskyQR2, factor only: Yhat1 = Y T1 (into Y1out),
+// U2 from Yhat1^T Yhat1, and T <- U2^{-1}.
+int run_orth_pass2(int64_t n, int ns, const double* Y, int64_t ldy, double* T, double* Y1out, int64_t ld1,
+                   const OrthWs& o, hipStream_t st) {
+  CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, Y, ldy, T, ns, 0.0, Y1out, ld1, st, true));
   CHEFSI_TRY(gemm_tn(ns, ns, n, 1.0, Y1out, ld1, Y1out, ld1, 0.0, o.S, ns, true, o.split, o.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(o.S, ns, ns, 1, st));
   CHEFSI_TRY(cholesky_upper(o.S, ns, ns, o.status, o.Wt, st));
-  CHEFSI_TRY(upper_inverse(o.S, ns, T2, o.Wt, st));
-  return CHEFSI_OK;
+  return upper_inverse(o.S, ns, T, o.Wt, st);
 }
 
-// Rayleigh-Ritz on Yhat1 (in X, overwritten by the rotated block) with the
-// second-pass factor T2; Ybuf (N x ns) receives the rotation before it is
-// copied into X.
-int run_rr_factor2(Plan& p, const void* panel64, double* X, int64_t ldx, int ns, const double* T2, double* Ybuf,
-                   double* ritz, double* resid, const RrWs& r, hipStream_t st) {
+// Rayleigh-Ritz with the last Cholesky factor folded in.  B is the block whose
+// orthonormalisation is B T (T = U^{-1} of B's last factor): the filtered
+// block itself after one pass, Yhat1 after two.  Then
+//   Hhat = T^T (B^T H B) T,   X = B (T Q),
+// which equals Rayleigh-Ritz on B T in exact arithmetic and never forms B T.
+// X must not alias B unless tmp (N x ns) is given: the rotation then goes to
+// tmp and is copied into X.
+int run_rr_fold(Plan& p, const void* panel64, const double* B, int64_t ldb, int ns, const double* T, double* X,
+                int64_t ldx, double* tmp, double* ritz, double* resid, const RrWs& r, hipStream_t st) {
   CHEFSI_TRY(launch_const_coef(1.0, 0.0, r.coef, st));
-  StepIO io{X, ldx, true, nullptr, 0, true, r.W, ns, true, true};   // W = H Yhat1 (no c term)
+  StepIO io{B, ldb, true, nullptr, 0, true, r.W, ns, true, true};   // W = H B (no c term)
   CHEFSI_TRY(launch_step(p, panel64, CHEFSI_F64, r.coef, io, ns, st));
-  CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, X, ldx, r.W, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
+  CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, B, ldb, r.W, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
-  // Hhat = T2^T Hhat1 T2 (upper triangle, mirrored)
-  CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, r.Hh, ns, T2, ns, 0.0, r.Q, ns, st, true));
-  CHEFSI_TRY(gemm_tn(ns, ns, ns, 1.0, T2, ns, r.Q, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
+  // Hhat = T^T (B^T W) T (upper triangle, mirrored)
+  CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, r.Hh, ns, T, ns, 0.0, r.Q, ns, st, true));
+  CHEFSI_TRY(gemm_tn(ns, ns, ns, 1.0, T, ns, r.Q, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
   CHEFSI_TRY(launch_fill_int(r.info, 1, 0, st));
   CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.eig, r.eig_bytes, st));
   CHEFSI_TRY(launch_eigvec_fix(r.Hh, ns, ns, r.Q, ns, st));
-  // X = Yhat1 (T2 Q)
-  CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, T2, ns, r.Q, ns, 0.0, r.Hh, ns, st));
-  CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, X, ldx, r.Hh, ns, 0.0, Ybuf, ns, st));
-  CHEFSI_TRY(launch_copy_f64(Ybuf, ns, X, ldx, p.N, ns, st));
+  // X = B (T Q)
+  CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, T, ns, r.Q, ns, 0.0, r.Hh, ns, st));
+  if (tmp != nullptr) {
+    CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, B, ldb, r.Hh, ns, 0.0, tmp, ns, st));
+    CHEFSI_TRY(launch_copy_f64(tmp, ns, X, ldx, p.N, ns, st));
+  } else {
+    CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, B, ldb, r.Hh, ns, 0.0, X, ldx, st));
+  }
   if (resid != nullptr) {
     CHEFSI_TRY(launch_resid_partial(p, panel64, X, ldx, ritz, ns, r.part, st));
     CHEFSI_TRY(launch_colsum_sqrt(r.part, p.M, ns, resid, st));
@@ -348,13 +382,15 @@ int guarded(F&& f) {
   }
 }
 
-size_t sweep_bytes(Plan& p, int ns, int dtype, int passes, int k) {
+size_t sweep_bytes(Plan& p, int ns, int dtype, int k) {
   Carver c(nullptr, 0);
   c.take<double>(p.panel_elems);                        // FP64 panel
   c.take<double>(p.N * static_cast<int64_t>(ns));       // filtered block
   c.take<double>(8);                                    // bounds
   c.take<int>(8);                                       // status words
-  if (passes == 2) c.take<double>(static_cast<int64_t>(ns) * ns);   // T2
+  c.take<double>(static_cast<int64_t>(ns) * ns);        // inverse of the last Cholesky factor
+  c.take<double>(8);                                    // condition bound
+  c.take<double>(static_cast<int64_t>(cholqr_cond_scratch_elems(ns)));
   const size_t base = c.used;
   Carver cf(nullptr, 0);
   FilterWs f;
@@ -791,7 +827,8 @@ int chefsi_workspace_bytes(chefsi_plan plan, int op, int ns, int dtype, int pass
         if (!valid_dtype(dtype)) return fail(CHEFSI_ERR_ARG, "bad dtype");
         if (lanczos_steps < 1 || lanczos_steps > kMaxLanczos)
           return fail(CHEFSI_ERR_ARG, "lanczos_steps must be in [1, 64]");
-        *bytes = sweep_bytes(p, ns, dtype, passes, lanczos_steps);
+        if (passes < 0 || passes > 2) return fail(CHEFSI_ERR_ARG, "passes must be 0 (auto), 1 or 2");
+        *bytes = sweep_bytes(p, ns, dtype, lanczos_steps);
         return CHEFSI_OK;
       }
       default:
@@ -868,7 +905,7 @@ int chefsi_orthonormalize(int64_t n, int ns, double* d_Y, int64_t ldy, int passe
   return guarded([&]() -> int {
     if (n < 1 || ns < 1) return fail(CHEFSI_ERR_ARG, "n and ns must be >= 1");
     if (ns > n) return fail(CHEFSI_ERR_ARG, "ns must be <= n");
-    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    if (passes < 0 || passes > 2) return fail(CHEFSI_ERR_ARG, "passes must be 0 (auto), 1 or 2");
     CHEFSI_TRY(validate_mv("Y", d_Y, ldy, ns));
     if (d_U && overlaps(d_U, static_cast<size_t>(ns) * ns * 8, d_Y, mv_bytes(n, ldy, ns, 8)))
       return fail(CHEFSI_ERR_ARG, "U and Y overlap");
@@ -888,7 +925,7 @@ int chefsi_orthonormalize_workspace_bytes(int64_t n, int ns, int passes, size_t*
   return guarded([&]() -> int {
     if (bytes == nullptr) return fail(CHEFSI_ERR_ARG, "bytes is NULL");
     if (n < 1 || ns < 1 || ns > n) return fail(CHEFSI_ERR_ARG, "need 1 <= ns <= n");
-    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    if (passes < 0 || passes > 2) return fail(CHEFSI_ERR_ARG, "passes must be 0 (auto), 1 or 2");
     Carver c(nullptr, 0);
     OrthWs o;
     carve_orth(c, n, ns, o);
@@ -933,7 +970,7 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
     if (d_H == nullptr || d_ritz == nullptr) return fail(CHEFSI_ERR_ARG, "H or ritz is NULL");
     if (m < 0 || m > kMaxDegree) return fail(CHEFSI_ERR_ARG, "filter degree must be in [0, 100000]");
     if (!valid_dtype(filter_dtype)) return fail(CHEFSI_ERR_ARG, "bad dtype");
-    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    if (passes < 0 || passes > 2) return fail(CHEFSI_ERR_ARG, "passes must be 0 (auto), 1 or 2");
     if (ns < 1 || ns > p.N) return fail(CHEFSI_ERR_ARG, "ns must be in [1, N]");
     if (d_bounds_in == nullptr) {
       if (d_v0 == nullptr) return fail(CHEFSI_ERR_ARG, "v0 is NULL and no bounds were given");
@@ -942,7 +979,7 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
     }
     CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
     const int lk = (lanczos_steps >= 1 && lanczos_steps <= kMaxLanczos) ? lanczos_steps : 1;
-    const size_t need = sweep_bytes(p, ns, filter_dtype, passes, lk);
+    const size_t need = sweep_bytes(p, ns, filter_dtype, lk);
     CHEFSI_TRY(check_ws(ws, ws_bytes, need));
     CHEFSI_TRY(check_device(p));
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -961,7 +998,9 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
       double* Y = c.take<double>(p.N * static_cast<int64_t>(ns));
       double* bnd = c.take<double>(8);
       int* status = c.take<int>(8);
-      double* T2 = passes == 2 ? c.take<double>(static_cast<int64_t>(ns) * ns) : nullptr;
+      double* Tk = c.take<double>(static_cast<int64_t>(ns) * ns);
+      double* cond = c.take<double>(8);
+      double* cscr = c.take<double>(static_cast<int64_t>(cholqr_cond_scratch_elems(ns)));
       char* rest = static_cast<char*>(ws) + c.used;
       const size_t rest_bytes = ws_bytes - c.used;
       CHEFSI_TRY(mark(0));
@@ -987,16 +1026,24 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         CHEFSI_TRY(run_filter(p, fpanel, filter_dtype, f.coef, m, d_X, ldx, Y, ns, ns, f, st));
       }
       CHEFSI_TRY(mark(3));
-      // step 3: Cholesky-QR
+      // step 3: Cholesky-QR.  The first factor's condition bound decides the
+      // pass count when passes = 0; the last factor's inverse stays in Tk and
+      // is folded into Rayleigh-Ritz.
+      int used = passes;
+      double hcond = 0.0;
       {
         Carver co(rest, rest_bytes);
         OrthWs o;
         carve_orth(co, p.N, ns, o);
         o.status = status;
-        if (passes == 2)
-          CHEFSI_TRY(run_orth_factor2(p.N, ns, Y, ns, d_X, ldx, T2, o, st));   // Yhat1 -> X
-        else
-          CHEFSI_TRY(run_orth(p.N, ns, Y, ns, passes, nullptr, o, st));
+        CHEFSI_TRY(run_orth_factor1(p.N, ns, Y, ns, Tk, o, st));
+        CHEFSI_TRY(cholqr_cond_bound(o.S, Tk, ns, cscr, cond, st));
+        if (passes == 0) {
+          CHEFSI_HIP(hipMemcpyAsync(&hcond, cond, sizeof(double), hipMemcpyDeviceToHost, st));
+          CHEFSI_HIP(hipStreamSynchronize(st));
+          used = auto_passes_from_bound(hcond);
+        }
+        if (used == 2) CHEFSI_TRY(run_orth_pass2(p.N, ns, Y, ns, Tk, d_X, ldx, o, st));   // Yhat1 -> X
       }
       CHEFSI_TRY(mark(4));
       // steps 4-5: Rayleigh-Ritz and rotation
@@ -1005,16 +1052,17 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         RrWs r;
         CHEFSI_TRY(carve_rr(cr, p, ns, false, r));
         r.info = status + 1;
-        if (passes == 2)
-          CHEFSI_TRY(run_rr_factor2(p, panel64, d_X, ldx, ns, T2, Y, d_ritz, d_resid, r, st));
+        if (used == 2)
+          CHEFSI_TRY(run_rr_fold(p, panel64, d_X, ldx, ns, Tk, d_X, ldx, Y, d_ritz, d_resid, r, st));
         else
-          CHEFSI_TRY(run_rr(p, panel64, Y, ns, ns, d_X, ldx, d_ritz, d_resid, nullptr, r, st));
+          CHEFSI_TRY(run_rr_fold(p, panel64, Y, ns, ns, Tk, d_X, ldx, nullptr, d_ritz, d_resid, r, st));
       }
       CHEFSI_TRY(mark(5));
       if (d_bounds_out)
         CHEFSI_HIP(hipMemcpyAsync(d_bounds_out, bnd, 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
       int hs[2] = {0, 0};
       CHEFSI_HIP(hipMemcpyAsync(hs, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      if (passes != 0) CHEFSI_HIP(hipMemcpyAsync(&hcond, cond, sizeof(double), hipMemcpyDeviceToHost, st));
       CHEFSI_HIP(hipStreamSynchronize(st));
       if (stats) {
         float t[5];
@@ -1028,6 +1076,8 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         stats->orthonormalize_ms = t[3];
         stats->rayleigh_ritz_ms = t[4];
         stats->total_ms = tot;
+        stats->cholqr_passes = used;
+        stats->cholqr_cond_bound = hcond;
       }
       if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
       if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");

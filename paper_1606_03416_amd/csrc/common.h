@@ -179,6 +179,11 @@ size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k);
 int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st);
 // d_scr: device scratch of at least min(n, 64)^2 doubles.
 int cholesky_upper(double* S, int64_t lds, int n, int* d_status, double* d_scr, hipStream_t st);
+// Upper bound on the 2-norm condition number of the column-equilibrated block
+// from its Cholesky factor U and T = U^{-1} (n x n, row-major, upper parts
+// used); d_scr holds cholqr_cond_scratch_elems(n) doubles; d_out 1 double.
+size_t cholqr_cond_scratch_elems(int n);
+int cholqr_cond_bound(const double* U, const double* T, int n, double* d_scr, double* d_out, hipStream_t st);
 int trsm_right_upper(double* Y, int64_t ldy, int64_t nrows, const double* U, int64_t ldu, int n,
                      hipStream_t st);
 // Solve X L = Y in place (L lower triangular, n x n row-major).

@@ -779,6 +779,110 @@ int launch_transpose(const double* A, int64_t lda, double* B, int64_t ldb, int r
   return CHEFSI_OK;
 }
 
+// ------------------------------------------- Cholesky-QR condition bound
+// With U the upper Cholesky factor of Y^T Y and T = U^{-1} (both upper, row
+// major; entries below the diagonal are ignored), D_j = ||U[:, j]|| = ||y_j||,
+// U_e = U D^{-1} and T_e = U_e^{-1} = D T:
+//   bound = sqrt(||U_e||_1 ||T_e||_1 ||U_e||_inf ||T_e||_inf) >= kappa_2(Y D^{-1}).
+
+namespace {
+
+__global__ __launch_bounds__(256) void cond_colnorm_kernel(const double* __restrict__ U, int n,
+                                                           double* __restrict__ d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int k = 0; k <= j; ++k) {
+    const double u = U[static_cast<int64_t>(k) * n + j];
+    s += u * u;
+  }
+  d[j] = sqrt(s);
+}
+
+// column sums of |U_e| and |T_e| (thread per column)
+__global__ __launch_bounds__(256) void cond_colsum_kernel(const double* __restrict__ U, const double* __restrict__ T,
+                                                          int n, const double* __restrict__ d,
+                                                          double* __restrict__ cu, double* __restrict__ ct) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double su = 0.0, stt = 0.0;
+  for (int k = 0; k <= j; ++k) {
+    const int64_t o = static_cast<int64_t>(k) * n + j;
+    su += fabs(U[o]);
+    stt += d[k] * fabs(T[o]);
+  }
+  cu[j] = su / d[j];
+  ct[j] = stt;
+}
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return r;
+}
+
+// row sums of |U_e| and |T_e| (work-group per row)
+__global__ __launch_bounds__(256) void cond_rowsum_kernel(const double* __restrict__ U, const double* __restrict__ T,
+                                                          int n, const double* __restrict__ d,
+                                                          double* __restrict__ ru, double* __restrict__ rt) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  const int64_t o = static_cast<int64_t>(i) * n;
+  double su = 0.0, stt = 0.0;
+  for (int j = i + threadIdx.x; j < n; j += blockDim.x) {
+    su += fabs(U[o + j]) / d[j];
+    stt += fabs(T[o + j]);
+  }
+  su = block_sum256(su, red);
+  stt = block_sum256(stt, red);
+  if (threadIdx.x == 0) {
+    ru[i] = su;
+    rt[i] = d[i] * stt;
+  }
+}
+
+__global__ __launch_bounds__(256) void cond_final_kernel(const double* __restrict__ v, int n,
+                                                         double* __restrict__ out) {
+  __shared__ double red[4][4];
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+    for (int q = 0; q < 4; ++q) m[q] = fmax(m[q], v[static_cast<int64_t>(q) * n + j]);
+  for (int q = 0; q < 4; ++q) {
+    for (int o = 32; o > 0; o >>= 1) m[q] = fmax(m[q], __shfl_xor(m[q], o));
+    if ((threadIdx.x & 63) == 0) red[q][threadIdx.x >> 6] = m[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double p = 1.0;
+    for (int q = 0; q < 4; ++q) p *= fmax(fmax(red[q][0], red[q][1]), fmax(red[q][2], red[q][3]));
+    out[0] = sqrt(p);
+  }
+}
+
+}  // namespace
+
+size_t cholqr_cond_scratch_elems(int n) { return 5 * static_cast<size_t>(n); }
+
+int cholqr_cond_bound(const double* U, const double* T, int n, double* d_scr, double* d_out, hipStream_t st) {
+  if (n <= 0) return CHEFSI_OK;
+  double* d = d_scr;
+  double* v = d_scr + n;   // cu, ct, ru, rt
+  const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
+  cond_colnorm_kernel<<<g, 256, 0, st>>>(U, n, d);
+  CHEFSI_LAUNCHED("cond_colnorm");
+  cond_colsum_kernel<<<g, 256, 0, st>>>(U, T, n, d, v, v + n);
+  CHEFSI_LAUNCHED("cond_colsum");
+  cond_rowsum_kernel<<<static_cast<unsigned>(n), 256, 0, st>>>(U, T, n, d, v + 2 * static_cast<int64_t>(n),
+                                                                 v + 3 * static_cast<int64_t>(n));
+  CHEFSI_LAUNCHED("cond_rowsum");
+  cond_final_kernel<<<1, 256, 0, st>>>(v, n, d_out);
+  CHEFSI_LAUNCHED("cond_final");
+  return CHEFSI_OK;
+}
+
 // Vcm: n x n eigenvectors in column-major order (column j = eigenvector j);
 // Q (row-major) gets Q[i][j] = sign_j * Vcm[j*ldv + i].  Q[n..] holds scratch
 // for the n signs: the caller passes Q with room for n*ldq + n doubles.

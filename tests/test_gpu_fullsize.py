@@ -1,7 +1,8 @@
 """Full-size GPU checks on the bulk (12x12x12 elements, 64 ALBs, N_s = 4,096,
 m = 16) and sheet (48x40x1 elements, 5-block stencil, ALB counts drawn from
 {64, 72, ..., 128}, N_s = 8,192, m = 20) workloads, in the launch configuration
-the benchmark times (whole multivector, CholeskyQR2, 20 Lanczos steps).
+the benchmark times (whole multivector, automatic Cholesky-QR pass count, 20
+Lanczos steps).
 
 The oracle cannot filter or diagonalise at these sizes, so the checks are:
 * the filter is column-separable, so sampled columns of the GPU result are
@@ -94,14 +95,18 @@ def rayleigh_checks(name, P, bop, X, ritz, resid, s):
 
 
 def test_sweeps_full_size_properties(case, lib):
-    """Two FP64 sweeps (cold bounds, then warm), as the benchmark runs them."""
+    """Three FP64 sweeps (cold bounds, then warm) with the automatic
+    Cholesky-QR pass count, as the benchmark runs them."""
     w, P, X0, v0, plan, H, ws, bop = case
     X = torch.from_numpy(X0).cuda()
     v0d = torch.from_numpy(v0).cuda()
     ritz = None
-    for i in range(2):
-        ritz, resid, bnd, _ = plan.sweep(H, X, w.m, passes=2, lanczos_steps=w.lanczos_steps, v0=v0d,
-                                         ritz=ritz, warm=i > 0, ws=ws)
+    taken = []
+    for i in range(3):
+        ritz, resid, bnd, st = plan.sweep(H, X, w.m, passes=0, lanczos_steps=w.lanczos_steps, v0=v0d,
+                                          ritz=ritz, warm=i > 0, ws=ws, stats=True)
+        taken.append((int(st["cholqr_passes"]), round(st["cholqr_cond_bound"], 2)))
+    print(f"[{w.name}] (passes, condition bound) per sweep: {taken}")
     bh = bnd.cpu().numpy()
     s = float(max(abs(bh[1]), abs(bh[2])))
     assert bh[2] < bh[0] < bh[1]
@@ -121,7 +126,7 @@ def test_mixed_sweeps_reach_the_fp64_ritz_error(case, lib):
         X = torch.from_numpy(X0).cuda()
         ritz = None
         for i, dt in enumerate(dts):
-            ritz, resid, bnd, _ = plan.sweep(H, X, w.m, dtype=dt, passes=2, lanczos_steps=w.lanczos_steps,
+            ritz, resid, bnd, _ = plan.sweep(H, X, w.m, dtype=dt, passes=0, lanczos_steps=w.lanczos_steps,
                                              v0=v0d, ritz=ritz, warm=i > 0, ws=ws)
         out[label] = (ritz.cpu().numpy(), float(resid[:k].max().item()), bnd.cpu().numpy())
         if label == "mixed":

@@ -174,6 +174,25 @@ def test_orthonormalize_matches_oracle(lib, n, ns, passes):
     assert np.linalg.norm(Yh - Yh_o) / np.linalg.norm(Yh_o) <= 1e-13 * kappa ** (2 if passes == 1 else 1) * 10
 
 
+@pytest.mark.parametrize("n,ns,cond", [(4000, 64, False), (3000, 200, True)])
+def test_orthonormalize_auto_passes_match_oracle(lib, n, ns, cond):
+    """passes = 0: a tall well-conditioned block keeps one pass, a block with
+    two nearly parallel columns takes two, as the oracle decides; results
+    match the oracle's and are orthonormal to 1e-12."""
+    g = np.random.default_rng(n + 7)
+    Y = g.standard_normal((n, ns)) * np.logspace(0, 3, ns)[None, :]
+    if cond:
+        Y[:, 11] = Y[:, 5] * 7.0 + 1e-5 * g.standard_normal(n)
+    Yh_o, U_o, Us_o = oracle.cholesky_qr(Y, 0)
+    assert len(Us_o) == (2 if cond else 1)
+    Yd = dev(Y)
+    U = lib.orthonormalize(Yd, passes=0, want_U=True)
+    Yh = host(Yd)
+    assert np.linalg.norm(Yh.T @ Yh - np.eye(ns), 2) <= 1e-12
+    assert np.linalg.norm(host(U) - U_o) / np.linalg.norm(U_o) <= 1e-12 * np.linalg.cond(Y)
+    assert np.linalg.norm(Yh - Yh_o) / np.linalg.norm(Yh_o) <= 1e-10
+
+
 def test_orthonormalize_not_pd(lib):
     g = np.random.default_rng(1)
     Y = g.standard_normal((300, 20))
@@ -283,3 +302,47 @@ def test_sweep_low_precision_filter_then_f64_finish(lib, low):
         ritz, resid, _, _ = plan.sweep(Hd, X, w.m, dtype=dt, v0=v0d, ritz=ritz, warm=i > 0)
     k = 3 * w.ns // 4
     assert np.max(np.abs(host(ritz)[:k] - lam[:k])) <= 1e-9 * 6
+
+
+@pytest.mark.parametrize("name,ns,m", [("tiny", 48, 10), ("odd_3x3x3_nb40", 300, 12)])
+def test_sweep_auto_passes_match_oracle(lib, name, ns, m):
+    """passes = 0 with the oracle's bounds: every cycle takes the pass count
+    the oracle takes (condition bound of the first factor within 1e-8), its
+    Ritz values match the oracle's within 1e-10, and X stays orthonormal to
+    1e-12.  passes = 1 (the folded single pass) matches the oracle's single
+    pass, within the eps B^2 orthogonality loss of one pass."""
+    P = PROBLEMS[name]()
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    op = oracle.DenseOperator(H)
+    X0 = synth.make_start_block(P.J, ns)
+    v0 = synth.make_lanczos_start(P.N)
+    b, thl, tau = oracle.lanczos_upper_bound(op, v0, 20)
+    plan = mkplan(lib, P)
+    Hd = dev(P.packed())
+    eps = np.finfo(np.float64).eps
+    for passes in (0, 1):
+        bounds = oracle.bounds_cold(b, thl, tau, ns, P.N)
+        Xo, X = X0, dev(X0)
+        taken = []
+        for i in range(5):
+            Yt = oracle.chebyshev_filter(op, Xo, m, *bounds)
+            Yh, _, Us = oracle.cholesky_qr(Yt, passes)
+            Xo, th_o, _, _, _ = oracle.rayleigh_ritz(op, Yh)
+            ritz, resid, _, st = plan.sweep(Hd, X, m, bounds=bounds, passes=passes, stats=True)
+            B = oracle.cholqr_condition_bound(Us[0])
+            tol_orth = 1e-12 if len(Us) == 2 else max(1e-12, 50 * eps * B * B)
+            s = max(abs(bounds[2]), abs(bounds[1]))
+            assert ritz_rel(host(ritz), th_o, s) <= max(1e-10, 10 * tol_orth), (passes, i)
+            Xh = host(X)
+            assert np.linalg.norm(Xh.T @ Xh - np.eye(ns), 2) <= tol_orth, (passes, i, B)
+            assert st["cholqr_passes"] == len(Us), (passes, i)
+            # the first factor of an ill-conditioned block is itself accurate
+            # only to about eps B^2 in its small directions; after a lossy
+            # single-pass cycle the two inputs differ, so passes = 1 compares
+            # the bound of the first cycle only
+            if passes == 0 or i == 0:
+                assert abs(st["cholqr_cond_bound"] - B) <= (1e-8 + 1e-14 * B * B) * B, \
+                    (passes, i, st["cholqr_cond_bound"], B)
+            taken.append(int(st["cholqr_passes"]))
+            bounds = oracle.bounds_warm(th_o, b)
+        print(f"{name} passes={passes}: passes taken per cycle {taken}")
