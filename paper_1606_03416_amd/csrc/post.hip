@@ -133,9 +133,18 @@ __global__ __launch_bounds__(kFermiThreads) void fermi_kernel(const double* __re
 
 // ------------------------------------------------------- element products
 constexpr int kNtThreads = 256;
-constexpr int kNtKC = 32;            // reduction columns per chunk
-constexpr int kNtLD = kNtKC + 2;     // LDS row stride in doubles (rows 4 banks apart)
-constexpr int kNtTargetWG = 4096;    // work-groups a launch aims at (element x slice)
+#ifndef CHEFSI_NT_KC
+#define CHEFSI_NT_KC 32
+#endif
+#ifndef CHEFSI_NT_TARGET
+#define CHEFSI_NT_TARGET 4096
+#endif
+#ifndef CHEFSI_AP_TARGET
+#define CHEFSI_AP_TARGET 8192
+#endif
+constexpr int kNtKC = CHEFSI_NT_KC;          // reduction columns per chunk
+constexpr int kNtLD = kNtKC + 2;             // LDS row stride in doubles (rows 4 banks apart)
+constexpr int kNtTargetWG = CHEFSI_NT_TARGET;  // work-groups a launch aims at (element x slice)
 
 struct NtArgs {
   const double* A; int64_t lda;      // rows rowoff[K] .. rowoff[K]+J_K-1, row stride lda
@@ -200,9 +209,12 @@ __global__ __launch_bounds__(kNtThreads) void elem_nt_kernel(NtArgs a) {
 #pragma unroll
   for (int u = 0; u < PW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // staging: thread -> (row tid/16 + 16p, column pair 2(tid%16))
-  const int srow = tid >> 4, scol = (tid & 15) * 2;
-  d2 ra[RB], rb[RB], rw;
+  // staging: thread -> (row tid/TPR + RPP*p, column pair 2(tid%TPR)), TPR
+  // threads per chunk row, RPP rows per pass, NP passes
+  constexpr int TPR = kNtKC / 2, RPP = kNtThreads / TPR, NP = ROWS / RPP;
+  static_assert(ROWS % RPP == 0, "chunk rows split evenly over the passes");
+  const int srow = tid / TPR, scol = (tid % TPR) * 2;
+  d2 ra[NP], rb[NP], rw;
   auto load = [&](int chunk) {
     const int64_t col = cbeg + static_cast<int64_t>(chunk) * kNtKC + scol;
     const bool c0 = col < cend, c1 = col + 1 < cend;
@@ -213,8 +225,8 @@ __global__ __launch_bounds__(kNtThreads) void elem_nt_kernel(NtArgs a) {
       rw = d2{1.0, 1.0};
     }
 #pragma unroll
-    for (int p = 0; p < RB; ++p) {
-      const int row = srow + 16 * p;
+    for (int p = 0; p < NP; ++p) {
+      const int row = srow + RPP * p;
       d2 va = d2{0.0, 0.0}, vb = d2{0.0, 0.0};
       if (row < JK && c0) {
         const double* pa = a.A + (r0 + row) * a.lda + col;
@@ -240,8 +252,8 @@ __global__ __launch_bounds__(kNtThreads) void elem_nt_kernel(NtArgs a) {
   for (int c = 0; c < nchunk; ++c) {
     __syncthreads();  // the previous chunk's tiles are no longer read
 #pragma unroll
-    for (int p = 0; p < RB; ++p) {
-      const int row = srow + 16 * p;
+    for (int p = 0; p < NP; ++p) {
+      const int row = srow + RPP * p;
       *reinterpret_cast<d2*>(&xs[row * kNtLD + scol]) = ra[p];
       *reinterpret_cast<d2*>(&ys[row * kNtLD + scol]) = rb[p] * rw;
     }
@@ -297,7 +309,7 @@ __global__ __launch_bounds__(256) void nt_reduce_kernel(const double* __restrict
 // --------------------------------------------------- element rotation
 constexpr int kApThreads = 256;
 constexpr int kApCW = 64;              // columns per chunk (16 per wave)
-constexpr int kApTargetWG = 8192;
+constexpr int kApTargetWG = CHEFSI_AP_TARGET;
 
 struct ApplyArgs {
   const double* R;                     // R_K (J_K x J_K row-major) at R + sqoff[K]
