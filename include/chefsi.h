@@ -186,7 +186,7 @@ int chefsi_rayleigh_ritz(chefsi_plan plan, const double* d_H, const double* d_Yh
  * otherwise.  filter_dtype as in chefsi_filter.
  * passes: 1 = one Cholesky-QR pass (as in the paper), 2 = CholeskyQR2,
  * 0 = automatic: one pass when the first factor U_1 shows it is enough, i.e.
- * 10 eps B^2 <= 1e-13 for B = sqrt(k_1 k_inf), k_1 and k_inf the 1- and
+ * 10 eps B^2 <= 1e-12 for B = sqrt(k_1 k_inf), k_1 and k_inf the 1- and
  * inf-norm condition numbers of U_1 D^{-1} (D = column norms of the filtered
  * block Y), an upper bound on the 2-norm condition number of the
  * column-equilibrated Y (one pass loses orthogonality like eps kappa^2);

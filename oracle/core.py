@@ -273,15 +273,15 @@ def solve_right_upper(Y: np.ndarray, U: np.ndarray) -> np.ndarray:
     return Yh
 
 
-# One pass is kept when 10 eps B^2 <= 1e-13 for the condition bound B of the
-# first factor (a predicted orthogonality loss 10x below the 1e-12 target,
-# with a factor 10 over the observed eps kappa^2 behaviour).
-AUTO_LOSS_LIMIT = 1e-13
+# One pass is kept when 10 eps B^2 <= 1e-12 for the condition bound B of the
+# first factor: the predicted orthogonality loss, with a factor 10 over the
+# observed eps kappa^2 behaviour, stays within the 1e-12 target (B >= kappa).
+AUTO_LOSS_LIMIT = 1e-12
 AUTO_LOSS_FACTOR = 10.0
 
 
 def auto_passes(U1: np.ndarray) -> int:
-    """Passes chosen by passes = 0 (auto): 1 if 10 eps B^2 <= 1e-13 for
+    """Passes chosen by passes = 0 (auto): 1 if 10 eps B^2 <= 1e-12 for
     B = cholqr_condition_bound(U1), else 2."""
     B = cholqr_condition_bound(U1)
     return 1 if AUTO_LOSS_FACTOR * np.finfo(np.float64).eps * B * B <= AUTO_LOSS_LIMIT else 2

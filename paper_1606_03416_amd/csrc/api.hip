@@ -217,10 +217,10 @@ int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, 
   return CHEFSI_OK;
 }
 
-// passes = 0 (auto): one pass is kept when 10 eps B^2 <= 1e-13 for the
+// passes = 0 (auto): one pass is kept when 10 eps B^2 <= 1e-12 for the
 // condition bound B of the first factor (B >= kappa_2 of the
 // column-equilibrated block; one pass loses orthogonality like eps kappa^2).
-constexpr double kAutoLossLimit = 1e-13;
+constexpr double kAutoLossLimit = 1e-12;
 constexpr double kAutoLossFactor = 10.0;
 
 int auto_passes_from_bound(double B) {

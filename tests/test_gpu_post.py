@@ -3,8 +3,8 @@ oracle: Fermi level and occupations, diagonal density-matrix blocks (eq.
 densitymatrix), and the re-alignment to a new ALB basis (eq.
 basis_rotation_3).  Small cases cover every row-block class (ALB counts 1 to
 128, ragged tiles), odd and strided leading dimensions and ragged column
-counts; the bulk case runs at full size in the benchmark's launch
-configuration and is compared element by element on sampled elements."""
+counts; the bulk and sheet cases run at full size in the benchmark's launch
+configuration and are compared element by element on sampled elements."""
 import numpy as np
 import pytest
 
@@ -165,11 +165,13 @@ def sub_rows(J, Ks):
     return np.concatenate([np.arange(off[K], off[K + 1]) for K in Ks])
 
 
-def test_bulk_density_and_realign_sampled_elements(lib):
-    """Bulk workload (12^3 elements, 64 ALBs, N_s = 4,096, n_r = 512): GPU
-    density blocks and re-aligned rows of sampled elements against the
-    oracle's element-local definitions."""
-    w = synth.BULK
+@pytest.mark.parametrize("wname", ["bulk", "sheet"])
+def test_full_size_density_and_realign_sampled_elements(lib, wname):
+    """Bulk (12^3 elements, 64 ALBs, N_s = 4,096) and sheet (48 x 40
+    elements, 64-128 ALBs, N_s = 8,192) workloads with n_r = 512: GPU density
+    blocks and re-aligned rows of sampled elements against the oracle's
+    element-local definitions."""
+    w = {"bulk": synth.BULK, "sheet": synth.SHEET}[wname]
     J = synth.draw_alb_counts(w).astype(np.int64)
     plan = lib.Plan(w.grid, w.stencil, J.astype(np.int32))
     X0 = synth.make_start_block(J, w.ns)
@@ -181,7 +183,7 @@ def test_bulk_density_and_realign_sampled_elements(lib):
     ref = oracle.density_diag_blocks(J[Ks], X0[rows], f)
     blocks = plan.split_blocks(P)
     err = max(relf(blocks[K].cpu().numpy(), r) for K, r in zip(Ks, ref))
-    print(f"bulk density blocks, {len(Ks)} sampled elements: worst rel error {err:.2e}")
+    print(f"{wname} density blocks, {len(Ks)} sampled elements: worst rel error {err:.2e}")
     assert err <= 1e-13
     del P
     nr = synth.NR_PER_ELEMENT
@@ -193,7 +195,7 @@ def test_bulk_density_and_realign_sampled_elements(lib):
     ref = oracle.realign(J[Ks], nr, Vn[vrows], V[vrows], X0[rows])
     got = Xd[torch.from_numpy(rows).cuda()].cpu().numpy()
     err = relf(got, ref)
-    print(f"bulk realign, {len(Ks)} sampled elements: rel Frobenius error {err:.2e}")
+    print(f"{wname} realign, {len(Ks)} sampled elements: rel Frobenius error {err:.2e}")
     assert err <= 1e-13
     del Xd
     torch.cuda.empty_cache()
