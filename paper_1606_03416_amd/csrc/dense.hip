@@ -787,32 +787,57 @@ int launch_transpose(const double* A, int64_t lda, double* B, int64_t ldb, int r
 
 namespace {
 
-__global__ __launch_bounds__(256) void cond_colnorm_kernel(const double* __restrict__ U, int n,
-                                                           double* __restrict__ d) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double s = 0.0;
-  for (int k = 0; k <= j; ++k) {
-    const double u = U[static_cast<int64_t>(k) * n + j];
-    s += u * u;
+// Column sums over row stripes of kCondStripe rows: work-group s adds up rows
+// [s*kCondStripe, (s+1)*kCondStripe) for every column (threads walk the
+// columns, so each row is read coalesced) and writes one partial per column;
+// cond_stripe_reduce_kernel sums the stripes in order.
+//   mode 0: part = sum U[k][j]^2                      (k <= j)
+//   mode 1: part = sum |U[k][j]|, part2 = sum d_k |T[k][j]|  (k <= j)
+constexpr int kCondStripe = 16;
+
+__global__ __launch_bounds__(256) void cond_stripe_kernel(const double* __restrict__ U, const double* __restrict__ T,
+                                                          int n, const double* __restrict__ d, int mode,
+                                                          double* __restrict__ part, double* __restrict__ part2) {
+  const int s = blockIdx.x;
+  const int r0 = s * kCondStripe;
+  const int r1 = min(n, r0 + kCondStripe);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    const int kend = min(r1, j + 1);
+    for (int k = r0; k < kend; ++k) {
+      const int64_t o = static_cast<int64_t>(k) * n + j;
+      const double u = U[o];
+      if (mode == 0) {
+        a += u * u;
+      } else {
+        a += fabs(u);
+        b += d[k] * fabs(T[o]);
+      }
+    }
+    part[static_cast<int64_t>(s) * n + j] = a;
+    if (mode == 1) part2[static_cast<int64_t>(s) * n + j] = b;
   }
-  d[j] = sqrt(s);
 }
 
-// column sums of |U_e| and |T_e| (thread per column)
-__global__ __launch_bounds__(256) void cond_colsum_kernel(const double* __restrict__ U, const double* __restrict__ T,
-                                                          int n, const double* __restrict__ d,
-                                                          double* __restrict__ cu, double* __restrict__ ct) {
+// Stripe sums in stripe order; mode 0: d_j = sqrt(sum); mode 1: cu_j = sum/d_j
+// and ct_j = sum2.
+__global__ __launch_bounds__(256) void cond_stripe_reduce_kernel(const double* __restrict__ part,
+                                                                 const double* __restrict__ part2, int nstripe,
+                                                                 int n, int mode, double* __restrict__ d,
+                                                                 double* __restrict__ cu, double* __restrict__ ct) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  double su = 0.0, stt = 0.0;
-  for (int k = 0; k <= j; ++k) {
-    const int64_t o = static_cast<int64_t>(k) * n + j;
-    su += fabs(U[o]);
-    stt += d[k] * fabs(T[o]);
+  double a = 0.0, b = 0.0;
+  for (int s = 0; s < nstripe; ++s) {
+    a += part[static_cast<int64_t>(s) * n + j];
+    if (mode == 1) b += part2[static_cast<int64_t>(s) * n + j];
   }
-  cu[j] = su / d[j];
-  ct[j] = stt;
+  if (mode == 0) {
+    d[j] = sqrt(a);
+  } else {
+    cu[j] = a / d[j];
+    ct[j] = b;
+  }
 }
 
 __device__ __forceinline__ double block_sum256(double v, double* red) {
@@ -864,17 +889,27 @@ __global__ __launch_bounds__(256) void cond_final_kernel(const double* __restric
 
 }  // namespace
 
-size_t cholqr_cond_scratch_elems(int n) { return 5 * static_cast<size_t>(n); }
+size_t cholqr_cond_scratch_elems(int n) {
+  const size_t ns = static_cast<size_t>(ceil_div(n, kCondStripe));
+  return 5 * static_cast<size_t>(n) + 2 * ns * static_cast<size_t>(n);
+}
 
 int cholqr_cond_bound(const double* U, const double* T, int n, double* d_scr, double* d_out, hipStream_t st) {
   if (n <= 0) return CHEFSI_OK;
   double* d = d_scr;
   double* v = d_scr + n;   // cu, ct, ru, rt
+  const int nstripe = static_cast<int>(ceil_div(n, kCondStripe));
+  double* part = d_scr + 5 * static_cast<int64_t>(n);
+  double* part2 = part + static_cast<int64_t>(nstripe) * n;
   const unsigned g = static_cast<unsigned>(ceil_div(n, 256));
-  cond_colnorm_kernel<<<g, 256, 0, st>>>(U, n, d);
-  CHEFSI_LAUNCHED("cond_colnorm");
-  cond_colsum_kernel<<<g, 256, 0, st>>>(U, T, n, d, v, v + n);
-  CHEFSI_LAUNCHED("cond_colsum");
+  cond_stripe_kernel<<<static_cast<unsigned>(nstripe), 256, 0, st>>>(U, T, n, d, 0, part, part2);
+  CHEFSI_LAUNCHED("cond_stripe");
+  cond_stripe_reduce_kernel<<<g, 256, 0, st>>>(part, part2, nstripe, n, 0, d, v, v + n);
+  CHEFSI_LAUNCHED("cond_stripe_reduce");
+  cond_stripe_kernel<<<static_cast<unsigned>(nstripe), 256, 0, st>>>(U, T, n, d, 1, part, part2);
+  CHEFSI_LAUNCHED("cond_stripe");
+  cond_stripe_reduce_kernel<<<g, 256, 0, st>>>(part, part2, nstripe, n, 1, d, v, v + n);
+  CHEFSI_LAUNCHED("cond_stripe_reduce");
   cond_rowsum_kernel<<<static_cast<unsigned>(n), 256, 0, st>>>(U, T, n, d, v + 2 * static_cast<int64_t>(n),
                                                                  v + 3 * static_cast<int64_t>(n));
   CHEFSI_LAUNCHED("cond_rowsum");
