@@ -223,6 +223,15 @@ def test_rayleigh_ritz_matches_oracle(lib, name, ns):
     ok = gaps > 1e-4 * s
     assert np.max(np.abs(Q[:, ok] - Q_o[:, ok])) <= 1e-8
     assert np.max(np.abs(Xn[:, ok] - Xn_o[:, ok])) <= 1e-8
+    # clusters (neighbour gaps <= 1e-4 s): the spanned subspaces agree (all
+    # principal angles near zero)
+    start = 0
+    for i in range(1, ns + 1):
+        if i == ns or th_o[i] - th_o[i - 1] > 1e-4 * s:
+            if i - start >= 2:
+                sv = np.linalg.svd(Xn[:, start:i].T @ Xn_o[:, start:i], compute_uv=False)
+                assert sv.min() >= 1 - 1e-8, (start, i, sv.min())
+            start = i
     assert np.linalg.norm(Xn.T @ Xn - np.eye(ns), 2) <= 1e-12
 
 
