@@ -126,8 +126,13 @@ def cpu_baseline(w, P, X0, v0, passes, sample_cols):
 
 def filter_mode(args, w, P, plan, H, X0d, chefsi, torch):
     """Time p_m(H)X alone and report the step kernel's roofline: FP64 and FP32
-    steps are MFMA-bound, BF16 steps HBM-bound (intensity below the ridge)."""
+    steps are MFMA-bound, BF16 steps HBM-bound (intensity below the ridge).
+    --cols c filters only the first c columns: one GPU's share of a
+    column-sharded filter (the filter needs no communication across shards)."""
     ns, m = w.ns, w.m
+    if args.cols:
+        ns = min(int(args.cols), ns)
+        X0d = X0d[:, :ns].contiguous()
     dt = {"f64": chefsi.F64, "f32": chefsi.F32, "bf16": chefsi.BF16}[args.filter_dtype]
     esz = {"f64": 8, "f32": 4, "bf16": 2}[args.filter_dtype]
     dev = X0d.device
@@ -168,6 +173,7 @@ def filter_mode(args, w, P, plan, H, X0d, chefsi, torch):
                 "peak": pk, "unit": "TFLOP/s", "frac": round(achieved / pk, 4), "flops_per_launch": f_step}
     out = {
         "mode": "filter", "workload": w.name, "N": P.N, "ns": ns, "filter_degree": m,
+        "columns_of": w.ns,
         "filter_dtype": args.filter_dtype,
         "avg_step_ms": round(step_ms, 4), "filter_ms": round(step_ms * m, 3),
         "roofline": roof,
@@ -255,6 +261,9 @@ def main():
     ap.add_argument("--mode", default="sweep", choices=["sweep", "filter"],
                     help="filter: time only the FP64 Chebyshev filter (the dominant kernel), "
                          "with a plain device copy of known size for counter calibration")
+    ap.add_argument("--cols", type=int, default=0,
+                    help="--mode filter: filter only this many columns (one GPU's share of a column-sharded "
+                         "filter)")
     ap.add_argument("--filter-dtype", default="f64", choices=["f64", "f32", "bf16"],
                     help="arithmetic of the filter in --mode filter")
     args = ap.parse_args()
