@@ -198,7 +198,8 @@ int chefsi_rayleigh_ritz(chefsi_plan plan, const double* d_H, const double* d_Yh
  * d_bounds_out (3, may be NULL: the bounds used), stats (host, may be NULL:
  * per-stage event times, passes taken, condition bound).  Synchronises the
  * stream once at the end to read status words, and with passes = 0 also once
- * after the first factor to read its condition bound. */
+ * after the first factor to read its condition bound (a failed first factor
+ * then returns CHEFSI_ERR_NOT_PD at once, with d_X unchanged). */
 int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, int passes,
                  int lanczos_steps, const double* d_v0, const double* d_bounds_in, int warm,
                  double* d_X, int64_t ldx, int ns, double* d_ritz, double* d_resid,

@@ -256,8 +256,11 @@ int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout
     if (passes == 0 && pass == 0) {
       CHEFSI_TRY(cholqr_cond_bound(o.S, o.T, ns, o.cscr, o.cond, st));
       double h = 0.0;
+      int hs0 = 0;
       CHEFSI_HIP(hipMemcpyAsync(&h, o.cond, sizeof(double), hipMemcpyDeviceToHost, st));
+      CHEFSI_HIP(hipMemcpyAsync(&hs0, o.status, sizeof(int), hipMemcpyDeviceToHost, st));
       CHEFSI_HIP(hipStreamSynchronize(st));
+      if (hs0 != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
       used = auto_passes_from_bound(h);
     }
   }
@@ -1039,8 +1042,12 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         CHEFSI_TRY(run_orth_factor1(p.N, ns, Y, ns, Tk, o, st));
         CHEFSI_TRY(cholqr_cond_bound(o.S, Tk, ns, cscr, cond, st));
         if (passes == 0) {
+          int hs0 = 0;
           CHEFSI_HIP(hipMemcpyAsync(&hcond, cond, sizeof(double), hipMemcpyDeviceToHost, st));
+          CHEFSI_HIP(hipMemcpyAsync(&hs0, status, sizeof(int), hipMemcpyDeviceToHost, st));
           CHEFSI_HIP(hipStreamSynchronize(st));
+          // the host has synchronised anyway: stop here if the factor failed
+          if (hs0 != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
           used = auto_passes_from_bound(hcond);
         }
         if (used == 2) CHEFSI_TRY(run_orth_pass2(p.N, ns, Y, ns, Tk, d_X, ldx, o, st));   // Yhat1 -> X

@@ -193,13 +193,28 @@ def test_orthonormalize_auto_passes_match_oracle(lib, n, ns, cond):
     assert np.linalg.norm(Yh - Yh_o) / np.linalg.norm(Yh_o) <= 1e-10
 
 
-def test_orthonormalize_not_pd(lib):
+@pytest.mark.parametrize("passes", [0, 1, 2])
+def test_orthonormalize_not_pd(lib, passes):
     g = np.random.default_rng(1)
     Y = g.standard_normal((300, 20))
     Y[:, 7] = 0.0
     with pytest.raises(lib.ChefsiError) as e:
-        lib.orthonormalize(dev(Y), passes=1)
+        lib.orthonormalize(dev(Y), passes=passes)
     assert e.value.code == lib.ERR_NOT_PD
+
+
+def test_sweep_not_pd_auto_leaves_x_unchanged(lib):
+    """A zero column makes the filtered block rank deficient: the automatic
+    pass count stops after the first factor with NOT_PD and X untouched."""
+    P = synth.make_problem(synth.TINY)
+    plan = mkplan(lib, P)
+    X0 = synth.make_start_block(P.J, 48)
+    X0[:, 5] = 0.0
+    X = dev(X0)
+    with pytest.raises(lib.ChefsiError) as e:
+        plan.sweep(dev(P.packed()), X, 10, bounds=(0.5, 6.0, -1.5), passes=0)
+    assert e.value.code == lib.ERR_NOT_PD
+    assert np.array_equal(host(X), X0)
 
 
 # ---------------------------------------------------------------- Rayleigh-Ritz
