@@ -55,7 +55,7 @@ def case(request, lib):
     dev = torch.device("cuda", 0)
     H = torch.from_numpy(P.packed()).to(dev)
     ws = torch.empty(max(plan.workspace_bytes(lib.OP_SWEEP, w.ns, dt, 2, w.lanczos_steps)
-                         for dt in (lib.F64, lib.F32)), dtype=torch.uint8, device=dev)
+                         for dt in (lib.F64, lib.F32, lib.BF16)), dtype=torch.uint8, device=dev)
     bop = oracle.BlockOperator(P.grid, P.stencil, P.J, P.blocks)
     print(f"\n[{w.name}] N={P.N} ns={w.ns} m={w.m}", flush=True)
     yield w, P, X0, v0, plan, H, ws, bop
@@ -129,27 +129,36 @@ def test_sweeps_full_size_properties(case, lib):
 
 
 def test_mixed_sweeps_reach_the_fp64_ritz_error(case, lib):
-    """Two FP32-filter sweeps then two FP64 sweeps from the same start as four
-    FP64 sweeps: the wanted (lowest 3/4) Ritz values agree and the mixed run's
-    worst wanted residual is that of the FP64 run (5 % slack)."""
+    """Two low-precision-filter sweeps then two FP64 sweeps from the same start
+    as four FP64 sweeps.  FP32: the wanted (lowest 3/4) Ritz values agree to
+    1e-8 and the worst wanted residual is that of the FP64 run (5 % slack).
+    BF16: orthonormal Ritz pairs whose values agree to 1e-6, with a worst
+    wanted residual within 4x of the FP64 run's (measured 1.04x on the bulk
+    workload and 3.2x on the sheet, whose wider spectrum needs more FP64
+    cycles after the BF16 ones)."""
     w, P, X0, v0, plan, H, ws, bop = case
     v0d = torch.from_numpy(v0).cuda()
     k = 3 * w.ns // 4
-    out = {}
-    for label, dts in (("f64", [lib.F64] * 4), ("mixed", [lib.F32] * 2 + [lib.F64] * 2)):
+
+    def run(dts):
         X = torch.from_numpy(X0).cuda()
         ritz = None
         for i, dt in enumerate(dts):
             ritz, resid, bnd, _ = plan.sweep(H, X, w.m, dtype=dt, passes=0, lanczos_steps=w.lanczos_steps,
                                              v0=v0d, ritz=ritz, warm=i > 0, ws=ws)
-        out[label] = (ritz.cpu().numpy(), float(resid[:k].max().item()), bnd.cpu().numpy())
-        if label == "mixed":
-            s = float(max(abs(out[label][2][1]), abs(out[label][2][2])))
-            rayleigh_checks(w.name + " mixed", P, bop, X, ritz, resid, s)
-        del X
-    (t64, r64, b64), (tmx, rmx, _) = out["f64"], out["mixed"]
+        return X, ritz, resid, bnd.cpu().numpy()
+
+    X, t64, r64, b64 = run([lib.F64] * 4)
+    t64, r64 = t64.cpu().numpy(), float(r64[:k].max().item())
+    del X
     s = float(max(abs(b64[1]), abs(b64[2])))
-    dth = np.max(np.abs(tmx[:k] - t64[:k]) / np.maximum(np.abs(t64[:k]), s))
-    print(f"[{w.name}] max wanted residual: FP64 {r64:.3e}, mixed {rmx:.3e}; Ritz rel diff {dth:.3e}")
-    assert rmx <= 1.05 * r64
-    assert dth <= 1e-8
+    for name, low, rtol, ttol in (("FP32", lib.F32, 1.05, 1e-8), ("BF16", lib.BF16, 4.0, 1e-6)):
+        X, tmx, rmx, bmx = run([low] * 2 + [lib.F64] * 2)
+        rayleigh_checks(f"{w.name} {name} mixed", P, bop, X, tmx, rmx,
+                        float(max(abs(bmx[1]), abs(bmx[2]))))
+        tmx, rmx = tmx.cpu().numpy(), float(rmx[:k].max().item())
+        dth = np.max(np.abs(tmx[:k] - t64[:k]) / np.maximum(np.abs(t64[:k]), s))
+        print(f"[{w.name}] max wanted residual: FP64 {r64:.3e}, {name} mixed {rmx:.3e}; Ritz rel diff {dth:.3e}")
+        assert rmx <= rtol * r64
+        assert dth <= ttol
+        del X
