@@ -180,8 +180,11 @@ int chefsi_rayleigh_ritz(chefsi_plan plan, const double* d_H, const double* d_Yh
 
 /* ----------------------------------------------------------------- sweep --
  * One CheFSI cycle (Algorithm 1, steps 1-5), X updated in place.
- * Bounds: if d_bounds_in (device, a, b, a0) is non-NULL they are used as
- * given; otherwise step 1 runs as in chefsi_bounds with d_v0 and
+ * Bounds: if d_bounds_in (device, a, b, a0) is non-NULL and warm == 0 they are
+ * used as given; if d_bounds_in is non-NULL and warm != 0, b is taken from
+ * d_bounds_in[1] (the Lanczos upper bound depends only on H, so a later cycle
+ * may reuse it) and a, a0 come from d_ritz on entry by the rule of
+ * chefsi_bounds; otherwise step 1 runs as in chefsi_bounds with d_v0 and
  * lanczos_steps, warm (a, a0 from d_ritz on entry) if `warm` != 0, cold
  * otherwise.  filter_dtype as in chefsi_filter.
  * passes: 1 = one Cholesky-QR pass (as in the paper), 2 = CholeskyQR2,

@@ -1009,7 +1009,11 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
       CHEFSI_TRY(mark(0));
       CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, panel64, st));
       // step 1: bounds
-      if (d_bounds_in) {
+      if (d_bounds_in && warm) {
+        // the upper bound b is fixed per H: taken from the given bounds, with
+        // a and a0 from the previous Ritz values
+        CHEFSI_TRY(launch_warm_bounds(d_ritz, ns, d_bounds_in, bnd, st));
+      } else if (d_bounds_in) {
         CHEFSI_HIP(hipMemcpyAsync(bnd, d_bounds_in, 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
       } else {
         CHEFSI_TRY(lanczos_bounds(p, panel64, d_v0, lanczos_steps, warm ? d_ritz : nullptr, ns, bnd, rest,

@@ -214,7 +214,9 @@ size_t lanczos_ws_bytes(const Plan& p, int k);
 int lanczos_bounds(const Plan& p, const void* d_panel64, const double* d_v0, int k,
                    const double* d_ritz_prev, int ns, double* d_bounds, void* ws, size_t ws_bytes,
                    hipStream_t st);
-int launch_warm_bounds(const double* d_ritz, int ns, const double* d_b_src, double* d_bounds,
+// d_bounds = (a, b, a0) with b = d_bounds_src[1] and a, a0 from the ascending
+// Ritz values (largest, smallest; a0 separated from a as in chefsi_bounds).
+int launch_warm_bounds(const double* d_ritz, int ns, const double* d_bounds_src, double* d_bounds,
                        hipStream_t st);
 
 // Steps around the cycle (post.hip).

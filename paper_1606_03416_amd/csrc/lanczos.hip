@@ -385,9 +385,9 @@ int lanczos_bounds(const Plan& p, const void* d_panel64, const double* d_v0, int
   return CHEFSI_OK;
 }
 
-int launch_warm_bounds(const double* d_ritz, int ns, const double* d_b_src, double* d_bounds,
+int launch_warm_bounds(const double* d_ritz, int ns, const double* d_bounds_src, double* d_bounds,
                        hipStream_t st) {
-  warm_bounds_kernel<<<1, 64, 0, st>>>(d_ritz, ns, d_b_src, d_bounds);
+  warm_bounds_kernel<<<1, 64, 0, st>>>(d_ritz, ns, d_bounds_src, d_bounds);
   CHEFSI_LAUNCHED("warm_bounds");
   return CHEFSI_OK;
 }

@@ -370,3 +370,25 @@ def test_sweep_auto_passes_match_oracle(lib, name, ns, m):
             taken.append(int(st["cholqr_passes"]))
             bounds = oracle.bounds_warm(th_o, b)
         print(f"{name} passes={passes}: passes taken per cycle {taken}")
+
+
+def test_sweep_warm_reuses_the_lanczos_bound(lib):
+    """Warm cycles given the previous bounds take b from them and a, a0 from
+    the Ritz values: bit-identical to recomputing the (deterministic) Lanczos
+    bound every cycle."""
+    w = synth.TINY
+    P = synth.make_problem(w)
+    plan = mkplan(lib, P)
+    Hd = dev(P.packed())
+    v0d = dev(synth.make_lanczos_start(P.N))
+    X0 = synth.make_start_block(P.J, w.ns)
+    XA, XB = dev(X0), dev(X0)
+    rA = rB = bB = None
+    for i in range(4):
+        rA, _, bA, _ = plan.sweep(Hd, XA, w.m, v0=v0d, ritz=rA, warm=i > 0, passes=0)
+        if i == 0:
+            rB, _, bB, _ = plan.sweep(Hd, XB, w.m, v0=v0d, ritz=rB, warm=False, passes=0)
+        else:
+            rB, _, bB, _ = plan.sweep(Hd, XB, w.m, bounds=bB, ritz=rB, warm=True, passes=0)
+        assert torch.equal(bA, bB), (i, host(bA), host(bB))
+        assert torch.equal(rA, rB) and torch.equal(XA, XB)
