@@ -57,7 +57,7 @@ typedef enum {
   CHEFSI_ERR_NOT_PD = 4,      /* Cholesky met a pivot <= 0 or not finite          */
   CHEFSI_ERR_EIG = 5,         /* the dense eigensolver did not converge           */
   CHEFSI_ERR_NONFINITE = 6,   /* a non-finite value where a finite one is needed  */
-  CHEFSI_ERR_UNSUPPORTED = 7  /* valid request this build does not implement      */
+  CHEFSI_ERR_UNSUPPORTED = 7  /* valid request the library does not implement     */
 } chefsi_status;
 
 typedef enum { CHEFSI_F64 = 0, CHEFSI_F32 = 1, CHEFSI_BF16 = 2 } chefsi_dtype;
