@@ -159,18 +159,29 @@ struct NtArgs {
 };
 
 // Tiles of an RB x RB tile grid handled by one product: all of them, or the
-// ones on and above the diagonal (symmetric products).
+// ones on and above the diagonal (symmetric products); the work-group has the
+// fewest waves, from 4 to 8, that gives the fewest tiles per wave, so the
+// waves carry equal MFMA work (10 upper tiles of a 64-row element: 5 waves of
+// 2).  The first kNtThreads threads stage the operands.
 template <int RB, bool SYM>
 struct NtTiles {
   static constexpr int T = SYM ? RB * (RB + 1) / 2 : RB * RB;
-  static constexpr int PER_WAVE = (T + 3) / 4;
+  static constexpr int waves() {
+    int best = 4;
+    for (int w = 5; w <= 8; ++w)
+      if ((T + w - 1) / w < (T + best - 1) / best) best = w;
+    return best;
+  }
+  static constexpr int NW = waves();
+  static constexpr int PER_WAVE = (T + NW - 1) / NW;
 };
 
 template <int RB, bool SYM>
-__global__ __launch_bounds__(kNtThreads) void elem_nt_kernel(NtArgs a) {
+__global__ __launch_bounds__((NtTiles<RB, SYM>::NW * 64)) void elem_nt_kernel(NtArgs a) {
   constexpr int ROWS = RB * 16;
   constexpr int PW = NtTiles<RB, SYM>::PER_WAVE;
   constexpr int T = NtTiles<RB, SYM>::T;
+  constexpr int NW = NtTiles<RB, SYM>::NW;
   __shared__ __attribute__((aligned(16))) double xs[ROWS * kNtLD];
   __shared__ __attribute__((aligned(16))) double ys[ROWS * kNtLD];
 
@@ -190,7 +201,7 @@ __global__ __launch_bounds__(kNtThreads) void elem_nt_kernel(NtArgs a) {
   int ti[PW], tj[PW];
 #pragma unroll
   for (int u = 0; u < PW; ++u) {
-    const int t = wave + 4 * u;
+    const int t = wave + NW * u;
     ti[u] = -1;
     tj[u] = -1;
     if (t < T) {
@@ -248,17 +259,20 @@ __global__ __launch_bounds__(kNtThreads) void elem_nt_kernel(NtArgs a) {
     }
   };
 
-  if (nchunk > 0) load(0);
+  const bool stager = tid < kNtThreads;
+  if (stager && nchunk > 0) load(0);
   for (int c = 0; c < nchunk; ++c) {
     __syncthreads();  // the previous chunk's tiles are no longer read
+    if (stager) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int row = srow + RPP * p;
-      *reinterpret_cast<d2*>(&xs[row * kNtLD + scol]) = ra[p];
-      *reinterpret_cast<d2*>(&ys[row * kNtLD + scol]) = rb[p] * rw;
+      for (int p = 0; p < NP; ++p) {
+        const int row = srow + RPP * p;
+        *reinterpret_cast<d2*>(&xs[row * kNtLD + scol]) = ra[p];
+        *reinterpret_cast<d2*>(&ys[row * kNtLD + scol]) = rb[p] * rw;
+      }
     }
     __syncthreads();
-    if (c + 1 < nchunk) load(c + 1);
+    if (stager && c + 1 < nchunk) load(c + 1);
 #pragma unroll
     for (int g = 0; g < kNtKC / 8; ++g) {
       const int k = 8 * g + 2 * lq;
@@ -409,7 +423,7 @@ size_t apply_lds_bytes() {
 
 template <int RB, bool SYM>
 int launch_nt_group(const NtArgs& a, int nwg, hipStream_t st) {
-  hipLaunchKernelGGL((elem_nt_kernel<RB, SYM>), dim3(nwg), dim3(kNtThreads), 0, st, a);
+  hipLaunchKernelGGL((elem_nt_kernel<RB, SYM>), dim3(nwg), dim3(NtTiles<RB, SYM>::NW * 64), 0, st, a);
   CHEFSI_LAUNCHED("elem_nt_kernel");
   return CHEFSI_OK;
 }
