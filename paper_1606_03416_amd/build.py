@@ -1,7 +1,8 @@
 """Build the gfx950 C-ABI library libchefsi.so in-tree with hipcc.
 
 Every HIP source under csrc/ is compiled for gfx950 only, then linked into
-paper_1606_03416_amd/libchefsi.so (rocSOLVER provides the dense eigensolver).
+paper_1606_03416_amd/libchefsi.so (rocSOLVER provides the tridiagonal eigensolver and
+the back-transformation of its eigenvectors; rocBLAS the rank-2k updates).
 """
 from __future__ import annotations
 

@@ -316,7 +316,7 @@ int run_rr_fold(Plan& p, const void* panel64, const double* B, int64_t ldb, int 
   CHEFSI_TRY(gemm_tn(ns, ns, ns, 1.0, T, ns, r.Q, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
   CHEFSI_TRY(launch_fill_int(r.info, 1, 0, st));
-  CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.eig, r.eig_bytes, st));
+  CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.Q, r.eig, r.eig_bytes, st));
   CHEFSI_TRY(launch_eigvec_fix(r.Hh, ns, ns, r.Q, ns, st));
   // X = B (T Q)
   CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, T, ns, r.Q, ns, 0.0, r.Hh, ns, st));
@@ -342,7 +342,7 @@ int run_rr(Plan& p, const void* panel64, const double* Yh, int64_t ldy, int ns, 
   CHEFSI_TRY(gemm_tn(ns, ns, p.N, 1.0, Yh, ldy, r.W, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
   CHEFSI_TRY(launch_fill_int(r.info, 1, 0, st));
-  CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.eig, r.eig_bytes, st));
+  CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.Q, r.eig, r.eig_bytes, st));
   CHEFSI_TRY(launch_eigvec_fix(r.Hh, ns, ns, r.Q, ns, st));
   CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, Yh, ldy, r.Q, ns, 0.0, Xn, ldx, st));
   if (resid != nullptr) {
@@ -1174,7 +1174,7 @@ int chefsi_loss_backward(chefsi_plan plan, const double* d_H, int m, double a, d
     }
     CHEFSI_TRY(gemm_tn(ns, ns, N, 1.0, Yh, ns, w.W, ns, 0.0, w.Hh, ns, false, w.split, w.split_elems, st));
     CHEFSI_TRY(launch_symmetrize(w.Hh, ns, ns, 0, st));
-    CHEFSI_TRY(eig_sym(p, w.Hh, ns, ns, w.theta, w.E, w.status + 1, w.eig, w.eig_bytes, st));
+    CHEFSI_TRY(eig_sym(p, w.Hh, ns, ns, w.theta, w.E, w.status + 1, w.Q, w.eig, w.eig_bytes, st));
     CHEFSI_TRY(launch_eigvec_fix(w.Hh, ns, ns, w.Q, ns, st));
     CHEFSI_TRY(launch_sum_first(w.theta, k, w.loss, st));
     // ---- backward: Rayleigh-Ritz

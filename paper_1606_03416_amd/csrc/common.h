@@ -92,7 +92,7 @@ struct Plan {
   int64_t sqtot = 0;
   int64_t* d_sqoff = nullptr;   // [M+1]
   void* rocblas = nullptr;      // rocblas_handle for the dense eigensolver
-  size_t eig_ws_cache_n = 0, eig_ws_cache_bytes = 0;
+  size_t eig_ws_cache_n = 0, eig_ws_cache_bytes = 0, eig_ws_cache_roc = 0;
 };
 
 inline Plan* P(chefsi_plan p) { return reinterpret_cast<Plan*>(p); }
@@ -206,8 +206,12 @@ int launch_transpose(const double* A, int64_t lda, double* B, int64_t ldb, int r
 
 // Eigensolver (eig.hip)
 int eig_workspace_bytes(Plan& p, int n, size_t* bytes);
-int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, int* d_info,
+int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, int* d_info, double* Z,
             void* d_ws, size_t ws_bytes, hipStream_t st);
+// Householder tridiagonalisation (tridiag.hip), LAPACK lower format
+size_t tridiag_scratch_bytes(int n);
+int tridiag_lower(void* rocblas_h, double* A, int64_t lda, int n, double* D, double* E, double* tau,
+                  void* scratch, hipStream_t st);
 
 // Lanczos (lanczos.hip)
 size_t lanczos_ws_bytes(const Plan& p, int k);

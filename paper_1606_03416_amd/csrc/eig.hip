@@ -1,7 +1,10 @@
 // Dense symmetric eigensolve of the projected matrix Hhat (Algorithm 1 step 4)
-// on the GPU through rocSOLVER's divide-and-conquer driver (dsyevd), in FP64.
-// rocSOLVER's device scratch comes from the caller's workspace
-// (rocblas_set_workspace), so the call allocates nothing itself.
+// on the GPU, in FP64: Householder reduction to tridiagonal form by the
+// library's own kernels (tridiag.hip), then rocSOLVER's tridiagonal
+// divide-and-conquer (dstedc, eigenvectors of T) and its back-transformation
+// by the reflectors (dormtr).  rocSOLVER's device scratch and the reduction's
+// scratch come from the caller's workspace (rocblas_set_workspace), so the
+// call allocates nothing itself.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -31,21 +34,27 @@ int eig_workspace_bytes(Plan& p, int n, size_t* bytes) {
   rocblas_handle h = static_cast<rocblas_handle>(p.rocblas);
   if (rocblas_start_device_memory_size_query(h) != rocblas_status_success)
     return fail(CHEFSI_ERR_HIP, "rocblas size query start failed");
-  rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, nullptr, n, nullptr, nullptr,
-                   nullptr);
+  rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, nullptr, nullptr, nullptr, n, nullptr);
+  rocsolver_dormtr(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n, n, nullptr, n,
+                   nullptr, nullptr, n);
   size_t sz = 0;
   if (rocblas_stop_device_memory_size_query(h, &sz) != rocblas_status_success)
     return fail(CHEFSI_ERR_HIP, "rocblas size query stop failed");
+  const size_t roc = static_cast<size_t>(round_up(static_cast<int64_t>(sz), 256));
+  const size_t tau = static_cast<size_t>(round_up(static_cast<int64_t>(n) * 8, 256));
   p.eig_ws_cache_n = static_cast<size_t>(n);
-  p.eig_ws_cache_bytes = sz;
-  *bytes = sz;
+  p.eig_ws_cache_roc = roc;
+  p.eig_ws_cache_bytes = roc + tau + tridiag_scratch_bytes(n);
+  *bytes = p.eig_ws_cache_bytes;
   return CHEFSI_OK;
 }
 
-// A (n x n, symmetric, upper triangle read) is overwritten by eigenvectors in
-// column-major order; d_w gets the eigenvalues ascending; d_E (n) is scratch.
-int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, int* d_info,
+// A (n x n, symmetric, lower triangle read) is overwritten by eigenvectors in
+// column-major order; d_w gets the eigenvalues ascending; d_E (n) and Z (n x n,
+// leading dimension n) are scratch.
+int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, int* d_info, double* Z,
             void* d_ws, size_t ws_bytes, hipStream_t st) {
+  if (n <= 0) return CHEFSI_OK;
   CHEFSI_TRY(ensure_handle(p));
   size_t need = 0;
   CHEFSI_TRY(eig_workspace_bytes(p, n, &need));
@@ -53,13 +62,20 @@ int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, in
   rocblas_handle h = static_cast<rocblas_handle>(p.rocblas);
   if (rocblas_set_stream(h, st) != rocblas_status_success)
     return fail(CHEFSI_ERR_HIP, "rocblas_set_stream failed");
-  if (rocblas_set_workspace(h, need ? d_ws : nullptr, need) != rocblas_status_success)
+  const size_t roc = p.eig_ws_cache_roc;
+  if (rocblas_set_workspace(h, roc ? d_ws : nullptr, roc) != rocblas_status_success)
     return fail(CHEFSI_ERR_HIP, "rocblas_set_workspace failed");
-  rocblas_status s = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, A,
-                                      static_cast<rocblas_int>(lda), d_w, d_E, d_info);
+  double* tau = reinterpret_cast<double*>(static_cast<char*>(d_ws) + roc);
+  void* scratch = static_cast<char*>(d_ws) + roc + round_up(static_cast<int64_t>(n) * 8, 256);
+  CHEFSI_TRY(tridiag_lower(h, A, lda, n, d_w, d_E, tau, scratch, st));
+  rocblas_status s = rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, d_w, d_E, Z, n, d_info);
   if (s != rocblas_status_success)
-    return fail(CHEFSI_ERR_EIG, std::string("rocsolver_dsyevd: ") + rocblas_status_to_string(s));
-  return CHEFSI_OK;
+    return fail(CHEFSI_ERR_EIG, std::string("rocsolver_dstedc: ") + rocblas_status_to_string(s));
+  s = rocsolver_dormtr(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n, n, A,
+                       static_cast<rocblas_int>(lda), tau, Z, n);
+  if (s != rocblas_status_success)
+    return fail(CHEFSI_ERR_EIG, std::string("rocsolver_dormtr: ") + rocblas_status_to_string(s));
+  return launch_copy_f64(Z, n, A, lda, n, n, st);
 }
 
 void destroy_eig_handle(Plan& p) {

@@ -250,6 +250,56 @@ def test_rayleigh_ritz_matches_oracle(lib, name, ns):
     assert np.linalg.norm(Xn.T @ Xn - np.eye(ns), 2) <= 1e-12
 
 
+@pytest.mark.parametrize("ns", [1, 2, 3, 63, 64, 65, 127, 128, 129])
+def test_rayleigh_ritz_subspace_sizes(lib, ns):
+    """Projected matrices of order 1 to 129: one and several 64 x 64 tiles of
+    the tridiagonal reduction, panel boundaries at 64 and 128, ragged tails."""
+    P = PROBLEMS["odd_3x3x3_nb40"]()
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    Yh, _ = np.linalg.qr(np.random.default_rng(ns).standard_normal((P.N, ns)))
+    Xn_o, th_o, _, Q_o, _ = oracle.rayleigh_ritz(oracle.DenseOperator(H), Yh)
+    Xn, th, _, Q = mkplan(lib, P).rayleigh_ritz(dev(P.packed()), dev(Yh), want_Q=True)
+    th, Xn, Q = host(th), host(Xn), host(Q)
+    s = float(np.max(np.abs(th_o)))
+    assert ritz_rel(th, th_o, s) <= 1e-10
+    gaps = np.minimum(np.diff(th_o, prepend=-np.inf), np.diff(th_o, append=np.inf))
+    ok = gaps > 1e-4 * s
+    assert np.max(np.abs(Q[:, ok] - Q_o[:, ok])) <= 1e-8
+    assert np.linalg.norm(Q.T @ Q - np.eye(ns), 2) <= 1e-12
+    assert np.linalg.norm(Xn.T @ Xn - np.eye(ns), 2) <= 1e-12
+
+
+def test_rayleigh_ritz_diagonal_projection(lib):
+    """One unit vector per element of an independent set of elements (no two
+    are stencil neighbours): the projected matrix is exactly diagonal, so
+    every Householder reflector of the reduction is the identity.  The Ritz
+    values are the selected diagonal entries of H, sorted, and the Ritz
+    vectors are the unit vectors in that order."""
+    J = np.full(216, 8, dtype=np.int32)
+    P = synth.make_blocks((6, 6, 6), 7, J)
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    rows = []
+    for z in range(6):
+        for y in range(6):
+            for x in range(6):
+                if (x + y + z) % 3 == 0:
+                    K = x + 6 * (y + 6 * z)
+                    rows.append(8 * K + (K % 8))
+    rows = np.array(rows)
+    ns = rows.size
+    Yh = np.zeros((P.N, ns))
+    Yh[rows, np.arange(ns)] = 1.0
+    Hh = H[np.ix_(rows, rows)]
+    assert np.count_nonzero(Hh - np.diag(np.diag(Hh))) == 0
+    Xn, th, _, _ = mkplan(lib, P).rayleigh_ritz(dev(P.packed()), dev(Yh), want_Q=True)
+    th, Xn = host(th), host(Xn)
+    d = np.diag(Hh)
+    order = np.argsort(d, kind="stable")
+    assert np.min(np.diff(d[order])) > 1e-9
+    assert np.max(np.abs(th - d[order])) <= 1e-15 * np.max(np.abs(d))
+    assert np.max(np.abs(np.abs(Xn) - Yh[:, order])) <= 1e-15
+
+
 # ---------------------------------------------------------------- bounds
 @pytest.mark.parametrize("name", ["tiny", "mixed_5pt"])
 def test_bounds_match_oracle(lib, name):
