@@ -159,15 +159,17 @@ struct NtArgs {
 };
 
 // Tiles of an RB x RB tile grid handled by one product: all of them, or the
-// ones on and above the diagonal (symmetric products); the work-group has the
-// fewest waves, from 4 to 8, that gives the fewest tiles per wave, so the
-// waves carry equal MFMA work (10 upper tiles of a 64-row element: 5 waves of
-// 2).  The first kNtThreads threads stage the operands.
+// ones on and above the diagonal (symmetric products).  Up to 16 tiles, the
+// work-group has the fewest waves, from 4 to 8, that gives the fewest tiles per
+// wave, so the waves carry equal MFMA work (10 upper tiles of a 64-row element:
+// 5 waves of 2); larger grids keep 4 waves.  The first kNtThreads threads stage
+// the operands.
 template <int RB, bool SYM>
 struct NtTiles {
   static constexpr int T = SYM ? RB * (RB + 1) / 2 : RB * RB;
   static constexpr int waves() {
     int best = 4;
+    if (T > 16) return best;
     for (int w = 5; w <= 8; ++w)
       if ((T + w - 1) / w < (T + best - 1) / best) best = w;
     return best;
