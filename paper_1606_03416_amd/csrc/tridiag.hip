@@ -40,7 +40,7 @@ namespace {
 
 constexpr int kTB = 64;    // tile edge of the symmetric product
 constexpr int kNB = 64;    // panel width (reflectors per rank-2k update)
-constexpr int kTdThreads = 512;
+constexpr int kTdThreads = 256;
 
 struct TdArgs {
   double* A;
@@ -79,21 +79,58 @@ __device__ __forceinline__ double reflector(double sigma2, double alpha, double*
   return (b - alpha) / b;
 }
 
-constexpr int kSyOct = kTdThreads / 64;   // waves per tile (row/column octants)
-constexpr int kSyPer = kTB / kSyOct;       // tile entries per thread per column sweep
+constexpr int kSyWaves = kTdThreads / 64;   // waves per tile
+constexpr int kSyCols = kTB / kSyWaves;     // tile columns per wave (16)
 
-__device__ __forceinline__ double oct_sum(const double (*red)[kTB], int x) {
+__device__ __forceinline__ double wave_part_sum(const double (*red)[kTB], int x) {
   double s = 0.0;
 #pragma unroll
-  for (int q = 0; q < kSyOct; ++q) s += red[q][x];
+  for (int q = 0; q < kSyWaves; ++q) s += red[q][x];
   return s;
 }
 
+// Sums of 16 values per lane over the 64 lanes of a wave, all at once: each
+// exchange step halves the values a lane holds, then two butterfly steps
+// finish.  Lane l ends with the total of value l >> 2 (lanes l, l^1, l^2, l^3
+// hold the same total).
+__device__ __forceinline__ double wave_sum16(const double (&p)[16], int lane) {
+  double q8[8], q4[4], q2[2];
+  bool hi = (lane & 32) != 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double send = hi ? p[k] : p[k + 8];
+    q8[k] = (hi ? p[k + 8] : p[k]) + __shfl_xor(send, 32, 64);
+  }
+  hi = (lane & 16) != 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double send = hi ? q8[k] : q8[k + 4];
+    q4[k] = (hi ? q8[k + 4] : q8[k]) + __shfl_xor(send, 16, 64);
+  }
+  hi = (lane & 8) != 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double send = hi ? q4[k] : q4[k + 2];
+    q2[k] = (hi ? q4[k + 2] : q4[k]) + __shfl_xor(send, 8, 64);
+  }
+  hi = (lane & 4) != 0;
+  double q1 = (hi ? q2[1] : q2[0]) + __shfl_xor(hi ? q2[0] : q2[1], 4, 64);
+  q1 += __shfl_xor(q1, 2, 64);
+  q1 += __shfl_xor(q1, 1, 64);
+  return q1;
+}
+
+// One work-group per 64 x 64 tile (I, J), I >= J, of the trailing lower
+// triangle; wave q holds columns 16q .. 16q+15 of the tile in registers, lane
+// = row.  Off the diagonal the tile gives the row sums A_IJ v_J (combined over
+// the waves in LDS) and the column sums A_IJ^T v_I (one multi-value wave
+// reduction); a diagonal tile splits into its lower part with the diagonal
+// (row sums) and its strictly lower part (column sums).
 __global__ __launch_bounds__(kTdThreads) void td_symv_kernel(TdArgs a, int i, int j) {
-  __shared__ double sA[kTB][kTB + 1];   // [column][row]
   __shared__ double vI[kTB], vJ[kTB];
-  __shared__ double red[kSyOct][kTB];
-  __shared__ double red2[kSyOct][kTB];
+  __shared__ double red[kSyWaves][kTB];
+  __shared__ double red2[kSyWaves][kTB];
+  __shared__ double cs[kTB];
   const int t = threadIdx.x, r = t & 63, q = t >> 6;
   const int T0 = (i + 1) / kTB;
   const int64_t tile = blockIdx.x;
@@ -104,19 +141,16 @@ __global__ __launch_bounds__(kTdThreads) void td_symv_kernel(TdArgs a, int i, in
   const int I = T0 + Ir, J = T0 + Jr;
   const int r0 = I * kTB, c0 = J * kTB;
   const bool diag = (I == J);
+  const int gr = r0 + r;
 
   // every global load is issued before the first use: the tile, the raw
-  // column entries behind v_I and v_J, the norm partials, and (diagonal tiles)
-  // the panel rows of this block
-  double ld[kSyPer];
-  {
-    const int gr = r0 + r;
+  // column entries behind v_I and v_J, the norm partials
+  double ld[kSyCols];
 #pragma unroll
-    for (int k = 0; k < kSyPer; ++k) {
-      const int gc = c0 + q + kSyOct * k;
-      const bool ok = gr < a.n && gc < a.n && gr > i && gc > i && (!diag || gr >= gc);
-      ld[k] = ok ? a.A[gr + static_cast<int64_t>(gc) * a.lda] : 0.0;
-    }
+  for (int k = 0; k < kSyCols; ++k) {
+    const int gc = c0 + q * kSyCols + k;
+    const bool ok = gr < a.n && gc < a.n && gr > i && gc > i && (!diag || gr >= gc);
+    ld[k] = ok ? a.A[gr + static_cast<int64_t>(gc) * a.lda] : 0.0;
   }
   const int gv = (t < 64) ? r0 + t : c0 + t - 64;
   const double xraw = (t < 128 && gv >= i + 2 && gv < a.n) ? a.A[gv + static_cast<int64_t>(i) * a.lda] : 0.0;
@@ -124,15 +158,6 @@ __global__ __launch_bounds__(kTdThreads) void td_symv_kernel(TdArgs a, int i, in
   const int nb0 = (i + 2 < a.n) ? (i + 2) / kTB : a.nT;   // row blocks holding x(2:)
   const double s0 = (nb0 + r < a.nT) ? a.nrm[nb0 + r] : 0.0;
   const double s1 = (nb0 + r + 64 < a.nT) ? a.nrm[nb0 + r + 64] : 0.0;
-  double pv[kSyPer], pw[kSyPer];
-  const bool panel = diag && j > 0 && r < j;
-#pragma unroll
-  for (int k = 0; k < kSyPer; ++k) {
-    const int g = r0 + q * kSyPer + k;
-    const bool ok = panel && g > i && g < a.n;
-    pv[k] = ok ? a.Vp[static_cast<int64_t>(g) * kNB + r] : 0.0;
-    pw[k] = ok ? a.Wp[static_cast<int64_t>(g) * kNB + r] : 0.0;
-  }
 
   double s = s0 + s1;
   for (int b = nb0 + r + 128; b < a.nT; b += 64) s += a.nrm[b];
@@ -147,61 +172,62 @@ __global__ __launch_bounds__(kTdThreads) void td_symv_kernel(TdArgs a, int i, in
     if (t < 64) vI[t] = v;
     else vJ[t - 64] = v;
   }
-#pragma unroll
-  for (int k = 0; k < kSyPer; ++k) sA[q + kSyOct * k][r] = ld[k];
   __syncthreads();
 
-  // row sums: (A_IJ v_J)(r), octant q of the columns
-  double acc = 0.0;
+  const double vr = vI[r];
+  double acc = 0.0, p[kSyCols];
 #pragma unroll
-  for (int k = 0; k < kSyPer; ++k) {
-    const int c = q * kSyPer + k;
-    const double m = (!diag || r >= c) ? sA[c][r] : sA[r][c];
-    acc += m * vJ[c];
+  for (int k = 0; k < kSyCols; ++k) {
+    const int c = q * kSyCols + k;
+    acc += ld[k] * vJ[c];
+    p[k] = (!diag || r > c) ? ld[k] * vr : 0.0;
   }
   red[q][r] = acc;
-  if (!diag) {
-    // column sums: (A_IJ^T v_I)(c = r), octant q of the rows
-    double acc2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < kSyPer; ++k) {
-      const int rr = q * kSyPer + k;
-      acc2 += sA[r][rr] * vI[rr];
-    }
-    red2[q][r] = acc2;
+  const double col = wave_sum16(p, r);
+  const int cl = q * kSyCols + (r >> 2);
+  if ((r & 3) == 0) {
+    if (diag) cs[cl] = col;
+    else a.P[(static_cast<int64_t>(J) * a.nT + I) * kTB + cl] = col;
   }
   __syncthreads();
   if (t < 64) {
-    const double y = oct_sum(red, t);
+    double y = wave_part_sum(red, t);
+    if (diag) y += cs[t];
     a.P[(static_cast<int64_t>(I) * a.nT + J) * kTB + t] = y;
     const double sy = wave_sum(y * vI[t]);
     if (t == 0) a.S[tile] = diag ? sy : 2.0 * sy;
-  } else if (!diag && t < 128) {
-    const int c = t - 64;
-    const double y = oct_sum(red2, c);
-    a.P[(static_cast<int64_t>(J) * a.nT + I) * kTB + c] = y;
   }
   if (!diag) return;
 
   // diagonal tile: this row block's v into the panel, and its parts of
   // V^T v and W^T v over the panel's earlier columns (thread: column r,
-  // octant q of the rows)
-  const int gr = r0 + r;
+  // rows 16q .. 16q+15)
   if (q == 0 && gr < a.n) a.Vp[static_cast<int64_t>(gr) * kNB + j] = vI[r];
   if (j == 0) return;
+  // loaded only here (diagonal tiles), so that the tile's registers are free
   double sv = 0.0, sw = 0.0;
+  if (r < j) {
+    double pv[kSyCols], pw[kSyCols];
 #pragma unroll
-  for (int k = 0; k < kSyPer; ++k) {
-    sv += pv[k] * vI[q * kSyPer + k];
-    sw += pw[k] * vI[q * kSyPer + k];
+    for (int k = 0; k < kSyCols; ++k) {
+      const int g = r0 + q * kSyCols + k;
+      const bool ok = g > i && g < a.n;
+      pv[k] = ok ? a.Vp[static_cast<int64_t>(g) * kNB + r] : 0.0;
+      pw[k] = ok ? a.Wp[static_cast<int64_t>(g) * kNB + r] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kSyCols; ++k) {
+      sv += pv[k] * vI[q * kSyCols + k];
+      sw += pw[k] * vI[q * kSyCols + k];
+    }
   }
   __syncthreads();
   red[q][r] = sv;
   red2[q][r] = sw;
   __syncthreads();
   if (t < 64 && t < j) {
-    a.VV[static_cast<int64_t>(I) * kNB + t] = oct_sum(red, t);
-    a.WV[static_cast<int64_t>(I) * kNB + t] = oct_sum(red2, t);
+    a.VV[static_cast<int64_t>(I) * kNB + t] = wave_part_sum(red, t);
+    a.WV[static_cast<int64_t>(I) * kNB + t] = wave_part_sum(red2, t);
   }
 }
 
