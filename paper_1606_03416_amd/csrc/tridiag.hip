@@ -251,6 +251,13 @@ constexpr int kUpOct = 8;                      // threads per row (octants of th
 constexpr int kUpThreads = 64 * kUpOct + 64;   // + one wave for row i+1
 constexpr int kUpChunk = 8;                    // row blocks per octant per load batch
 
+// One work-group per 64-row block of column i's trailing rows.  Waves 0-7 own
+// the block's rows (lane = row, wave = octant of every sum); wave 8 repeats the
+// arithmetic of row i+1, whose w every work-group needs for the next column.
+// Phases: (1) all loads; (2) a = W^T v, b = V^T v and v^T A v from their
+// partials; (3) w for the block's rows, the reflector stored in LAPACK form;
+// (4) unless column i is the last of its panel, the next column corrected by
+// the panel and its squared-norm partial for the next reflector.
 __global__ __launch_bounds__(kUpThreads) void td_update_kernel(TdArgs a, int i, int j, int update_next,
                                                                int64_t ntiles) {
   __shared__ double sa[kNB], sb[kNB], W1[kNB + 1], V1[kNB + 1];
