@@ -163,9 +163,11 @@ int launch_copy_f64(const double* src, int64_t lds, double* dst, int64_t ldd, in
 // Dense FP64 kernels (dense.hip).
 // C(m x n) = alpha * A^T B + beta * C, A (k x m, lda), B (k x n, ldb), row-major.
 // upper_only: compute only tiles on/above the diagonal (symmetric results).
+// kmin: fewest reduction rows per split-K part (splits fill the chip when the
+// result has few tiles; the partial sums need d_split_ws).
 int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool upper_only,
-            double* d_split_ws, size_t split_ws_elems, hipStream_t st);
+            double* d_split_ws, size_t split_ws_elems, hipStream_t st, int64_t kmin = 1024);
 // C(m x n) = alpha * A B + beta * C, A (m x k, lda), B (k x n, ldb), row-major.
 // b_upper: B is upper triangular (its zero part is skipped).
 int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
@@ -174,7 +176,7 @@ int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
 // T = U^{-1} for an upper triangular n x n U (T upper triangular); W is
 // scratch of (n/2 + 64)^2 doubles.
 int upper_inverse(const double* U, int n, double* T, double* W, hipStream_t st);
-size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k);
+size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k, int64_t kmin = 1024);
 // mode 0: (A + A^T)/2; 1: upper -> lower; 2: lower -> upper.
 int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st);
 // d_scr: device scratch of at least min(n, 64)^2 doubles.
@@ -212,6 +214,13 @@ int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, in
 size_t tridiag_scratch_bytes(int n);
 int tridiag_lower(void* rocblas_h, double* A, int64_t lda, int n, double* D, double* E, double* tau,
                   void* scratch, hipStream_t st);
+// Back-transformation (backtr.hip): out = Q C for the reflectors of
+// tridiag_lower in A and tau; C (n x n column-major, leading dimension n, the
+// eigenvectors of T) is overwritten; out is column-major with leading
+// dimension ldo and may be A itself.
+size_t backtr_scratch_bytes(int n);
+int backtr_lower(const double* A, int64_t lda, int n, const double* tau, double* C, double* out, int64_t ldo,
+                 void* scratch, size_t scratch_bytes, hipStream_t st);
 
 // Lanczos (lanczos.hip)
 size_t lanczos_ws_bytes(const Plan& p, int k);

@@ -565,9 +565,9 @@ unsigned grid1(int64_t total) {
 // operand rows can be read as aligned 16-byte pairs
 bool vec_ok(const double* X, int64_t ld) { return (ld % 2) == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0; }
 
-int choose_splits(int64_t tiles, int64_t k) {
+int choose_splits(int64_t tiles, int64_t k, int64_t kmin) {
   int64_t s = ceil_div(2048, tiles > 0 ? tiles : 1);
-  const int64_t maxs = ceil_div(k, 1024);
+  const int64_t maxs = ceil_div(k, kmin);
   if (s > maxs) s = maxs;
   if (s > 64) s = 64;
   if (s < 1) s = 1;
@@ -576,20 +576,20 @@ int choose_splits(int64_t tiles, int64_t k) {
 
 }  // namespace
 
-size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k) {
+size_t gemm_tn_split_ws_elems(int64_t m, int64_t n, int64_t k, int64_t kmin) {
   // the upper-triangle-only launch has fewer tiles, hence the most splits
   const int64_t tm = ceil_div(m, GT);
   const int64_t tiles = (m == n) ? (tm * (tm + 1)) / 2 : tm * ceil_div(n, GT);
-  const int s = choose_splits(tiles, k);
+  const int s = choose_splits(tiles, k, kmin);
   return s > 1 ? static_cast<size_t>(s) * m * n : 0;
 }
 
 int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool upper_only,
-            double* d_split_ws, size_t split_ws_elems, hipStream_t st) {
+            double* d_split_ws, size_t split_ws_elems, hipStream_t st, int64_t kmin) {
   if (m <= 0 || n <= 0) return CHEFSI_OK;
   const int64_t tm = ceil_div(m, GT), tn = ceil_div(n, GT);
-  int splits = choose_splits(upper_only ? (tm * (tm + 1)) / 2 : tm * tn, k);
+  int splits = choose_splits(upper_only ? (tm * (tm + 1)) / 2 : tm * tn, k, kmin);
   if (splits > 1 && (d_split_ws == nullptr || split_ws_elems < static_cast<size_t>(splits) * m * n))
     splits = 1;
   GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, 0, nullptr, upper_only, false, 0, 0};

@@ -1,10 +1,10 @@
 // Dense symmetric eigensolve of the projected matrix Hhat (Algorithm 1 step 4)
 // on the GPU, in FP64: Householder reduction to tridiagonal form by the
-// library's own kernels (tridiag.hip), then rocSOLVER's tridiagonal
-// divide-and-conquer (dstedc, eigenvectors of T) and its back-transformation
-// by the reflectors (dormtr).  rocSOLVER's device scratch and the reduction's
-// scratch come from the caller's workspace (rocblas_set_workspace), so the
-// call allocates nothing itself.
+// library's own kernels (tridiag.hip), rocSOLVER's tridiagonal
+// divide-and-conquer (dstedc, eigenvectors of T), and the back-transformation
+// by the reflectors as block reflectors on the library's GEMMs (backtr.hip).
+// rocSOLVER's device scratch and the library's scratch come from the caller's
+// workspace (rocblas_set_workspace), so the call allocates nothing itself.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -35,8 +35,6 @@ int eig_workspace_bytes(Plan& p, int n, size_t* bytes) {
   if (rocblas_start_device_memory_size_query(h) != rocblas_status_success)
     return fail(CHEFSI_ERR_HIP, "rocblas size query start failed");
   rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, nullptr, nullptr, nullptr, n, nullptr);
-  rocsolver_dormtr(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n, n, nullptr, n,
-                   nullptr, nullptr, n);
   size_t sz = 0;
   if (rocblas_stop_device_memory_size_query(h, &sz) != rocblas_status_success)
     return fail(CHEFSI_ERR_HIP, "rocblas size query stop failed");
@@ -44,7 +42,8 @@ int eig_workspace_bytes(Plan& p, int n, size_t* bytes) {
   const size_t tau = static_cast<size_t>(round_up(static_cast<int64_t>(n) * 8, 256));
   p.eig_ws_cache_n = static_cast<size_t>(n);
   p.eig_ws_cache_roc = roc;
-  p.eig_ws_cache_bytes = roc + tau + tridiag_scratch_bytes(n);
+  const size_t td = tridiag_scratch_bytes(n), bt = backtr_scratch_bytes(n);
+  p.eig_ws_cache_bytes = roc + tau + (td > bt ? td : bt);
   *bytes = p.eig_ws_cache_bytes;
   return CHEFSI_OK;
 }
@@ -71,11 +70,8 @@ int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, in
   rocblas_status s = rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, d_w, d_E, Z, n, d_info);
   if (s != rocblas_status_success)
     return fail(CHEFSI_ERR_EIG, std::string("rocsolver_dstedc: ") + rocblas_status_to_string(s));
-  s = rocsolver_dormtr(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n, n, A,
-                       static_cast<rocblas_int>(lda), tau, Z, n);
-  if (s != rocblas_status_success)
-    return fail(CHEFSI_ERR_EIG, std::string("rocsolver_dormtr: ") + rocblas_status_to_string(s));
-  return launch_copy_f64(Z, n, A, lda, n, n, st);
+  const size_t scratch_bytes = need - roc - static_cast<size_t>(round_up(static_cast<int64_t>(n) * 8, 256));
+  return backtr_lower(A, lda, n, tau, Z, A, lda, scratch, scratch_bytes, st);
 }
 
 void destroy_eig_handle(Plan& p) {
