@@ -1,8 +1,8 @@
 """Build the gfx950 C-ABI library libchefsi.so in-tree with hipcc.
 
 Every HIP source under csrc/ is compiled for gfx950 only, then linked into
-paper_1606_03416_amd/libchefsi.so (rocSOLVER provides the tridiagonal eigensolver and
-the back-transformation of its eigenvectors; rocBLAS the rank-2k updates).
+paper_1606_03416_amd/libchefsi.so (rocSOLVER provides the tridiagonal divide-and-conquer
+eigensolver; rocBLAS the rank-2k updates of the tridiagonal reduction).
 """
 from __future__ import annotations
 
