@@ -1,7 +1,8 @@
 // Householder reduction of the projected matrix Hhat to symmetric tridiagonal
 // form (the first stage of the dense eigensolve of Algorithm 1 step 4), FP64,
-// in LAPACK's lower-triangle format so that rocSOLVER's tridiagonal
-// divide-and-conquer and back-transformation take the result unchanged:
+// in LAPACK's lower-triangle format (rocSOLVER's tridiagonal
+// divide-and-conquer takes D and E unchanged; backtr.hip applies the
+// reflectors as stored here):
 //   Q = H(0) H(1) ... H(n-2),  H(i) = I - tau_i v_i v_i^T,
 //   v_i = 0 above row i+1, v_i(i+1) = 1, v_i(i+2:n) stored in A(i+2:n, i),
 //   D(i) = T(i, i), E(i) = T(i+1, i).
@@ -283,6 +284,15 @@ __global__ __launch_bounds__(kUpThreads) void td_update_kernel(TdArgs a, int i, 
   const int Ig = g / kTB, rg = g - Ig * kTB;
   double pa[kUpChunk], pb[kUpChunk], pp[kUpChunk], ps[8], vr[8], wr[8];
 #pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int c = o * 8 + k;
+    const bool ok = live && c < j;
+    vr[k] = ok ? a.Vp[static_cast<int64_t>(g) * kNB + c] : 0.0;
+    wr[k] = ok ? a.Wp[static_cast<int64_t>(g) * kNB + c] : 0.0;
+  }
+  const double vg = live ? a.Vp[static_cast<int64_t>(g) * kNB + j] : 0.0;
+  const double anext = (live && update_next && !extra) ? a.A[g + static_cast<int64_t>(i + 1) * a.lda] : 0.0;
+#pragma unroll
   for (int m = 0; m < kUpChunk; ++m) {
     const int b = T0 + o + kUpOct * m;
     const bool ok = pan && b < a.nT;
@@ -295,15 +305,6 @@ __global__ __launch_bounds__(kUpThreads) void td_update_kernel(TdArgs a, int i, 
     const int64_t k = t + static_cast<int64_t>(kUpThreads) * u;
     ps[u] = k < ntiles ? a.S[k] : 0.0;
   }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int c = o * 8 + k;
-    const bool ok = live && c < j;
-    vr[k] = ok ? a.Vp[static_cast<int64_t>(g) * kNB + c] : 0.0;
-    wr[k] = ok ? a.Wp[static_cast<int64_t>(g) * kNB + c] : 0.0;
-  }
-  const double vg = live ? a.Vp[static_cast<int64_t>(g) * kNB + j] : 0.0;
-  const double anext = (live && update_next && !extra) ? a.A[g + static_cast<int64_t>(i + 1) * a.lda] : 0.0;
   double xa = 0.0, xb = 0.0, y = 0.0, xs = 0.0;
 #pragma unroll
   for (int m = 0; m < kUpChunk; ++m) {
@@ -339,7 +340,8 @@ __global__ __launch_bounds__(kUpThreads) void td_update_kernel(TdArgs a, int i, 
     for (int u = 0; u < 8; ++u) xs += ps[u];
   }
 
-  // ---- a = W^T v, b = V^T v, v^T A v: fixed-order reductions
+  // ---- a = W^T v, b = V^T v, v^T A v: fixed-order reductions, finished by
+  // wave 0 (which also forms a^T b) so that one barrier publishes them
   if (!extra) {
     red[wv][lane] = xa;
     redB[wv][lane] = xb;
@@ -347,24 +349,24 @@ __global__ __launch_bounds__(kUpThreads) void td_update_kernel(TdArgs a, int i, 
   xs = wave_sum(xs);
   if (lane == 0) shs[wv] = xs;
   __syncthreads();
-  if (t < j) {
-    double u = 0.0, v = 0.0;
-#pragma unroll
-    for (int q = 0; q < kUpOct; ++q) {
-      u += red[q][t];
-      v += redB[q][t];
-    }
-    sa[t] = u;
-    sb[t] = v;
-  }
-  __syncthreads();
   if (t < 64) {
-    const double ab = wave_sum(t < j ? sa[t] * sb[t] : 0.0);
+    double u = 0.0, v = 0.0;
+    if (t < j) {
+#pragma unroll
+      for (int q = 0; q < kUpOct; ++q) {
+        u += red[q][t];
+        v += redB[q][t];
+      }
+      sa[t] = u;
+      sb[t] = v;
+    }
+    const double ab = wave_sum(u * v);
     double vav = 0.0;
 #pragma unroll
     for (int q = 0; q < kUpThreads / 64; ++q) vav += shs[q];
     if (t == 0) sc[0] = -0.5 * tau * tau * (vav - 2.0 * ab);
   }
+  __syncthreads();   // sa, sb, alpha2 ready; red/redB read
   // ---- w = tau (A v - V a - W b) + alpha2 v
   double z = y;
 #pragma unroll
@@ -372,7 +374,6 @@ __global__ __launch_bounds__(kUpThreads) void td_update_kernel(TdArgs a, int i, 
     const int c = o * 8 + k;
     if (c < j) z -= vr[k] * sa[c] + wr[k] * sb[c];
   }
-  __syncthreads();   // sc ready; red/redB free again
   const double alpha2 = sc[0];
   if (!extra) red[wv][lane] = live ? z : 0.0;
   else if (lane < kUpOct) redx[lane] = z;
@@ -425,15 +426,14 @@ __global__ __launch_bounds__(kUpThreads) void td_update_kernel(TdArgs a, int i, 
     }
     if (o == kUpOct - 1) u += vg * W1[j] + sw[lane] * V1[j];
   }
-  __syncthreads();   // every read of red is done
-  if (!extra) red[wv][lane] = u;
+  if (!extra) redB[wv][lane] = u;   // redB was last read before the previous barrier
   __syncthreads();
   if (t < 64) {
     double x2 = 0.0;
     if (live) {
       double upd = 0.0;
 #pragma unroll
-      for (int q = 0; q < kUpOct; ++q) upd += red[q][t];
+      for (int q = 0; q < kUpOct; ++q) upd += redB[q][t];
       const double x = anext - upd;
       a.A[g + static_cast<int64_t>(i + 1) * a.lda] = x;
       if (g == i + 1) a.D[i + 1] = x;
