@@ -33,7 +33,9 @@
  *   - `ws` is caller-provided device workspace of at least the size returned by
  *     chefsi_workspace_bytes() for the same operation and sizes (256-byte
  *     aligned).  The library allocates device memory only in
- *     chefsi_plan_create (index tables, rocSOLVER handle).
+ *     chefsi_plan_create (index tables) and, once per plan, when the first
+ *     workspace query or call that needs the dense eigensolver creates the
+ *     plan's rocBLAS handle.
  *   - Every entry point returns a chefsi_status; argument checks happen on the
  *     host before any HIP call.  chefsi_last_error() gives a message for the
  *     calling thread's most recent failure.  No C++ exception crosses the ABI.
