@@ -723,12 +723,36 @@ __global__ void convert_kernel(const TS* src, int64_t lds, TD* dst, int64_t ldd,
   }
 }
 
-__global__ void colsum_sqrt_kernel(const double* part, int rows, int ns, double* out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ns) return;
+// out[j] = sqrt(sum_r part[r][j]): 64 columns per work-group, 16 row groups
+// per column (rows g, g+16, ...; four independent loads in flight), the group
+// sums combined in a fixed order.
+__global__ __launch_bounds__(1024) void colsum_sqrt_kernel(const double* part, int rows, int ns, double* out) {
+  __shared__ double red[16][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
   double s = 0.0;
-  for (int r = 0; r < rows; ++r) s += part[static_cast<int64_t>(r) * ns + j];
-  out[j] = sqrt(s);
+  if (j < ns) {
+    int r = g;
+    for (; r + 48 < rows; r += 64) {
+      const double a0 = part[static_cast<int64_t>(r) * ns + j];
+      const double a1 = part[static_cast<int64_t>(r + 16) * ns + j];
+      const double a2 = part[static_cast<int64_t>(r + 32) * ns + j];
+      const double a3 = part[static_cast<int64_t>(r + 48) * ns + j];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; r < rows; r += 16) s += part[static_cast<int64_t>(r) * ns + j];
+  }
+  red[g][c] = s;
+  __syncthreads();
+  if (g == 0 && j < ns) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[q][c];
+    out[j] = sqrt(t);
+  }
 }
 
 unsigned grid_for(int64_t total, int threads = 256) {
@@ -887,7 +911,7 @@ int launch_resid_partial(const Plan& p, const void* d_panel, const double* d_X, 
 
 int launch_colsum_sqrt(const double* d_part, int rows, int ns, double* d_out, hipStream_t st) {
   if (ns <= 0) return CHEFSI_OK;
-  colsum_sqrt_kernel<<<static_cast<unsigned>(ceil_div(ns, 256)), 256, 0, st>>>(d_part, rows, ns, d_out);
+  colsum_sqrt_kernel<<<static_cast<unsigned>(ceil_div(ns, 64)), 1024, 0, st>>>(d_part, rows, ns, d_out);
   CHEFSI_LAUNCHED("colsum_sqrt");
   return CHEFSI_OK;
 }
