@@ -50,27 +50,44 @@ __global__ __launch_bounds__(LT) void lanczos_init_kernel(const double* v0, int6
   }
 }
 
-// y = H x for one vector, straight from the FP64 panel: one work-group per
-// element, thread i accumulates row i over the concatenated neighbour rows
-// (HBM-bound; the panel is read once).
-__global__ __launch_bounds__(128) void spmv_kernel(const double* panel, const int64_t* poff,
-                                                   const int32_t* kpad, const int64_t* koff,
-                                                   const int32_t* kmap, const int32_t* J, const int32_t* rb,
-                                                   const int64_t* rowoff, const double* x, double* y) {
+// y = H x for one vector, straight from the FP64 panel: one work-group of
+// kSpmvThreads per element.  Rows of up to 64 ALBs take 4 waves and rows of up
+// to 128 take 2 (lane group = row), each wave a quarter or a half of the
+// concatenated neighbour rows (pairs k, k+1 interleaved), and the parts are
+// added in a fixed order (HBM-bound; the panel is read once).
+constexpr int kSpmvThreads = 256;
+
+__global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(const double* panel, const int64_t* poff,
+                                                            const int32_t* kpad, const int64_t* koff,
+                                                            const int32_t* kmap, const int32_t* J,
+                                                            const int32_t* rb, const int64_t* rowoff,
+                                                            const double* x, double* y) {
+  __shared__ double red[kSpmvThreads];
   const int K = blockIdx.x;
-  const int i = threadIdx.x;
-  if (i >= J[K]) return;
-  const int JP = rb[K] * 16;
-  const double* pk = panel + poff[K] + i;
-  const int32_t* km = kmap + koff[K];
-  const int kp = kpad[K];
+  const int JK = J[K];
+  const int splits = (JK <= 64) ? 4 : 2;
+  const int rows = kSpmvThreads / splits;
+  const int i = threadIdx.x % rows, sp = threadIdx.x / rows;
   double a0 = 0.0, a1 = 0.0;
-  for (int k = 0; k < kp; k += 2) {
-    const int g0 = km[k], g1 = km[k + 1];
-    a0 += pk[static_cast<int64_t>(k) * JP] * (g0 >= 0 ? x[g0] : 0.0);
-    a1 += pk[static_cast<int64_t>(k + 1) * JP] * (g1 >= 0 ? x[g1] : 0.0);
+  if (i < JK) {
+    const int JP = rb[K] * 16;
+    const double* pk = panel + poff[K] + i;
+    const int32_t* km = kmap + koff[K];
+    const int kp = kpad[K];
+#pragma unroll 4
+    for (int k = 2 * sp; k < kp; k += 2 * splits) {
+      const int g0 = km[k], g1 = km[k + 1];
+      a0 += pk[static_cast<int64_t>(k) * JP] * (g0 >= 0 ? x[g0] : 0.0);
+      a1 += pk[static_cast<int64_t>(k + 1) * JP] * (g1 >= 0 ? x[g1] : 0.0);
+    }
   }
-  y[rowoff[K] + i] = a0 + a1;
+  red[threadIdx.x] = a0 + a1;
+  __syncthreads();
+  if (sp == 0 && i < JK) {
+    double s = 0.0;
+    for (int q = 0; q < splits; ++q) s += red[q * rows + i];
+    y[rowoff[K] + i] = s;
+  }
 }
 
 constexpr int RG = 256;   // work-groups of the reduction kernels
@@ -369,7 +386,7 @@ int lanczos_bounds(const Plan& p, const void* d_panel64, const double* d_v0, int
   CHEFSI_LAUNCHED("lanczos_init");
   const double* panel = static_cast<const double*>(d_panel64);
   for (int j = 0; j < k; ++j) {
-    spmv_kernel<<<p.M, 128, 0, st>>>(panel, p.d_poff, p.d_kpad, p.d_koff, p.d_kmap, p.d_J, p.d_rb, p.d_rowoff,
+    spmv_kernel<<<p.M, kSpmvThreads, 0, st>>>(panel, p.d_poff, p.d_kpad, p.d_koff, p.d_kmap, p.d_J, p.d_rb, p.d_rowoff,
                                      V + static_cast<int64_t>(j) * p.N, w);
     lz_alpha_partial<<<RG, RT, 0, st>>>(V, w, p.N, j, partA, stt);
     lz_three_term<<<RG, RT, 0, st>>>(V, w, p.N, j, partA, partB, stt);
