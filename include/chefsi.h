@@ -134,7 +134,10 @@ int chefsi_workspace_bytes(chefsi_plan plan, int op, int ns, int dtype, int pass
  *   eigenvectors) reaches ns/N.
  * If a0 >= a - 1e-12|b| then a0 = a - 1e-3 (b - a).
  * Writes (a, b, a0) to d_bounds (device, 3 doubles, may be NULL) and to
- * h_bounds (host, 3 doubles, may be NULL).  Synchronises the stream. */
+ * h_bounds (host, 3 doubles, may be NULL).  Synchronises the stream.
+ * Returns CHEFSI_ERR_NONFINITE if a bound is not finite and CHEFSI_ERR_ARG if
+ * a0 < a < b fails (previous Ritz values at or above the Lanczos bound: they
+ * belong to another H); the bounds are written in either case. */
 int chefsi_bounds(chefsi_plan plan, const double* d_H, const double* d_v0, int lanczos_steps,
                   const double* d_ritz_prev, int ns, double* d_bounds, double* h_bounds,
                   void* ws, size_t ws_bytes, void* stream);
@@ -204,7 +207,13 @@ int chefsi_rayleigh_ritz(chefsi_plan plan, const double* d_H, const double* d_Yh
  * per-stage event times, passes taken, condition bound).  Synchronises the
  * stream once at the end to read status words, and with passes = 0 also once
  * after the first factor to read its condition bound (a failed first factor
- * then returns CHEFSI_ERR_NOT_PD at once, with d_X unchanged). */
+ * then returns at once).
+ * Errors found on the device: CHEFSI_ERR_NONFINITE (bounds not finite),
+ * CHEFSI_ERR_ARG (bounds with a0 < a < b violated, e.g. warm Ritz values at or
+ * above a reused upper bound), CHEFSI_ERR_NOT_PD, CHEFSI_ERR_EIG, reported in
+ * that order of precedence.  On every error return d_X is unchanged (the final
+ * rotation checks the status words on the device before writing); d_ritz,
+ * d_resid and d_bounds_out are then undefined. */
 int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, int passes,
                  int lanczos_steps, const double* d_v0, const double* d_bounds_in, int warm,
                  double* d_X, int64_t ldx, int ns, double* d_ritz, double* d_resid,

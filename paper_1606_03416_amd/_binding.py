@@ -95,15 +95,36 @@ def _stream():
     return _vp(torch.cuda.current_stream().cuda_stream)
 
 
-def _mv(t: torch.Tensor, name: str, dtype=torch.float64) -> int:
-    if not t.is_cuda or t.dtype != dtype or t.dim() != 2 or t.stride(1) != 1:
-        raise ValueError(f"{name} must be a 2-D {dtype} CUDA tensor with contiguous rows")
-    return t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+def _on(t: torch.Tensor, device) -> bool:
+    return device is None or t.device == device
 
 
-def _vec(t: torch.Tensor, name: str, n: int):
-    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
-        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of >= {n} elements")
+def _mv(t, name: str, rows: Optional[int] = None, device=None, dtype=torch.float64) -> int:
+    """Checks a multivector (rows x ns, contiguous rows) and returns its row
+    stride; every check runs before any library call."""
+    if (not torch.is_tensor(t) or not t.is_cuda or t.dtype != dtype or t.dim() != 2 or t.stride(1) != 1
+            or not _on(t, device)):
+        raise ValueError(f"{name} must be a 2-D {dtype} CUDA tensor with contiguous rows"
+                         + ("" if device is None else f" on {device}"))
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{name} must have {rows} rows, got {t.shape[0]}")
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+    if ld < t.shape[1]:
+        raise ValueError(f"{name}: rows overlap (row stride {ld} < {t.shape[1]} columns)")
+    return ld
+
+
+def _vec(t, name: str, n: int, device=None):
+    if (not torch.is_tensor(t) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()
+            or t.numel() < n or not _on(t, device)):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of >= {n} elements"
+                         + ("" if device is None else f" on {device}"))
+
+
+def _user_ws(ws, device) -> None:
+    if (not torch.is_tensor(ws) or not ws.is_cuda or ws.dtype != torch.uint8 or not ws.is_contiguous()
+            or not _on(ws, device)):
+        raise ValueError("ws must be a contiguous uint8 CUDA tensor" + ("" if device is None else f" on {device}"))
 
 
 def _workspace(nbytes: int, device) -> torch.Tensor:
@@ -150,19 +171,22 @@ class Plan:
         return int(out.value)
 
     def _check_H(self, H: torch.Tensor):
-        if not H.is_cuda or H.dtype != torch.float64 or not H.is_contiguous() or H.numel() != self.h_elems:
-            raise ValueError(f"H must be a contiguous float64 CUDA tensor of {self.h_elems} elements")
+        if (not torch.is_tensor(H) or not H.is_cuda or H.dtype != torch.float64 or not H.is_contiguous()
+                or H.numel() != self.h_elems or H.device != self.device):
+            raise ValueError(f"H must be a contiguous float64 CUDA tensor of {self.h_elems} elements on {self.device}")
 
     # -- Algorithm 1 step 1
     def bounds(self, H, v0, lanczos_steps: int = 20, ritz_prev=None, ns: Optional[int] = None,
                out: Optional[torch.Tensor] = None) -> Tuple[float, float, float]:
         self._check_H(H)
-        _vec(v0, "v0", self.N)
+        _vec(v0, "v0", self.N, self.device)
         if ritz_prev is not None:
             ns = ritz_prev.numel()
-            _vec(ritz_prev, "ritz_prev", ns)
+            _vec(ritz_prev, "ritz_prev", ns, self.device)
         if ns is None:
             raise ValueError("ns is required for first-cycle bounds")
+        if out is not None:
+            _vec(out, "out", 3, self.device)
         ws = _workspace(self.workspace_bytes(OP_BOUNDS, ns, lanczos_steps=lanczos_steps), H.device)
         hb = (ctypes.c_double * 3)()
         _check(lib.chefsi_bounds(self._h, _p(H), _p(v0), lanczos_steps, _p(ritz_prev), ns, _p(out),
@@ -173,11 +197,11 @@ class Plan:
     def filter(self, H, X, m: int, a: float, b: float, a0: float, dtype: int = F64,
                out: Optional[torch.Tensor] = None) -> torch.Tensor:
         self._check_H(H)
-        ldx = _mv(X, "X")
+        ldx = _mv(X, "X", self.N, self.device)
         ns = X.shape[1]
         if out is None:
             out = torch.empty((self.N, ns), dtype=torch.float64, device=X.device)
-        ldy = _mv(out, "out")
+        ldy = _mv(out, "out", self.N, self.device)
         ws = _workspace(self.workspace_bytes(OP_FILTER, ns, dtype), X.device)
         _check(lib.chefsi_filter(self._h, _p(H), m, a, b, a0, dtype, _p(X), ldx, _p(out), ldy, ns,
                                  _p(ws), ws.numel(), _stream()))
@@ -187,12 +211,12 @@ class Plan:
     def rayleigh_ritz(self, H, Yhat, out: Optional[torch.Tensor] = None, want_Q: bool = False,
                       want_resid: bool = True):
         self._check_H(H)
-        ldy = _mv(Yhat, "Yhat")
+        ldy = _mv(Yhat, "Yhat", self.N, self.device)
         ns = Yhat.shape[1]
         dev = Yhat.device
         if out is None:
             out = torch.empty((self.N, ns), dtype=torch.float64, device=dev)
-        ldx = _mv(out, "out")
+        ldx = _mv(out, "out", self.N, self.device)
         ritz = torch.empty(ns, dtype=torch.float64, device=dev)
         resid = torch.empty(ns, dtype=torch.float64, device=dev) if want_resid else None
         Q = torch.empty((ns, ns), dtype=torch.float64, device=dev) if want_Q else None
@@ -205,17 +229,33 @@ class Plan:
     def sweep(self, H, X, m: int, *, dtype: int = F64, passes: int = 2, lanczos_steps: int = 20,
               v0=None, bounds=None, ritz=None, warm: bool = False, want_resid: bool = True,
               stats: bool = False, ws: Optional[torch.Tensor] = None):
-        """X is updated in place; returns (ritz, resid, bounds_used, stats_dict|None)."""
+        """X is updated in place; returns (ritz, resid, bounds_used, stats_dict|None).
+
+        warm=True takes a and a0 from `ritz` (the previous cycle's Ritz values),
+        which must then be given.  Every argument is checked here before the
+        library is called."""
         self._check_H(H)
-        ldx = _mv(X, "X")
+        ldx = _mv(X, "X", self.N, self.device)
         ns = X.shape[1]
         dev = X.device
+        if v0 is not None:
+            _vec(v0, "v0", self.N, self.device)
+        elif bounds is None:
+            raise ValueError("v0 is required when no bounds are given")
         if ritz is None:
+            if warm:
+                raise ValueError("warm=True needs the previous Ritz values in `ritz`")
             ritz = torch.empty(ns, dtype=torch.float64, device=dev)
+        else:
+            _vec(ritz, "ritz", ns, self.device)
+        if bounds is not None:
+            if not torch.is_tensor(bounds):
+                bounds = torch.tensor([float(v) for v in bounds], dtype=torch.float64, device=dev)
+            _vec(bounds, "bounds", 3, self.device)
+        if ws is not None:
+            _user_ws(ws, self.device)
         resid = torch.empty(ns, dtype=torch.float64, device=dev) if want_resid else None
         bout = torch.empty(3, dtype=torch.float64, device=dev)
-        if bounds is not None and not torch.is_tensor(bounds):
-            bounds = torch.tensor(list(bounds), dtype=torch.float64, device=dev)
         need = self.workspace_bytes(OP_SWEEP, ns, dtype, passes, lanczos_steps)
         if ws is None or ws.numel() < need:
             ws = _workspace(need, dev)
@@ -229,7 +269,7 @@ class Plan:
     def loss_backward(self, H, X, m: int, a: float, b: float, a0: float, k: int, passes: int = 2,
                       ckpt_stride: int = 4):
         self._check_H(H)
-        ldx = _mv(X, "X")
+        ldx = _mv(X, "X", self.N, self.device)
         ns = X.shape[1]
         dev = X.device
         Hbar = torch.empty_like(H)
@@ -244,12 +284,16 @@ class Plan:
     def filter_backward(self, H, X, Ybar, m: int, a: float, b: float, a0: float, ckpt_stride: int = 4,
                         Hbar: Optional[torch.Tensor] = None):
         self._check_H(H)
-        ldx = _mv(X, "X")
-        ldyb = _mv(Ybar, "Ybar")
+        ldx = _mv(X, "X", self.N, self.device)
+        ldyb = _mv(Ybar, "Ybar", self.N, self.device)
         ns = X.shape[1]
+        if Ybar.shape[1] != ns:
+            raise ValueError("Ybar must have as many columns as X")
         dev = X.device
         if Hbar is None:
             Hbar = torch.zeros_like(H)
+        else:
+            self._check_H(Hbar)
         Xbar = torch.empty((self.N, ns), dtype=torch.float64, device=dev)
         ws = _workspace(self.backward_workspace_bytes(OP_FILTER_BACKWARD, m, ns, 2, ckpt_stride), dev)
         _check(lib.chefsi_filter_backward(self._h, _p(H), m, a, b, a0, ckpt_stride, _p(X), ldx, _p(Ybar),
@@ -260,12 +304,14 @@ class Plan:
     # -- after the cycle: diagonal density-matrix blocks (eq. densitymatrix)
     def density_blocks(self, X, f, out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
         """P_KK = X_K diag(f) X_K^T for every element, back to back (flat)."""
-        ldx = _mv(X, "X")
+        ldx = _mv(X, "X", self.N, self.device)
         ns = X.shape[1]
-        _vec(f, "f", ns)
+        _vec(f, "f", ns, self.device)
         if out is None:
             out = torch.empty(self.block_elems, dtype=torch.float64, device=X.device)
-        _vec(out, "out", self.block_elems)
+        _vec(out, "out", self.block_elems, self.device)
+        if ws is not None:
+            _user_ws(ws, self.device)
         need = self.workspace_bytes(OP_DENSITY, ns)
         if ws is None or ws.numel() < need:
             ws = _workspace(need, X.device)
@@ -289,10 +335,12 @@ class Plan:
     def realign(self, X, V_new, V_old, nr: int, ws: Optional[torch.Tensor] = None):
         """X_K <- V_new,K^T V_old,K X_K in place (V packed element-major as
         V_K^T, J_K rows of nr samples each)."""
-        ldx = _mv(X, "X")
+        ldx = _mv(X, "X", self.N, self.device)
         ns = X.shape[1]
-        _vec(V_new, "V_new", self.N * nr)
-        _vec(V_old, "V_old", self.N * nr)
+        _vec(V_new, "V_new", self.N * nr, self.device)
+        _vec(V_old, "V_old", self.N * nr, self.device)
+        if ws is not None:
+            _user_ws(ws, self.device)
         need = self.realign_workspace_bytes(nr)
         if ws is None or ws.numel() < need:
             ws = _workspace(need, X.device)

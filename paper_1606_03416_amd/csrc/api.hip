@@ -302,10 +302,10 @@ int run_orth_pass2(int64_t n, int ns, const double* Y, int64_t ldy, double* T, d
 // block itself after one pass, Yhat1 after two.  Then
 //   Hhat = T^T (B^T H B) T,   X = B (T Q),
 // which equals Rayleigh-Ritz on B T in exact arithmetic and never forms B T.
-// X must not alias B unless tmp (N x ns) is given: the rotation then goes to
-// tmp and is copied into X.
+// X must not alias B.  The rotation into X is skipped on the device when any of
+// status[0..2] is set, so that a failed cycle leaves X as it was.
 int run_rr_fold(Plan& p, const void* panel64, const double* B, int64_t ldb, int ns, const double* T, double* X,
-                int64_t ldx, double* tmp, double* ritz, double* resid, const RrWs& r, hipStream_t st) {
+                int64_t ldx, const int* status, double* ritz, double* resid, const RrWs& r, hipStream_t st) {
   CHEFSI_TRY(launch_const_coef(1.0, 0.0, r.coef, st));
   StepIO io{B, ldb, true, nullptr, 0, true, r.W, ns, true, true};   // W = H B (no c term)
   CHEFSI_TRY(launch_step(p, panel64, CHEFSI_F64, r.coef, io, ns, st));
@@ -316,16 +316,11 @@ int run_rr_fold(Plan& p, const void* panel64, const double* B, int64_t ldb, int 
   CHEFSI_TRY(gemm_tn(ns, ns, ns, 1.0, T, ns, r.Q, ns, 0.0, r.Hh, ns, true, r.split, r.split_elems, st));
   CHEFSI_TRY(launch_symmetrize(r.Hh, ns, ns, 1, st));
   CHEFSI_TRY(launch_fill_int(r.info, 1, 0, st));
-  CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.Q, r.eig, r.eig_bytes, st));
+  CHEFSI_TRY(eig_sym(p, r.Hh, ns, ns, ritz, r.E, r.info, r.Q, r.eig, r.eig_bytes, st, status));
   CHEFSI_TRY(launch_eigvec_fix(r.Hh, ns, ns, r.Q, ns, st));
   // X = B (T Q)
   CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, T, ns, r.Q, ns, 0.0, r.Hh, ns, st));
-  if (tmp != nullptr) {
-    CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, B, ldb, r.Hh, ns, 0.0, tmp, ns, st));
-    CHEFSI_TRY(launch_copy_f64(tmp, ns, X, ldx, p.N, ns, st));
-  } else {
-    CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, B, ldb, r.Hh, ns, 0.0, X, ldx, st));
-  }
+  CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, B, ldb, r.Hh, ns, 0.0, X, ldx, st, false, status));
   if (resid != nullptr) {
     CHEFSI_TRY(launch_resid_partial(p, panel64, X, ldx, ritz, ns, r.part, st));
     CHEFSI_TRY(launch_colsum_sqrt(r.part, p.M, ns, resid, st));
@@ -357,6 +352,7 @@ int read_status(const int* d_status, int code_if_set, const char* what, hipStrea
   int h = 0;
   CHEFSI_HIP(hipMemcpyAsync(&h, d_status, sizeof(int), hipMemcpyDeviceToHost, st));
   CHEFSI_HIP(hipStreamSynchronize(st));
+  if (h < 0) return fail(CHEFSI_ERR_NONFINITE, "the projected matrix is not finite");
   if (h != 0) return fail(code_if_set, std::string(what) + " (device status " + std::to_string(h) + ")");
   return CHEFSI_OK;
 }
@@ -385,7 +381,12 @@ int guarded(F&& f) {
   }
 }
 
-size_t sweep_bytes(Plan& p, int ns, int dtype, int k) {
+// Workspace of a sweep: a common part, then the filter, Cholesky-QR and
+// Rayleigh-Ritz carvings one after the other in the same region, except that
+// with a second pass (passes != 1) the Rayleigh-Ritz carving follows the
+// Cholesky-QR one, whose block B then holds Yhat1 = Y U1^{-1} (so d_X is
+// written only by the final rotation).
+size_t sweep_bytes(Plan& p, int ns, int dtype, int k, int passes) {
   Carver c(nullptr, 0);
   c.take<double>(p.panel_elems);                        // FP64 panel
   c.take<double>(p.N * static_cast<int64_t>(ns));       // filtered block
@@ -405,7 +406,8 @@ size_t sweep_bytes(Plan& p, int ns, int dtype, int k) {
   RrWs r;
   carve_rr(cr, p, ns, false, r);
   size_t lz = lanczos_ws_bytes(p, k);
-  return base + std::max(std::max(cf.used, co.used), std::max(cr.used, lz));
+  const size_t subspace = (passes == 1) ? std::max(co.used, cr.used) : co.used + cr.used;
+  return base + std::max(std::max(cf.used, subspace), lz);
 }
 
 
@@ -831,7 +833,7 @@ int chefsi_workspace_bytes(chefsi_plan plan, int op, int ns, int dtype, int pass
         if (lanczos_steps < 1 || lanczos_steps > kMaxLanczos)
           return fail(CHEFSI_ERR_ARG, "lanczos_steps must be in [1, 64]");
         if (passes < 0 || passes > 2) return fail(CHEFSI_ERR_ARG, "passes must be 0 (auto), 1 or 2");
-        *bytes = sweep_bytes(p, ns, dtype, lanczos_steps);
+        *bytes = sweep_bytes(p, ns, dtype, lanczos_steps, passes);
         return CHEFSI_OK;
       }
       default:
@@ -868,6 +870,8 @@ int chefsi_bounds(chefsi_plan plan, const double* d_H, const double* d_v0, int l
     if (h_bounds) std::memcpy(h_bounds, hb, sizeof(hb));
     if (!std::isfinite(hb[0]) || !std::isfinite(hb[1]) || !std::isfinite(hb[2]))
       return fail(CHEFSI_ERR_NONFINITE, "bounds are not finite");
+    if (!(hb[2] < hb[0] && hb[0] < hb[1]))
+      return fail(CHEFSI_ERR_ARG, "bounds violate a0 < a < b (previous Ritz values above the upper bound?)");
     return CHEFSI_OK;
   });
 }
@@ -982,7 +986,7 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
     }
     CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
     const int lk = (lanczos_steps >= 1 && lanczos_steps <= kMaxLanczos) ? lanczos_steps : 1;
-    const size_t need = sweep_bytes(p, ns, filter_dtype, lk);
+    const size_t need = sweep_bytes(p, ns, filter_dtype, lk, passes);
     CHEFSI_TRY(check_ws(ws, ws_bytes, need));
     CHEFSI_TRY(check_device(p));
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1007,6 +1011,8 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
       char* rest = static_cast<char*>(ws) + c.used;
       const size_t rest_bytes = ws_bytes - c.used;
       CHEFSI_TRY(mark(0));
+      // status words: [0] Cholesky pivot, [1] eigensolver, [2] bounds
+      CHEFSI_TRY(launch_fill_int(status, 3, 0, st));
       CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, panel64, st));
       // step 1: bounds
       if (d_bounds_in && warm) {
@@ -1019,6 +1025,7 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         CHEFSI_TRY(lanczos_bounds(p, panel64, d_v0, lanczos_steps, warm ? d_ritz : nullptr, ns, bnd, rest,
                                   rest_bytes, st));
       }
+      CHEFSI_TRY(launch_check_bounds(bnd, status + 2, st));
       CHEFSI_TRY(mark(1));
       // step 2: filter
       {
@@ -1038,41 +1045,55 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
       // is folded into Rayleigh-Ritz.
       int used = passes;
       double hcond = 0.0;
+      size_t orth_used = 0;
+      double* Y1 = nullptr;   // Yhat1 = Y U1^{-1} when a second pass runs
       {
         Carver co(rest, rest_bytes);
         OrthWs o;
         carve_orth(co, p.N, ns, o);
+        orth_used = co.used;
         o.status = status;
         CHEFSI_TRY(run_orth_factor1(p.N, ns, Y, ns, Tk, o, st));
         CHEFSI_TRY(cholqr_cond_bound(o.S, Tk, ns, cscr, cond, st));
         if (passes == 0) {
-          int hs0 = 0;
+          int hs0[3] = {0, 0, 0};
           CHEFSI_HIP(hipMemcpyAsync(&hcond, cond, sizeof(double), hipMemcpyDeviceToHost, st));
-          CHEFSI_HIP(hipMemcpyAsync(&hs0, status, sizeof(int), hipMemcpyDeviceToHost, st));
+          CHEFSI_HIP(hipMemcpyAsync(hs0, status, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
           CHEFSI_HIP(hipStreamSynchronize(st));
-          // the host has synchronised anyway: stop here if the factor failed
-          if (hs0 != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+          // the host has synchronised anyway: stop here if the bounds or the
+          // factor failed (d_X is untouched so far)
+          if (hs0[2] == 1) return fail(CHEFSI_ERR_NONFINITE, "filter bounds are not finite");
+          if (hs0[2] != 0)
+            return fail(CHEFSI_ERR_ARG, "filter bounds violate a0 < a < b (previous Ritz values above the upper bound?)");
+          if (hs0[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
           used = auto_passes_from_bound(hcond);
         }
-        if (used == 2) CHEFSI_TRY(run_orth_pass2(p.N, ns, Y, ns, Tk, d_X, ldx, o, st));   // Yhat1 -> X
+        if (used == 2) {
+          Y1 = o.B;
+          CHEFSI_TRY(run_orth_pass2(p.N, ns, Y, ns, Tk, Y1, ns, o, st));
+        }
       }
       CHEFSI_TRY(mark(4));
       // steps 4-5: Rayleigh-Ritz and rotation
       {
-        Carver cr(rest, rest_bytes);
+        // after a second pass the carving starts behind Cholesky-QR's, which
+        // holds Yhat1
+        const size_t off = (used == 2) ? orth_used : 0;
+        Carver cr(rest + off, rest_bytes - off);
         RrWs r;
         CHEFSI_TRY(carve_rr(cr, p, ns, false, r));
+        if (!cr.ok()) return fail(CHEFSI_ERR_WORKSPACE, "sweep: workspace too small for two passes");
         r.info = status + 1;
         if (used == 2)
-          CHEFSI_TRY(run_rr_fold(p, panel64, d_X, ldx, ns, Tk, d_X, ldx, Y, d_ritz, d_resid, r, st));
+          CHEFSI_TRY(run_rr_fold(p, panel64, Y1, ns, ns, Tk, d_X, ldx, status, d_ritz, d_resid, r, st));
         else
-          CHEFSI_TRY(run_rr_fold(p, panel64, Y, ns, ns, Tk, d_X, ldx, nullptr, d_ritz, d_resid, r, st));
+          CHEFSI_TRY(run_rr_fold(p, panel64, Y, ns, ns, Tk, d_X, ldx, status, d_ritz, d_resid, r, st));
       }
       CHEFSI_TRY(mark(5));
       if (d_bounds_out)
         CHEFSI_HIP(hipMemcpyAsync(d_bounds_out, bnd, 3 * sizeof(double), hipMemcpyDeviceToDevice, st));
-      int hs[2] = {0, 0};
-      CHEFSI_HIP(hipMemcpyAsync(hs, status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      int hs[3] = {0, 0, 0};
+      CHEFSI_HIP(hipMemcpyAsync(hs, status, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
       if (passes != 0) CHEFSI_HIP(hipMemcpyAsync(&hcond, cond, sizeof(double), hipMemcpyDeviceToHost, st));
       CHEFSI_HIP(hipStreamSynchronize(st));
       if (stats) {
@@ -1090,7 +1111,11 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
         stats->cholqr_passes = used;
         stats->cholqr_cond_bound = hcond;
       }
+      if (hs[2] == 1) return fail(CHEFSI_ERR_NONFINITE, "filter bounds are not finite");
+      if (hs[2] != 0)
+        return fail(CHEFSI_ERR_ARG, "filter bounds violate a0 < a < b (previous Ritz values above the upper bound?)");
       if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+      if (hs[1] < 0) return fail(CHEFSI_ERR_NONFINITE, "the projected matrix is not finite");
       if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");
       return CHEFSI_OK;
     };
@@ -1212,6 +1237,7 @@ int chefsi_loss_backward(chefsi_plan plan, const double* d_H, int m, double a, d
     CHEFSI_HIP(hipStreamSynchronize(st));
     if (h_loss) *h_loss = hl;
     if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+    if (hs[1] < 0) return fail(CHEFSI_ERR_NONFINITE, "the projected matrix is not finite");
     if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");
     return CHEFSI_OK;
   });

@@ -169,10 +169,12 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, bool upper_only,
             double* d_split_ws, size_t split_ws_elems, hipStream_t st, int64_t kmin = 1024);
 // C(m x n) = alpha * A B + beta * C, A (m x k, lda), B (k x n, ldb), row-major.
-// b_upper: B is upper triangular (its zero part is skipped).
+// b_upper: B is upper triangular (its zero part is skipped).  skip_if
+// (device, 3 ints, may be null): if any is nonzero when the kernel runs, C is
+// left untouched (status words of earlier steps of the same stream).
 int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st,
-            bool b_upper = false);
+            bool b_upper = false, const int* skip_if = nullptr);
 // T = U^{-1} for an upper triangular n x n U (T upper triangular); W is
 // scratch of (n/2 + 64)^2 doubles.
 int upper_inverse(const double* U, int n, double* T, double* W, hipStream_t st);
@@ -208,8 +210,11 @@ int launch_transpose(const double* A, int64_t lda, double* B, int64_t ldb, int r
 
 // Eigensolver (eig.hip)
 int eig_workspace_bytes(Plan& p, int n, size_t* bytes);
+// *d_info: 0 ok, > 0 the tridiagonal solver failed, -1 A was not finite.
+// skip (device, 3 ints, may be null): if any is set, the identity is solved
+// instead of A (a failed earlier step; the caller reports it).
 int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, int* d_info, double* Z,
-            void* d_ws, size_t ws_bytes, hipStream_t st);
+            void* d_ws, size_t ws_bytes, hipStream_t st, const int* skip = nullptr);
 // Householder tridiagonalisation (tridiag.hip), LAPACK lower format
 size_t tridiag_scratch_bytes(int n);
 int tridiag_lower(void* rocblas_h, double* A, int64_t lda, int n, double* D, double* E, double* tau,
@@ -231,6 +236,8 @@ int lanczos_bounds(const Plan& p, const void* d_panel64, const double* d_v0, int
 // Ritz values (largest, smallest; a0 separated from a as in chefsi_bounds).
 int launch_warm_bounds(const double* d_ritz, int ns, const double* d_bounds_src, double* d_bounds,
                        hipStream_t st);
+// *d_status = 1 if the bounds (a, b, a0) are not finite, 2 if a0 < a < b fails.
+int launch_check_bounds(const double* d_bounds, int* d_status, hipStream_t st);
 
 // Steps around the cycle (post.hip).
 // Fermi level mu (sum_i f_i = n_occ) by bisection and occupations f (device).

@@ -46,6 +46,7 @@ struct GemmArgs {
   bool b_upper;     // B is upper triangular: column tile tj needs k < (tj+1)*GT only
   int tri_tiles;    // upper_only: number of upper-triangle tiles (1-D grid)
   int tn_tiles;     // upper_only: tiles per row of the square tile grid
+  const int* skip;  // if set and any of skip[0..2] is nonzero, write nothing
 };
 
 // One GT x GK operand chunk, 16 bytes (two doubles) per thread per load, four
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
     split = blockIdx.z;
   }
   if (g.upper_only && ti > tj) return;
+  if (g.skip != nullptr && (g.skip[0] | g.skip[1] | g.skip[2]) != 0) return;
   __shared__ __attribute__((aligned(16))) double sA[2 * GBUF];
   __shared__ __attribute__((aligned(16))) double sB[2 * GBUF];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -592,7 +594,7 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   int splits = choose_splits(upper_only ? (tm * (tm + 1)) / 2 : tm * tn, k, kmin);
   if (splits > 1 && (d_split_ws == nullptr || split_ws_elems < static_cast<size_t>(splits) * m * n))
     splits = 1;
-  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, 0, nullptr, upper_only, false, 0, 0};
+  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, 0, nullptr, upper_only, false, 0, 0, nullptr};
   g.kper = round_up(ceil_div(k, splits), GK);
   if (k <= 0) g.kper = GK;
   if (splits > 1) g.part = d_split_ws;
@@ -617,12 +619,12 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
 
 int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st,
-            bool b_upper) {
+            bool b_upper, const int* skip_if) {
   if (m <= 0 || n <= 0) return CHEFSI_OK;
   const int64_t tm = ceil_div(m, GT), tn = ceil_div(n, GT);
   if (tm > 65535) return fail(CHEFSI_ERR_ARG, "gemm_nn: too many row tiles");
   GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, round_up(k > 0 ? k : 1, GK), nullptr, false, b_upper,
-             0, 0};
+             0, 0, skip_if};
   dim3 grid(static_cast<unsigned>(tn), static_cast<unsigned>(tm), 1);
   if (vec_ok(A, lda) && vec_ok(B, ldb))
     gemm_kernel<false, true><<<grid, GNT, 0, st>>>(g);

@@ -361,6 +361,19 @@ __global__ void warm_bounds_kernel(const double* ritz, int ns, const double* bsr
   bounds[2] = a0;
 }
 
+// The filter needs finite bounds with a0 < a < b: previous Ritz values above
+// a reused upper bound (H changed since) or a failed Lanczos run break that.
+// *status = 1 (bounds not finite) or 2 (not ordered); untouched otherwise.
+__global__ void check_bounds_kernel(const double* bounds, int* status) {
+  if (threadIdx.x != 0) return;
+  const double a = bounds[0], b = bounds[1], a0 = bounds[2];
+  if (!isfinite(a) || !isfinite(b) || !isfinite(a0)) {
+    *status = 1;
+  } else if (!(a0 < a && a < b)) {
+    *status = 2;
+  }
+}
+
 }  // namespace
 
 size_t lanczos_ws_bytes(const Plan& p, int k) {
@@ -406,6 +419,12 @@ int launch_warm_bounds(const double* d_ritz, int ns, const double* d_bounds_src,
                        hipStream_t st) {
   warm_bounds_kernel<<<1, 64, 0, st>>>(d_ritz, ns, d_bounds_src, d_bounds);
   CHEFSI_LAUNCHED("warm_bounds");
+  return CHEFSI_OK;
+}
+
+int launch_check_bounds(const double* d_bounds, int* d_status, hipStream_t st) {
+  check_bounds_kernel<<<1, 64, 0, st>>>(d_bounds, d_status);
+  CHEFSI_LAUNCHED("check_bounds");
   return CHEFSI_OK;
 }
 

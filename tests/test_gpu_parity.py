@@ -203,18 +203,69 @@ def test_orthonormalize_not_pd(lib, passes):
     assert e.value.code == lib.ERR_NOT_PD
 
 
-def test_sweep_not_pd_auto_leaves_x_unchanged(lib):
-    """A zero column makes the filtered block rank deficient: the automatic
-    pass count stops after the first factor with NOT_PD and X untouched."""
+@pytest.mark.parametrize("passes", [0, 1, 2])
+def test_sweep_not_pd_leaves_x_unchanged(lib, passes):
+    """A zero column makes the filtered block rank deficient: the sweep returns
+    NOT_PD and X is untouched (the automatic pass count stops after the first
+    factor; with 1 or 2 passes the final rotation sees the status word on the
+    device and writes nothing)."""
     P = synth.make_problem(synth.TINY)
     plan = mkplan(lib, P)
     X0 = synth.make_start_block(P.J, 48)
     X0[:, 5] = 0.0
     X = dev(X0)
     with pytest.raises(lib.ChefsiError) as e:
-        plan.sweep(dev(P.packed()), X, 10, bounds=(0.5, 6.0, -1.5), passes=0)
+        plan.sweep(dev(P.packed()), X, 10, bounds=(0.5, 6.0, -1.5), passes=passes)
     assert e.value.code == lib.ERR_NOT_PD
     assert np.array_equal(host(X), X0)
+
+
+@pytest.mark.parametrize("passes", [0, 1, 2])
+def test_sweep_rejects_warm_ritz_values_above_a_reused_bound(lib, passes):
+    """Warm bounds whose reused upper bound lies below the previous top Ritz
+    value (Ritz values of another H) would invert the filter; the sweep reports
+    ERR_ARG and leaves X unchanged.  chefsi_bounds does the same on the host."""
+    w = synth.TINY
+    P = synth.make_problem(w)
+    plan = mkplan(lib, P)
+    Hd = dev(P.packed())
+    X0 = synth.make_start_block(P.J, w.ns)
+    X = dev(X0)
+    ritz, _, bnd, _ = plan.sweep(Hd, X, w.m, v0=dev(synth.make_lanczos_start(P.N)), passes=2)
+    top = float(host(ritz)[-1])
+    Xs = host(X).copy()
+    stale = torch.tensor([0.0, top - 0.25, -1.0], dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.ChefsiError) as e:
+        plan.sweep(Hd, X, w.m, bounds=stale, ritz=ritz, warm=True, passes=passes)
+    assert e.value.code == lib.ERR_ARG
+    assert np.array_equal(host(X), Xs)
+    # explicit bounds that are not finite
+    with pytest.raises(lib.ChefsiError) as e:
+        plan.sweep(Hd, X, w.m, bounds=(0.5, float("inf"), -1.0), passes=passes)
+    assert e.value.code == lib.ERR_NONFINITE
+    assert np.array_equal(host(X), Xs)
+
+
+def test_binding_rejects_short_or_foreign_tensors_before_the_call(lib):
+    P = synth.make_problem(synth.TINY)
+    plan = mkplan(lib, P)
+    Hd = dev(P.packed())
+    X = dev(synth.make_start_block(P.J, 48))
+    v0 = dev(synth.make_lanczos_start(P.N))
+    bad = [
+        lambda: plan.sweep(Hd, X, 10, v0=v0[:-1].clone()),                       # short v0
+        lambda: plan.sweep(Hd, X, 10, v0=v0.cpu()),                               # host v0
+        lambda: plan.sweep(Hd, X, 10, v0=v0, ritz=torch.zeros(48, device="cuda")),   # float32 ritz
+        lambda: plan.sweep(Hd, X, 10, v0=v0, ritz=torch.zeros(47, dtype=torch.float64, device="cuda")),
+        lambda: plan.sweep(Hd, X, 10, bounds=torch.zeros(2, dtype=torch.float64, device="cuda")),
+        lambda: plan.sweep(Hd, X, 10, v0=v0, ws=torch.empty(1 << 20, dtype=torch.float64, device="cuda")),
+        lambda: plan.sweep(Hd, X, 10, v0=v0, warm=True),                          # warm without ritz
+        lambda: plan.sweep(Hd, X[:-8], 10, v0=v0),                                # too few rows
+        lambda: plan.filter(Hd, X[:, ::2], 4, 0.0, 1.0, -1.0),                    # strided columns
+    ]
+    for f in bad:
+        with pytest.raises(ValueError):
+            f()
 
 
 # ---------------------------------------------------------------- Rayleigh-Ritz
@@ -406,11 +457,22 @@ def test_sweep_auto_passes_match_oracle(lib, name, ns, m):
             Xo, th_o, _, _, _ = oracle.rayleigh_ritz(op, Yh)
             ritz, resid, _, st = plan.sweep(Hd, X, m, bounds=bounds, passes=passes, stats=True)
             B = oracle.cholqr_condition_bound(Us[0])
+            Bmax = B if i == 0 else max(Bmax, B)
             tol_orth = 1e-12 if len(Us) == 2 else max(1e-12, 50 * eps * B * B)
             s = max(abs(bounds[2]), abs(bounds[1]))
             assert ritz_rel(host(ritz), th_o, s) <= max(1e-10, 10 * tol_orth), (passes, i)
             Xh = host(X)
             assert np.linalg.norm(Xh.T @ Xh - np.eye(ns), 2) <= tol_orth, (passes, i, B)
+            if passes == 1:
+                # One pass loses orthogonality like eps B^2, but the span of
+                # its output is that of the filtered block to about eps B, and
+                # the filter of the next cycle depends only on that span: the
+                # Ritz values of span(X) (orthonormalised twice here) match the
+                # oracle's Ritz values of span(Y~) (two passes) to ~eps B.
+                th_span = oracle.rayleigh_ritz(op, oracle.cholesky_qr(Xh, 2)[0])[1]
+                th_ref = oracle.rayleigh_ritz(op, oracle.cholesky_qr(Yt, 2)[0])[1]
+                tol_span = max(1e-10, 100 * eps * Bmax)
+                assert ritz_rel(th_span, th_ref, s) <= tol_span, (i, B, ritz_rel(th_span, th_ref, s))
             assert st["cholqr_passes"] == len(Us), (passes, i)
             # the first factor of an ill-conditioned block is itself accurate
             # only to about eps B^2 in its small directions; after a lossy
