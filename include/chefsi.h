@@ -72,7 +72,9 @@ typedef enum {
   CHEFSI_OP_SWEEP = 4,
   CHEFSI_OP_FILTER_BACKWARD = 5,
   CHEFSI_OP_LOSS_BACKWARD = 6,
-  CHEFSI_OP_DENSITY = 7
+  CHEFSI_OP_DENSITY = 7,
+  CHEFSI_OP_LOSS = 8,
+  CHEFSI_OP_RAYLEIGH_RITZ_BACKWARD = 9
 } chefsi_op;
 
 typedef struct chefsi_plan_s* chefsi_plan;
@@ -236,11 +238,56 @@ int chefsi_loss_backward(chefsi_plan plan, const double* d_H, int m, double a, d
                          int64_t ldx, int ns, double* d_Hbar, double* d_Xbar, int64_t ldxb,
                          double* h_loss, void* ws, size_t ws_bytes, void* stream);
 
-/* Workspace bytes of chefsi_loss_backward (op = CHEFSI_OP_LOSS_BACKWARD) or
- * chefsi_filter_backward (op = CHEFSI_OP_FILTER_BACKWARD) for degree m, ns
- * columns, `passes` Cholesky-QR passes and checkpoint stride ckpt_stride. */
+/* The loss alone, L = sum_{i<k} theta_i of the same pass, with exactly the
+ * arithmetic of chefsi_loss_backward's forward part (so both report the same
+ * value) and no checkpoints, adjoint or rotation: what a forward evaluation
+ * without gradients costs.  *h_loss (host).  Synchronises the stream.
+ * Workspace: chefsi_backward_workspace_bytes(op = CHEFSI_OP_LOSS). */
+int chefsi_loss(chefsi_plan plan, const double* d_H, int m, double a, double b, double a0, int passes,
+                int k, const double* d_X, int64_t ldx, int ns, double* h_loss, void* ws,
+                size_t ws_bytes, void* stream);
+
+/* Workspace bytes of chefsi_loss_backward (op = CHEFSI_OP_LOSS_BACKWARD),
+ * chefsi_loss (op = CHEFSI_OP_LOSS) or chefsi_filter_backward
+ * (op = CHEFSI_OP_FILTER_BACKWARD) for degree m, ns columns, `passes`
+ * Cholesky-QR passes and checkpoint stride ckpt_stride. */
 int chefsi_backward_workspace_bytes(chefsi_plan plan, int op, int m, int ns, int passes,
                                     int ckpt_stride, size_t* bytes);
+
+/* Adjoint of chefsi_orthonormalize (Algorithm 1 step 3): Yhat = Y U^{-1} is
+ * the thin QR factorisation of Y (U upper triangular with positive diagonal,
+ * d_U as chefsi_orthonormalize returns it: U_2 U_1 after two passes, which is
+ * the same factorisation).  Given Yhat_bar = dL/dYhat and no dependence of L
+ * on U, writes dL/dY by the textbook QR backward rule
+ *   M = -Yhat_bar^T Yhat,  Y_bar = (Yhat_bar + Yhat copyltu(M)) U^{-T},
+ * copyltu(M) = tril(M) + tril(M, -1)^T (the last product by triangular
+ * substitution).  d_Yhat, d_Yhat_bar, d_Y_bar: n x ns float64 row-major
+ * (device); d_U: ns x ns row-major (device).  d_Y_bar may be d_Yhat_bar itself
+ * (in place, same leading dimension) but must not otherwise overlap an
+ * input.  Workspace: chefsi_orthonormalize_backward_workspace_bytes.
+ * Asynchronous. */
+int chefsi_orthonormalize_backward(int64_t n, int ns, const double* d_Yhat, int64_t ldy,
+                                   const double* d_U, const double* d_Yhat_bar, int64_t ldyb,
+                                   double* d_Y_bar, int64_t ldb, void* ws, size_t ws_bytes,
+                                   void* stream);
+int chefsi_orthonormalize_backward_workspace_bytes(int64_t n, int ns, size_t* bytes);
+
+/* Adjoint of chefsi_rayleigh_ritz's Ritz values (Algorithm 1 step 4): for
+ * Hhat = sym(Yhat^T H Yhat) = Q diag(theta) Q^T and a cotangent theta_bar of
+ * the Ritz values, Hhat_bar = Q diag(theta_bar) Q^T and
+ *   Yhat_bar = H Yhat Hhat_bar + H^T Yhat Hhat_bar   (d_Yhat_bar, written),
+ *   H_bar    = Yhat Hhat_bar Yhat^T on the stored blocks (d_Hbar, block-list
+ *              layout; overwritten, or added to when accumulate != 0).
+ * d_Q: the ns x ns eigenvector matrix chefsi_rayleigh_ritz returns (row-major,
+ * column j = eigenvector j); d_ritz_bar: ns float64 (device).  The gradient of
+ * the rotated vectors (X_new = Yhat Q) is not part of this rule.
+ * d_Yhat_bar and d_Hbar must not overlap any input.  Workspace:
+ * chefsi_workspace_bytes(op = CHEFSI_OP_RAYLEIGH_RITZ_BACKWARD, ns).
+ * Asynchronous. */
+int chefsi_rayleigh_ritz_backward(chefsi_plan plan, const double* d_H, const double* d_Yhat,
+                                  int64_t ldy, int ns, const double* d_Q, const double* d_ritz_bar,
+                                  double* d_Yhat_bar, int64_t ldyb, double* d_Hbar, int accumulate,
+                                  void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint of chefsi_filter alone (FP64): given Ybar = dL/dY for Y = p_m(H)X,
  * accumulates dL/dH onto d_Hbar (block-list layout, added to) and writes

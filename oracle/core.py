@@ -351,17 +351,30 @@ def symmetric_eig(A: np.ndarray):
     return np.linalg.eigh(A)
 
 
-def rayleigh_ritz(op, Yh: np.ndarray):
+def rayleigh_ritz(op, Yh: np.ndarray, col_chunk: int = 0):
     """Hhat = Yhat^T (H Yhat), Hhat Q = Q D, X_new = Yhat Q, residuals
-    r_i = ||H x_i - theta_i x_i||_2 (Algorithm 1 steps 4-5)."""
-    W = op.apply(Yh)
-    Hh = Yh.T @ W
+    r_i = ||H x_i - theta_i x_i||_2 (Algorithm 1 steps 4-5).
+
+    col_chunk > 0 forms the columns of H Yhat (and of Hhat) and the residual
+    columns that many at a time, to bound the memory of very tall blocks;
+    every column is the same product as without it."""
+    N, ns = Yh.shape
+    step = col_chunk if col_chunk > 0 else ns
+    Hh = np.empty((ns, ns))
+    for c0 in range(0, ns, step):
+        W = op.apply(Yh[:, c0:c0 + step])
+        Hh[:, c0:c0 + step] = Yh.T @ W
+        del W
     Hh = 0.5 * (Hh + Hh.T)
     theta, Q = symmetric_eig(Hh)
     Q = sign_normalize(Q)
     Xn = Yh @ Q
-    R = op.apply(Xn) - Xn * theta[None, :]
-    resid = np.sqrt(np.sum(R * R, axis=0))
+    resid = np.empty(ns)
+    for c0 in range(0, ns, step):
+        Xc = Xn[:, c0:c0 + step]
+        R = op.apply(Xc) - Xc * theta[None, c0:c0 + step]
+        resid[c0:c0 + step] = np.sqrt(np.sum(R * R, axis=0))
+        del R
     return Xn, theta, resid, Q, Hh
 
 

@@ -22,7 +22,7 @@ lib = ctypes.CDLL(library_path)
 
 F64, F32, BF16 = 0, 1, 2
 (OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP, OP_FILTER_BACKWARD, OP_LOSS_BACKWARD,
- OP_DENSITY) = range(8)
+ OP_DENSITY, OP_LOSS, OP_RAYLEIGH_RITZ_BACKWARD) = range(10)
 ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_NOT_PD, ERR_EIG, ERR_NONFINITE, ERR_UNSUPPORTED = range(1, 8)
 
 _vp = ctypes.c_void_p
@@ -68,6 +68,10 @@ _sig("chefsi_sweep", _i, _vp, _vp, _i, _i, _i, _i, _vp, _vp, _i, _vp, _i64, _i, 
 _sig("chefsi_loss_backward", _i, _vp, _vp, _i, _d, _d, _d, _i, _i, _i, _vp, _i64, _i, _vp, _vp, _i64,
      _dp, _vp, _sz, _vp)
 _sig("chefsi_backward_workspace_bytes", _i, _vp, _i, _i, _i, _i, _i, ctypes.POINTER(_sz))
+_sig("chefsi_loss", _i, _vp, _vp, _i, _d, _d, _d, _i, _i, _vp, _i64, _i, _dp, _vp, _sz, _vp)
+_sig("chefsi_orthonormalize_backward", _i, _i64, _i, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _vp)
+_sig("chefsi_orthonormalize_backward_workspace_bytes", _i, _i64, _i, ctypes.POINTER(_sz))
+_sig("chefsi_rayleigh_ritz_backward", _i, _vp, _vp, _vp, _i64, _i, _vp, _vp, _vp, _i64, _vp, _i, _vp, _sz, _vp)
 _sig("chefsi_filter_backward", _i, _vp, _vp, _i, _d, _d, _d, _i, _vp, _i64, _vp, _i64, _i, _vp, _vp,
      _i64, _vp, _sz, _vp)
 _sig("chefsi_occupations", _i, _i, _vp, _d, _d, _vp, _vp, _vp)
@@ -265,6 +269,45 @@ class Plan:
                                 ctypes.byref(st) if stats else None, _p(ws), ws.numel(), _stream()))
         return ritz, resid, bout, (st.as_dict() if stats else None)
 
+    # -- loss of one filter + Cholesky-QR + Rayleigh-Ritz pass (forward only)
+    def loss(self, H, X, m: int, a: float, b: float, a0: float, k: int, passes: int = 2) -> float:
+        self._check_H(H)
+        ldx = _mv(X, "X", self.N, self.device)
+        ns = X.shape[1]
+        ws = _workspace(self.backward_workspace_bytes(OP_LOSS, m, ns, passes, 1), X.device)
+        loss = ctypes.c_double(0.0)
+        _check(lib.chefsi_loss(self._h, _p(H), m, a, b, a0, passes, k, _p(X), ldx, ns, ctypes.byref(loss),
+                               _p(ws), ws.numel(), _stream()))
+        return float(loss.value)
+
+    # -- adjoint of the Ritz values of chefsi_rayleigh_ritz
+    def rayleigh_ritz_backward(self, H, Yhat, Q, ritz_bar, Hbar: Optional[torch.Tensor] = None,
+                               accumulate: bool = False, out: Optional[torch.Tensor] = None):
+        """(Yhat_bar, Hbar) for the cotangent ritz_bar of the Ritz values."""
+        self._check_H(H)
+        ldy = _mv(Yhat, "Yhat", self.N, self.device)
+        ns = Yhat.shape[1]
+        _mv(Q, "Q", ns, self.device)
+        if Q.shape[1] != ns or not Q.is_contiguous():
+            raise ValueError("Q must be a contiguous ns x ns tensor")
+        _vec(ritz_bar, "ritz_bar", ns, self.device)
+        if Hbar is None:
+            if accumulate:
+                raise ValueError("accumulate=True needs Hbar")
+            Hbar = torch.empty_like(H)
+        else:
+            self._check_H(Hbar)
+        if out is None:
+            out = torch.empty((self.N, ns), dtype=torch.float64, device=Yhat.device)
+        ldo = _mv(out, "out", self.N, self.device)
+        if out.shape[1] != ns:
+            raise ValueError("out must have ns columns")
+        ws = _workspace(self.workspace_bytes(OP_RAYLEIGH_RITZ_BACKWARD, ns), Yhat.device)
+        _check(lib.chefsi_rayleigh_ritz_backward(self._h, _p(H), _p(Yhat), ldy, ns, _p(Q), _p(ritz_bar), _p(out),
+                                                 ldo, _p(Hbar), 1 if accumulate else 0, _p(ws), ws.numel(),
+                                                 _stream()))
+        return out, Hbar
+
     # -- adjoint of one filter + Cholesky-QR + Rayleigh-Ritz pass
     def loss_backward(self, H, X, m: int, a: float, b: float, a0: float, k: int, passes: int = 2,
                       ckpt_stride: int = 4):
@@ -364,19 +407,23 @@ def occupations(ritz: torch.Tensor, n_occ: float, kT: float, out: Optional[torch
 
 class ChefsiLoss(torch.autograd.Function):
     """L = sum of the k lowest Ritz values after one filter + Cholesky-QR +
-    Rayleigh-Ritz pass, with the hand-written adjoint (chefsi_loss_backward)
-    as its backward.  Bounds are held constant."""
+    Rayleigh-Ritz pass (forward: chefsi_loss), with the hand-written adjoint
+    (chefsi_loss_backward, which recomputes the forward from checkpoints) as
+    its backward.  Bounds are held constant."""
 
     @staticmethod
     def forward(ctx, H, X, plan, m, bounds, k, passes=2, ckpt_stride=4):
         a, b, a0 = bounds
-        loss, Hbar, Xbar = plan.loss_backward(H, X, m, a, b, a0, k, passes, ckpt_stride)
-        ctx.save_for_backward(Hbar, Xbar)
+        ctx.plan, ctx.args = plan, (m, a, b, a0, k, passes, ckpt_stride)
+        ctx.save_for_backward(H, X)
+        loss = plan.loss(H, X, m, a, b, a0, k, passes)
         return torch.tensor(loss, dtype=torch.float64, device=H.device)
 
     @staticmethod
     def backward(ctx, g):
-        Hbar, Xbar = ctx.saved_tensors
+        H, X = ctx.saved_tensors
+        m, a, b, a0, k, passes, cs = ctx.args
+        _, Hbar, Xbar = ctx.plan.loss_backward(H, X, m, a, b, a0, k, passes, cs)
         return g * Hbar, g * Xbar, None, None, None, None, None, None
 
 
@@ -407,6 +454,32 @@ def orthonormalize(Y: torch.Tensor, passes: int = 2, want_U: bool = False):
     ws = _workspace(_orth_ws_bytes(n, ns, passes), dev)
     _check(lib.chefsi_orthonormalize(n, ns, _p(Y), ldy, passes, _p(U), _p(ws), ws.numel(), _stream()))
     return U
+
+
+def orthonormalize_backward(Yhat: torch.Tensor, U: torch.Tensor, Yhat_bar: torch.Tensor,
+                            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dL/dY for Yhat = Y U^{-1} (the factor chefsi_orthonormalize returns),
+    given dL/dYhat.  out may be Yhat_bar itself (in place)."""
+    ldy = _mv(Yhat, "Yhat")
+    n, ns = Yhat.shape
+    dev = Yhat.device
+    ldg = _mv(Yhat_bar, "Yhat_bar", n, dev)
+    _mv(U, "U", ns, dev)
+    if U.shape[1] != ns or not U.is_contiguous():
+        raise ValueError("U must be a contiguous ns x ns tensor")
+    if Yhat_bar.shape[1] != ns:
+        raise ValueError("Yhat_bar must have ns columns")
+    if out is None:
+        out = torch.empty((n, ns), dtype=torch.float64, device=dev)
+    ldo = _mv(out, "out", n, dev)
+    if out.shape[1] != ns:
+        raise ValueError("out must have ns columns")
+    nb = _sz(0)
+    _check(lib.chefsi_orthonormalize_backward_workspace_bytes(n, ns, ctypes.byref(nb)))
+    ws = _workspace(nb.value, dev)
+    _check(lib.chefsi_orthonormalize_backward(n, ns, _p(Yhat), ldy, _p(U), _p(Yhat_bar), ldg, _p(out), ldo,
+                                              _p(ws), ws.numel(), _stream()))
+    return out
 
 
 def _orth_ws_bytes(n: int, ns: int, passes: int = 2) -> int:

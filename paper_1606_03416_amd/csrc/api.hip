@@ -434,14 +434,17 @@ struct BwdWs {
   size_t eig_bytes = 0;
 };
 
-int carve_bwd(Carver& c, Plan& p, int m, int ns, int passes, int stride, bool loss_path, BwdWs& b) {
+// reverse = false: the forward of the loss only (no checkpoints, no H^T
+// panel, no reverse-sweep buffers).
+int carve_bwd(Carver& c, Plan& p, int m, int ns, int passes, int stride, bool loss_path, BwdWs& b,
+              bool reverse = true) {
   const int64_t mv = p.N * static_cast<int64_t>(ns);
   const int64_t nn = static_cast<int64_t>(ns) * ns;
-  const int nseg = m > 0 ? static_cast<int>(ceil_div(m, stride)) : 0;
+  const int nseg = (m > 0 && reverse) ? static_cast<int>(ceil_div(m, stride)) : 0;
   b.panel = c.take<double>(p.panel_elems);
-  b.panelT = c.take<double>(p.panel_elems);
+  b.panelT = reverse ? c.take<double>(p.panel_elems) : nullptr;
   b.coef = c.take<double>(3 * static_cast<int64_t>(std::max(m, 1)));
-  b.rcoef = c.take<double>(3 * static_cast<int64_t>(std::max(m, 1)));
+  b.rcoef = reverse ? c.take<double>(3 * static_cast<int64_t>(std::max(m, 1))) : nullptr;
   b.bounds = c.take<double>(4);
   b.cconst = c.take<double>(8);
   b.F[0] = c.take<double>(mv);
@@ -453,16 +456,17 @@ int carve_bwd(Carver& c, Plan& p, int m, int ns, int passes, int stride, bool lo
     b.ckP[i] = c.take<double>(mv);
   }
   b.seg.assign(std::max(stride, 1), nullptr);
-  for (int t = 1; t < stride && t < m; ++t) b.seg[t] = c.take<double>(mv);
-  b.LA = c.take<double>(mv);
-  b.LB = c.take<double>(mv);
+  if (reverse)
+    for (int t = 1; t < stride && t < m; ++t) b.seg[t] = c.take<double>(mv);
+  b.LA = reverse ? c.take<double>(mv) : nullptr;
+  b.LB = reverse ? c.take<double>(mv) : nullptr;
   b.status = c.take<int>(8);
   if (!loss_path) return CHEFSI_OK;
   b.P1 = c.take<double>(mv);
   b.P2 = passes == 2 ? c.take<double>(mv) : nullptr;
   b.W = c.take<double>(mv);
-  b.YH = c.take<double>(mv);
-  b.G = c.take<double>(mv);
+  b.YH = reverse ? c.take<double>(mv) : nullptr;
+  b.G = reverse ? c.take<double>(mv) : nullptr;
   b.S = c.take<double>(nn);
   b.U0 = c.take<double>(nn);
   b.U1 = c.take<double>(nn);
@@ -555,6 +559,133 @@ int validate_bwd_common(Plan& p, int m, double a, double bb, double a0, int ns, 
   if (ns < 1 || ns > p.N) return fail(CHEFSI_ERR_ARG, "ns must be in [1, N]");
   if (m > 0 && (ckpt_stride < 1 || ckpt_stride > m)) return fail(CHEFSI_ERR_ARG, "ckpt_stride must be in [1, m]");
   return validate_bounds(a, bb, a0);
+}
+
+// Adjoint of the thin QR Y = Yhat U (U upper with positive diagonal) with
+// R_bar = 0, in place on G (Yhat_bar on entry, Y_bar on exit):
+//   M = -G^T Yhat,  G <- (G + Yhat copyltu(M)) U^{-T},
+// copyltu(M) = tril(M) + tril(M, -1)^T.  M, Lt: ns x ns scratch.
+int run_qr_backward(int64_t n, int ns, const double* Yh, int64_t ldy, const double* U, double* G, int64_t ldg,
+                    double* M, double* Lt, double* split, size_t split_elems, hipStream_t st) {
+  CHEFSI_TRY(gemm_tn(ns, ns, n, -1.0, G, ldg, Yh, ldy, 0.0, M, ns, false, split, split_elems, st));
+  CHEFSI_TRY(launch_symmetrize(M, ns, ns, 2, st));
+  CHEFSI_TRY(gemm_nn(n, ns, ns, 1.0, Yh, ldy, M, ns, 1.0, G, ldg, st));
+  CHEFSI_TRY(launch_transpose(U, ns, Lt, ns, ns, ns, st));
+  return trsm_right_lower(G, ldg, n, Lt, ns, ns, st);
+}
+
+// Adjoint of Hhat = sym(Yhat^T H Yhat) and Hhat Q = Q diag(theta) for the
+// Ritz-value cotangent theta_bar: Hhat_bar = Q diag(theta_bar) Q^T,
+// YH = Yhat Hhat_bar, G = H YH + H^T YH (into G, ld ldg) and
+// Hbar += YH Yhat^T on the stored blocks.  Q: ns x ns row-major (column j =
+// eigenvector j); QT, QD, Hhb: ns x ns scratch; YH: N x ns scratch;
+// cconst: the constant coefficients (1, 0, 0) and, 4 doubles on, (1, -1, 0).
+int run_rr_backward(const Plan& p, const double* panel, const double* panelT, const double* cconst,
+                    const double* Yh, int64_t ldy, int ns, const double* Q, const double* theta_bar,
+                    double* QT, double* QD, double* Hhb, double* YH, double* G, int64_t ldg, double* Hbar,
+                    hipStream_t st) {
+  CHEFSI_TRY(launch_transpose(Q, ns, QT, ns, ns, ns, st));
+  CHEFSI_TRY(launch_transpose(QT, ns, QD, ns, ns, ns, st, theta_bar));   // Q diag(theta_bar)
+  CHEFSI_TRY(gemm_nn(ns, ns, ns, 1.0, QD, ns, QT, ns, 0.0, Hhb, ns, st));
+  CHEFSI_TRY(gemm_nn(p.N, ns, ns, 1.0, Yh, ldy, Hhb, ns, 0.0, YH, ns, st));
+  StepIO io{YH, ns, true, nullptr, 0, true, G, ldg, true};
+  CHEFSI_TRY(launch_step(p, panel, CHEFSI_F64, cconst, io, ns, st));
+  StepIO io2{YH, ns, true, G, ldg, true, G, ldg, true};
+  CHEFSI_TRY(launch_step(p, panelT, CHEFSI_F64, cconst + 4, io2, ns, st));
+  return sddmm_accumulate(p, YH, ns, Yh, ldy, ns, 1.0, nullptr, Hbar, st);
+}
+
+// Forward of the differentiated pass, as the adjoint sees it: the filter with
+// checkpoints every `stride` steps (none when b.ckY is empty), `passes`
+// Cholesky-QR passes with their factors kept (Qp[pass] = output of the pass,
+// Up[pass] = its factor), Hhat = sym(Yhat^T H Yhat), its eigenpairs
+// (b.theta, b.Q) and the loss sum_{i<k} theta_i (b.loss).  Status words:
+// b.status[0] Cholesky, b.status[1] eigensolver.
+int loss_forward_dev(Plan& p, const double* d_H, int m, double a, double bb, double a0, int passes, int k,
+                     int stride, const double* d_X, int64_t ldx, int ns, BwdWs& w, hipStream_t st) {
+  const int64_t N = p.N;
+  CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, w.panel, st));
+  if (w.panelT) CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, true, w.panelT, st));
+  CHEFSI_TRY(launch_set_bounds(a, bb, a0, w.bounds, st));
+  CHEFSI_TRY(launch_cheb_coef(w.bounds, m, w.coef, st));
+  if (m > 0 && w.rcoef) CHEFSI_TRY(launch_rev_coef(w.coef, m, w.rcoef, st));
+  CHEFSI_TRY(launch_fill_int(w.status, 2, 0, st));
+  const double* Ym = nullptr;
+  int64_t ldm = 0;
+  CHEFSI_TRY(forward_checkpointed(p, w.panel, w.coef, m, stride, d_X, ldx, ns, w, &Ym, &ldm, st));
+  double* Qp[2] = {w.P1, w.P2};
+  double* Up[2] = {w.U0, w.U1};
+  CHEFSI_TRY(launch_copy_f64(Ym, ldm, w.P1, ns, N, ns, st));
+  for (int pass = 0; pass < passes; ++pass) {
+    if (pass == 1) CHEFSI_TRY(launch_copy_f64(w.P1, ns, w.P2, ns, N, ns, st));
+    double* Y = Qp[pass];
+    CHEFSI_TRY(gemm_tn(ns, ns, N, 1.0, Y, ns, Y, ns, 0.0, w.S, ns, true, w.split, w.split_elems, st));
+    CHEFSI_TRY(launch_symmetrize(w.S, ns, ns, 1, st));
+    CHEFSI_TRY(cholesky_upper(w.S, ns, ns, w.status, w.Mb, st));
+    CHEFSI_TRY(trsm_right_upper(Y, ns, N, w.S, ns, ns, st));
+    CHEFSI_TRY(launch_copy_f64(w.S, ns, Up[pass], ns, ns, ns, st));
+  }
+  double* Yh = Qp[passes - 1];
+  CHEFSI_TRY(launch_const_coef3(1.0, 0.0, 0.0, w.cconst, st));        // plain H x
+  CHEFSI_TRY(launch_const_coef3(1.0, -1.0, 0.0, w.cconst + 4, st));   // H x + prev
+  {
+    StepIO io{Yh, ns, true, nullptr, 0, true, w.W, ns, true};
+    CHEFSI_TRY(launch_step(p, w.panel, CHEFSI_F64, w.cconst, io, ns, st));
+  }
+  CHEFSI_TRY(gemm_tn(ns, ns, N, 1.0, Yh, ns, w.W, ns, 0.0, w.Hh, ns, false, w.split, w.split_elems, st));
+  CHEFSI_TRY(launch_symmetrize(w.Hh, ns, ns, 0, st));
+  CHEFSI_TRY(eig_sym(p, w.Hh, ns, ns, w.theta, w.E, w.status + 1, w.Q, w.eig, w.eig_bytes, st));
+  CHEFSI_TRY(launch_eigvec_fix(w.Hh, ns, ns, w.Q, ns, st));
+  return launch_sum_first(w.theta, k, w.loss, st);
+}
+
+int read_loss_status(const BwdWs& w, double* h_loss, hipStream_t st) {
+  double hl = 0.0;
+  int hs[2] = {0, 0};
+  CHEFSI_HIP(hipMemcpyAsync(&hl, w.loss, sizeof(double), hipMemcpyDeviceToHost, st));
+  CHEFSI_HIP(hipMemcpyAsync(hs, w.status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  CHEFSI_HIP(hipStreamSynchronize(st));
+  if (h_loss) *h_loss = hl;
+  if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+  if (hs[1] < 0) return fail(CHEFSI_ERR_NONFINITE, "the projected matrix is not finite");
+  if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");
+  return CHEFSI_OK;
+}
+
+struct QrBwdWs {
+  double* M;
+  double* Lt;
+  double* split;
+  size_t split_elems;
+};
+
+void carve_qr_bwd(Carver& c, int64_t n, int ns, QrBwdWs& q) {
+  const int64_t nn = static_cast<int64_t>(ns) * ns;
+  q.M = c.take<double>(nn);
+  q.Lt = c.take<double>(nn);
+  q.split_elems = gemm_tn_split_ws_elems(ns, ns, n);
+  q.split = q.split_elems ? c.take<double>(static_cast<int64_t>(q.split_elems)) : nullptr;
+}
+
+struct RrBwdWs {
+  double* panel;
+  double* panelT;
+  double* cconst;
+  double* QT;
+  double* QD;
+  double* Hhb;
+  double* YH;
+};
+
+void carve_rr_bwd(Carver& c, const Plan& p, int ns, RrBwdWs& r) {
+  const int64_t nn = static_cast<int64_t>(ns) * ns;
+  r.panel = c.take<double>(p.panel_elems);
+  r.panelT = c.take<double>(p.panel_elems);
+  r.cconst = c.take<double>(8);
+  r.QT = c.take<double>(nn);
+  r.QD = c.take<double>(nn);
+  r.Hhb = c.take<double>(nn);
+  r.YH = c.take<double>(p.N * static_cast<int64_t>(ns));
 }
 
 }  // namespace
@@ -825,6 +956,13 @@ int chefsi_workspace_bytes(chefsi_plan plan, int op, int ns, int dtype, int pass
       case CHEFSI_OP_DENSITY: {
         Carver c(nullptr, 0);
         c.take<double>(static_cast<int64_t>(elem_nt_slices(p, ns)) * p.sqtot);
+        *bytes = c.used;
+        return CHEFSI_OK;
+      }
+      case CHEFSI_OP_RAYLEIGH_RITZ_BACKWARD: {
+        Carver c(nullptr, 0);
+        RrBwdWs r;
+        carve_rr_bwd(c, p, ns, r);
         *bytes = c.used;
         return CHEFSI_OK;
       }
@@ -1131,14 +1269,16 @@ int chefsi_backward_workspace_bytes(chefsi_plan plan, int op, int m, int ns, int
                                     size_t* bytes) {
   return guarded([&]() -> int {
     if (plan == nullptr || bytes == nullptr) return fail(CHEFSI_ERR_ARG, "plan/bytes is NULL");
-    if (op != CHEFSI_OP_LOSS_BACKWARD && op != CHEFSI_OP_FILTER_BACKWARD) return fail(CHEFSI_ERR_ARG, "bad op");
+    if (op != CHEFSI_OP_LOSS_BACKWARD && op != CHEFSI_OP_FILTER_BACKWARD && op != CHEFSI_OP_LOSS)
+      return fail(CHEFSI_ERR_ARG, "bad op");
     if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
     Plan& p = *P(plan);
     if (m < 0 || ns < 1) return fail(CHEFSI_ERR_ARG, "need m >= 0 and ns >= 1");
-    const int stride = m > 0 ? std::max(1, std::min(ckpt_stride, m)) : 1;
+    const bool loss_only = (op == CHEFSI_OP_LOSS);
+    const int stride = loss_only ? std::max(m, 1) : (m > 0 ? std::max(1, std::min(ckpt_stride, m)) : 1);
     Carver c(nullptr, 0);
     BwdWs b;
-    CHEFSI_TRY(carve_bwd(c, p, m, ns, passes, stride, op == CHEFSI_OP_LOSS_BACKWARD, b));
+    CHEFSI_TRY(carve_bwd(c, p, m, ns, passes, stride, op != CHEFSI_OP_FILTER_BACKWARD, b, !loss_only));
     *bytes = c.used;
     return CHEFSI_OK;
   });
@@ -1169,60 +1309,19 @@ int chefsi_loss_backward(chefsi_plan plan, const double* d_H, int m, double a, d
     CHEFSI_TRY(carve_bwd(c, p, m, ns, passes, stride, true, w));
     const int64_t N = p.N;
     // ---- forward: filter (checkpointed), Cholesky-QR (per-pass factors kept), Rayleigh-Ritz
-    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, w.panel, st));
-    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, true, w.panelT, st));
-    CHEFSI_TRY(launch_set_bounds(a, b, a0, w.bounds, st));
-    CHEFSI_TRY(launch_cheb_coef(w.bounds, m, w.coef, st));
-    if (m > 0) CHEFSI_TRY(launch_rev_coef(w.coef, m, w.rcoef, st));
-    CHEFSI_TRY(launch_fill_int(w.status, 2, 0, st));
-    const double* Ym = nullptr;
-    int64_t ldm = 0;
-    CHEFSI_TRY(forward_checkpointed(p, w.panel, w.coef, m, stride, d_X, ldx, ns, w, &Ym, &ldm, st));
+    CHEFSI_TRY(loss_forward_dev(p, d_H, m, a, b, a0, passes, k, stride, d_X, ldx, ns, w, st));
     double* Qp[2] = {w.P1, w.P2};
     double* Up[2] = {w.U0, w.U1};
-    CHEFSI_TRY(launch_copy_f64(Ym, ldm, w.P1, ns, N, ns, st));
-    for (int pass = 0; pass < passes; ++pass) {
-      if (pass == 1) CHEFSI_TRY(launch_copy_f64(w.P1, ns, w.P2, ns, N, ns, st));
-      double* Y = Qp[pass];
-      CHEFSI_TRY(gemm_tn(ns, ns, N, 1.0, Y, ns, Y, ns, 0.0, w.S, ns, true, w.split, w.split_elems, st));
-      CHEFSI_TRY(launch_symmetrize(w.S, ns, ns, 1, st));
-      CHEFSI_TRY(cholesky_upper(w.S, ns, ns, w.status, w.Mb, st));
-      CHEFSI_TRY(trsm_right_upper(Y, ns, N, w.S, ns, ns, st));
-      CHEFSI_TRY(launch_copy_f64(w.S, ns, Up[pass], ns, ns, ns, st));
-    }
     double* Yh = Qp[passes - 1];
-    CHEFSI_TRY(launch_const_coef3(1.0, 0.0, 0.0, w.cconst, st));        // plain H x
-    CHEFSI_TRY(launch_const_coef3(1.0, -1.0, 0.0, w.cconst + 4, st));   // H x + prev
-    {
-      StepIO io{Yh, ns, true, nullptr, 0, true, w.W, ns, true};
-      CHEFSI_TRY(launch_step(p, w.panel, CHEFSI_F64, w.cconst, io, ns, st));
-    }
-    CHEFSI_TRY(gemm_tn(ns, ns, N, 1.0, Yh, ns, w.W, ns, 0.0, w.Hh, ns, false, w.split, w.split_elems, st));
-    CHEFSI_TRY(launch_symmetrize(w.Hh, ns, ns, 0, st));
-    CHEFSI_TRY(eig_sym(p, w.Hh, ns, ns, w.theta, w.E, w.status + 1, w.Q, w.eig, w.eig_bytes, st));
-    CHEFSI_TRY(launch_eigvec_fix(w.Hh, ns, ns, w.Q, ns, st));
-    CHEFSI_TRY(launch_sum_first(w.theta, k, w.loss, st));
-    // ---- backward: Rayleigh-Ritz
-    CHEFSI_TRY(launch_transpose(w.Q, ns, w.QT, ns, ns, ns, st));
-    CHEFSI_TRY(gemm_tn(ns, ns, k, 1.0, w.QT, ns, w.QT, ns, 0.0, w.Hhb, ns, false, nullptr, 0, st));
-    CHEFSI_TRY(gemm_nn(N, ns, ns, 1.0, Yh, ns, w.Hhb, ns, 0.0, w.YH, ns, st));
-    {
-      StepIO io{w.YH, ns, true, nullptr, 0, true, w.G, ns, true};
-      CHEFSI_TRY(launch_step(p, w.panel, CHEFSI_F64, w.cconst, io, ns, st));
-      StepIO io2{w.YH, ns, true, w.G, ns, true, w.G, ns, true};
-      CHEFSI_TRY(launch_step(p, w.panelT, CHEFSI_F64, w.cconst + 4, io2, ns, st));
-    }
+    // ---- backward: Rayleigh-Ritz (theta_bar = 1 on the k lowest, 0 above)
+    CHEFSI_TRY(launch_fill(w.E, ns, 0.0, st));
+    CHEFSI_TRY(launch_fill(w.E, k, 1.0, st));
     CHEFSI_TRY(launch_fill(d_Hbar, p.h_elems, 0.0, st));
-    CHEFSI_TRY(sddmm_accumulate(p, w.YH, ns, Yh, ns, ns, 1.0, nullptr, d_Hbar, st));
+    CHEFSI_TRY(run_rr_backward(p, w.panel, w.panelT, w.cconst, Yh, ns, ns, w.Q, w.E, w.QT, w.Lt, w.Hhb, w.YH, w.G,
+                               ns, d_Hbar, st));
     // ---- backward: Cholesky-QR passes in reverse
-    for (int pass = passes - 1; pass >= 0; --pass) {
-      double* Qv = Qp[pass];
-      CHEFSI_TRY(gemm_tn(ns, ns, N, -1.0, w.G, ns, Qv, ns, 0.0, w.Mb, ns, false, w.split, w.split_elems, st));
-      CHEFSI_TRY(launch_symmetrize(w.Mb, ns, ns, 2, st));
-      CHEFSI_TRY(gemm_nn(N, ns, ns, 1.0, Qv, ns, w.Mb, ns, 1.0, w.G, ns, st));
-      CHEFSI_TRY(launch_transpose(Up[pass], ns, w.Lt, ns, ns, ns, st));
-      CHEFSI_TRY(trsm_right_lower(w.G, ns, N, w.Lt, ns, ns, st));
-    }
+    for (int pass = passes - 1; pass >= 0; --pass)
+      CHEFSI_TRY(run_qr_backward(N, ns, Qp[pass], ns, Up[pass], w.G, ns, w.Mb, w.Lt, w.split, w.split_elems, st));
     // ---- backward: filter
     if (m == 0) {
       CHEFSI_TRY(launch_copy_f64(w.G, ns, d_Xbar, ldxb, N, ns, st));
@@ -1230,16 +1329,109 @@ int chefsi_loss_backward(chefsi_plan plan, const double* d_H, int m, double a, d
       CHEFSI_TRY(launch_copy_f64(w.G, ns, w.LA, ns, N, ns, st));
       CHEFSI_TRY(reverse_sweep(p, m, stride, d_X, ldx, ns, w, d_Hbar, d_Xbar, ldxb, st));
     }
-    double hl = 0.0;
-    int hs[2] = {0, 0};
-    CHEFSI_HIP(hipMemcpyAsync(&hl, w.loss, sizeof(double), hipMemcpyDeviceToHost, st));
-    CHEFSI_HIP(hipMemcpyAsync(hs, w.status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    CHEFSI_HIP(hipStreamSynchronize(st));
-    if (h_loss) *h_loss = hl;
-    if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
-    if (hs[1] < 0) return fail(CHEFSI_ERR_NONFINITE, "the projected matrix is not finite");
-    if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");
+    return read_loss_status(w, h_loss, st);
+  });
+}
+
+int chefsi_loss(chefsi_plan plan, const double* d_H, int m, double a, double b, double a0, int passes, int k,
+                const double* d_X, int64_t ldx, int ns, double* h_loss, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (d_H == nullptr || h_loss == nullptr) return fail(CHEFSI_ERR_ARG, "H or loss is NULL");
+    CHEFSI_TRY(validate_bwd_common(p, m, a, b, a0, ns, m > 0 ? m : 1));
+    if (passes != 1 && passes != 2) return fail(CHEFSI_ERR_ARG, "passes must be 1 or 2");
+    if (k < 1 || k > ns) return fail(CHEFSI_ERR_ARG, "k must be in [1, ns]");
+    CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_backward_workspace_bytes(plan, CHEFSI_OP_LOSS, m, ns, passes, 1, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    BwdWs w;
+    const int stride = std::max(m, 1);
+    CHEFSI_TRY(carve_bwd(c, p, m, ns, passes, stride, true, w, false));
+    CHEFSI_TRY(loss_forward_dev(p, d_H, m, a, b, a0, passes, k, stride, d_X, ldx, ns, w, st));
+    return read_loss_status(w, h_loss, st);
+  });
+}
+
+int chefsi_orthonormalize_backward_workspace_bytes(int64_t n, int ns, size_t* bytes) {
+  return guarded([&]() -> int {
+    if (bytes == nullptr) return fail(CHEFSI_ERR_ARG, "bytes is NULL");
+    if (n < 1 || ns < 1 || ns > n) return fail(CHEFSI_ERR_ARG, "need 1 <= ns <= n");
+    Carver c(nullptr, 0);
+    QrBwdWs q;
+    carve_qr_bwd(c, n, ns, q);
+    *bytes = c.used;
     return CHEFSI_OK;
+  });
+}
+
+int chefsi_orthonormalize_backward(int64_t n, int ns, const double* d_Yhat, int64_t ldy, const double* d_U,
+                                   const double* d_Yhat_bar, int64_t ldyb, double* d_Y_bar, int64_t ldb, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (n < 1 || ns < 1 || ns > n) return fail(CHEFSI_ERR_ARG, "need 1 <= ns <= n");
+    if (d_U == nullptr) return fail(CHEFSI_ERR_ARG, "U is NULL");
+    CHEFSI_TRY(validate_mv("Yhat", d_Yhat, ldy, ns));
+    CHEFSI_TRY(validate_mv("Yhat_bar", d_Yhat_bar, ldyb, ns));
+    CHEFSI_TRY(validate_mv("Y_bar", d_Y_bar, ldb, ns));
+    const size_t yb = mv_bytes(n, ldy, ns, 8), gb = mv_bytes(n, ldyb, ns, 8), ob = mv_bytes(n, ldb, ns, 8);
+    const size_t ub = static_cast<size_t>(ns) * ns * 8;
+    if (overlaps(d_Y_bar, ob, d_Yhat, yb) || overlaps(d_Y_bar, ob, d_U, ub))
+      return fail(CHEFSI_ERR_ARG, "Y_bar overlaps Yhat or U");
+    const bool in_place = (d_Y_bar == d_Yhat_bar);
+    if (in_place && ldb != ldyb) return fail(CHEFSI_ERR_ARG, "in place needs ld(Y_bar) == ld(Yhat_bar)");
+    if (!in_place && overlaps(d_Y_bar, ob, d_Yhat_bar, gb)) return fail(CHEFSI_ERR_ARG, "Y_bar partially overlaps Yhat_bar");
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_orthonormalize_backward_workspace_bytes(n, ns, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    QrBwdWs q;
+    carve_qr_bwd(c, n, ns, q);
+    if (!in_place) CHEFSI_TRY(launch_copy_f64(d_Yhat_bar, ldyb, d_Y_bar, ldb, n, ns, st));
+    return run_qr_backward(n, ns, d_Yhat, ldy, d_U, d_Y_bar, ldb, q.M, q.Lt, q.split, q.split_elems, st);
+  });
+}
+
+int chefsi_rayleigh_ritz_backward(chefsi_plan plan, const double* d_H, const double* d_Yhat, int64_t ldy, int ns,
+                                  const double* d_Q, const double* d_ritz_bar, double* d_Yhat_bar, int64_t ldyb,
+                                  double* d_Hbar, int accumulate, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (d_H == nullptr || d_Q == nullptr || d_ritz_bar == nullptr || d_Hbar == nullptr)
+      return fail(CHEFSI_ERR_ARG, "H, Q, ritz_bar or Hbar is NULL");
+    if (ns < 1 || ns > p.N) return fail(CHEFSI_ERR_ARG, "ns must be in [1, N]");
+    CHEFSI_TRY(validate_mv("Yhat", d_Yhat, ldy, ns));
+    CHEFSI_TRY(validate_mv("Yhat_bar", d_Yhat_bar, ldyb, ns));
+    const size_t ob = mv_bytes(p.N, ldyb, ns, 8), hb = static_cast<size_t>(p.h_elems) * 8;
+    const size_t nn8 = static_cast<size_t>(ns) * ns * 8;
+    if (overlaps(d_Yhat_bar, ob, d_Yhat, mv_bytes(p.N, ldy, ns, 8)) || overlaps(d_Yhat_bar, ob, d_H, hb) ||
+        overlaps(d_Yhat_bar, ob, d_Q, nn8) || overlaps(d_Yhat_bar, ob, d_Hbar, hb) ||
+        overlaps(d_Yhat_bar, ob, d_ritz_bar, static_cast<size_t>(ns) * 8))
+      return fail(CHEFSI_ERR_ARG, "Yhat_bar overlaps another argument");
+    if (overlaps(d_Hbar, hb, d_H, hb) || overlaps(d_Hbar, hb, d_Yhat, mv_bytes(p.N, ldy, ns, 8)) ||
+        overlaps(d_Hbar, hb, d_Q, nn8))
+      return fail(CHEFSI_ERR_ARG, "Hbar overlaps another argument");
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_workspace_bytes(plan, CHEFSI_OP_RAYLEIGH_RITZ_BACKWARD, ns, 0, 1, 1, &need));
+    CHEFSI_TRY(check_ws(ws, ws_bytes, need));
+    CHEFSI_TRY(check_device(p));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Carver c(ws, ws_bytes);
+    RrBwdWs r;
+    carve_rr_bwd(c, p, ns, r);
+    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, false, r.panel, st));
+    CHEFSI_TRY(launch_repack(p, d_H, CHEFSI_F64, true, r.panelT, st));
+    CHEFSI_TRY(launch_const_coef3(1.0, 0.0, 0.0, r.cconst, st));
+    CHEFSI_TRY(launch_const_coef3(1.0, -1.0, 0.0, r.cconst + 4, st));
+    if (!accumulate) CHEFSI_TRY(launch_fill(d_Hbar, p.h_elems, 0.0, st));
+    return run_rr_backward(p, r.panel, r.panelT, r.cconst, d_Yhat, ldy, ns, d_Q, d_ritz_bar, r.QT, r.QD, r.Hhb,
+                           r.YH, d_Yhat_bar, ldyb, d_Hbar, st);
   });
 }
 

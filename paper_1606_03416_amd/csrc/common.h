@@ -205,8 +205,9 @@ int launch_fill_int(int* d, int64_t count, int v, hipStream_t st);
 int trmm_upper_upper(const double* A, const double* B, double* C, int n, hipStream_t st);
 int launch_eigvec_fix(const double* Vcm, int64_t ldv, int n, double* Q, int64_t ldq,
                       hipStream_t st);
+// B[c][r] = A[r][c] * (row_scale ? row_scale[r] : 1)
 int launch_transpose(const double* A, int64_t lda, double* B, int64_t ldb, int rows, int cols,
-                     hipStream_t st);
+                     hipStream_t st, const double* row_scale = nullptr);
 
 // Eigensolver (eig.hip)
 int eig_workspace_bytes(Plan& p, int n, size_t* bytes);

@@ -774,9 +774,9 @@ int trmm_upper_upper(const double* A, const double* B, double* C, int n, hipStre
 }
 
 int launch_transpose(const double* A, int64_t lda, double* B, int64_t ldb, int rows, int cols,
-                     hipStream_t st) {
+                     hipStream_t st, const double* row_scale) {
   dim3 grid(static_cast<unsigned>(ceil_div(cols, 32)), static_cast<unsigned>(ceil_div(rows, 32)));
-  transpose_kernel<<<grid, 256, 0, st>>>(A, lda, B, ldb, rows, cols, nullptr);
+  transpose_kernel<<<grid, 256, 0, st>>>(A, lda, B, ldb, rows, cols, row_scale);
   CHEFSI_LAUNCHED("transpose");
   return CHEFSI_OK;
 }

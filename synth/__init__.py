@@ -41,7 +41,7 @@ Random streams: numpy SeedSequence(base_seed, spawn_key=(purpose, K)), so any
 element's data can be regenerated on its own.  Purposes: 0 eigenvalues,
 1 Haar Q, 2 off-diagonal blocks, 3 start block X, 4 Lanczos start vector,
 5 mixed J_K draw, 6 finite-difference entry choice, 7 ALB samples,
-8 ALB change between SCF steps.
+8 ALB change between SCF steps, 9 dense orthonormal block.
 """
 from __future__ import annotations
 
@@ -56,7 +56,7 @@ BASE_SEED = 1606
 SLOT_DIRS = ((0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1))
 
 (PURPOSE_EIG, PURPOSE_HAAR, PURPOSE_OFFDIAG, PURPOSE_X0, PURPOSE_LANCZOS, PURPOSE_JDRAW, PURPOSE_FD,
- PURPOSE_ALB, PURPOSE_ALB_STEP) = range(9)
+ PURPOSE_ALB, PURPOSE_ALB_STEP, PURPOSE_ORTH) = range(10)
 
 # Boltzmann constant in Hartree per kelvin (CODATA 2018) and the electronic
 # temperature of the paper's runs (Sec. III: 300 K Fermi-Dirac smearing).
@@ -268,6 +268,43 @@ def make_start_block(J: np.ndarray, ns: int, base_seed: int = BASE_SEED, dtype=n
 
 def make_lanczos_start(N: int, base_seed: int = BASE_SEED) -> np.ndarray:
     return rng_for(PURPOSE_LANCZOS, 0, base_seed).standard_normal(N)
+
+
+def make_orthonormal_block(N: int, ns: int, base_seed: int = BASE_SEED, threads: int = 0) -> np.ndarray:
+    """A dense N x ns block with orthonormal columns, cheap to draw at any size:
+    ns distinct columns of the orthonormal DCT-II basis of length N (random
+    frequencies k_j), with the rows permuted and their signs flipped at random,
+        Y[i, j] = d_i c_{k_j} cos(pi (2 p_i + 1) k_j / (2N)),
+    c_0 = sqrt(1/N), c_k = sqrt(2/N) otherwise, p a random permutation and d
+    random signs.  The argument (2p+1)k is reduced modulo 4N in integers
+    before the cosine, so every entry is accurate to rounding.  Rows are drawn
+    in blocks on several threads; the result does not depend on the count."""
+    import concurrent.futures as cf
+    import os
+    if not (1 <= ns <= N):
+        raise ValueError("need 1 <= ns <= N")
+    g = rng_for(PURPOSE_ORTH, 0, base_seed)
+    k = np.sort(g.choice(N, size=ns, replace=False)).astype(np.int64)
+    perm = g.permutation(N).astype(np.int64)
+    sign = np.where(g.integers(0, 2, size=N) == 1, 1.0, -1.0)
+    scale = np.where(k == 0, np.sqrt(1.0 / N), np.sqrt(2.0 / N))
+    Y = np.empty((N, ns), dtype=np.float64)
+    step = 2048
+
+    def fill(r0):
+        r1 = min(N, r0 + step)
+        m = ((2 * perm[r0:r1, None] + 1) * k[None, :]) % (4 * N)
+        Y[r0:r1] = np.cos((np.pi / (2 * N)) * m) * scale[None, :] * sign[r0:r1, None]
+
+    nthr = threads or min(16, os.cpu_count() or 1)
+    starts = range(0, N, step)
+    if nthr <= 1:
+        for r0 in starts:
+            fill(r0)
+    else:
+        with cf.ThreadPoolExecutor(nthr) as ex:
+            list(ex.map(fill, starts))
+    return Y
 
 
 def fd_entries(P: BlockProblem, count: int, base_seed: int = BASE_SEED):

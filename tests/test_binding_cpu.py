@@ -58,6 +58,9 @@ def test_every_plan_method_checks_first():
         lambda: p.density_blocks(X, cpu(48)),
         lambda: p.realign(X, cpu(p.N * 16), cpu(p.N * 16), 16),
         lambda: chefsi.orthonormalize(X),
+        lambda: chefsi.orthonormalize_backward(X, cpu(48, 48), X),
+        lambda: p.loss(H, X, 4, 0.0, 1.0, -1.0, 8),
+        lambda: p.rayleigh_ritz_backward(H, X, cpu(48, 48), cpu(48)),
         lambda: chefsi.occupations(cpu(48), 10.0, 1e-3),
     ]
     for c in calls:

@@ -156,6 +156,90 @@ def test_diff_workload_gradient_against_finite_differences(lib):
     assert abs((lp - lm) / (2 * h) - dd) <= 1e-4 * max(abs(dd), 1e-8)
 
 
+def test_diff_workload_gradient_matches_oracle(lib):
+    """Differentiation workload against the oracle's block-mode adjoint: X is
+    the output of 3 cold oracle cycles (the oracle's own Lanczos bound and
+    policy), bounds from its last Ritz values; loss over the lowest 384 Ritz
+    values, two Cholesky-QR passes, checkpoints every 4 steps."""
+    w = synth.DIFF
+    P = synth.make_problem(w)
+    op = oracle.BlockOperator(P.grid, P.stencil, P.J, P.blocks)
+    X, theta, _, hist = core.run_sweeps(op, synth.make_start_block(P.J, w.ns), synth.make_lanczos_start(P.N),
+                                        w.m, 3)
+    bounds = core.bounds_warm(theta, hist[0][0][1])
+    k = 384
+    L_o, cache = oracle.loss_forward(op, X, w.m, bounds, k, 2)
+    Gb_o, Xbar_o = oracle.loss_backward(op, cache)
+    plan = lib.Plan(P.grid, P.stencil, P.J)
+    L, Hbar, Xbar = plan.loss_backward(dev(P.packed()), dev(X), w.m, *bounds, k, 2, 4)
+    Gb = synth.BlockProblem.from_packed(P.grid, P.stencil, P.J, host(Hbar)).blocks
+    eH, eX = blocks_rel(Gb, Gb_o), float(np.linalg.norm(host(Xbar) - Xbar_o) / np.linalg.norm(Xbar_o))
+    print(f"diff workload vs oracle adjoint: loss {abs(L - L_o) / abs(L_o):.2e}, Hbar {eH:.2e}, Xbar {eX:.2e}")
+    assert abs(L - L_o) <= 1e-12 * abs(L_o)
+    assert eH <= 1e-10 and eX <= 1e-10
+
+
+@pytest.mark.parametrize("n,ns,inplace", [(300, 20, False), (2000, 130, True), (10368, 257, False)])
+def test_orthonormalize_backward_matches_oracle(lib, n, ns, inplace):
+    """chefsi_orthonormalize_backward on the oracle's own QR factors (two
+    passes, combined factor) against the oracle's QR adjoint."""
+    g = np.random.default_rng(n + ns)
+    Y = g.standard_normal((n, ns)) * 10.0 ** g.uniform(-2, 2, ns)[None, :]
+    Yh, U, _ = oracle.cholesky_qr(Y, 2)
+    Gbar = g.standard_normal((n, ns))
+    ref = oracle.cholesky_qr_backward([Yh], [U], Gbar)
+    Gd = dev(Gbar)
+    out = lib.orthonormalize_backward(dev(Yh), dev(U), Gd, out=Gd if inplace else None)
+    if inplace:
+        assert out.data_ptr() == Gd.data_ptr()
+    assert np.linalg.norm(host(out) - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name,ns", [("tiny", 48), ("mixed", 100)])
+def test_rayleigh_ritz_backward_matches_oracle(lib, name, ns):
+    """chefsi_rayleigh_ritz_backward on the oracle's orthonormal block and
+    eigenvectors, random Ritz-value cotangent, against the oracle's rule; and
+    accumulation onto an existing gradient."""
+    if name == "tiny":
+        P = synth.make_problem(synth.TINY)
+    else:
+        J = np.array([8, 16, 24, 40, 64, 128, 72, 88, 104, 120, 56, 32], dtype=np.int32)
+        P = synth.make_blocks((4, 3, 1), 5, J)
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    op = oracle.DenseOperator(H)
+    g = np.random.default_rng(ns)
+    Yh = oracle.cholesky_qr(g.standard_normal((P.N, ns)), 2)[0]
+    _, theta, _, Q, _ = oracle.rayleigh_ritz(op, Yh)
+    tb = g.standard_normal(ns)
+    acc = oracle.adjoint._PatternAccumulator(op)
+    Yb_o = oracle.rayleigh_ritz_backward(op, Yh, Q, tb, acc)
+    Gb_o = oracle.restrict_to_pattern(acc.result(), P.grid, P.stencil, P.J)
+    plan = lib.Plan(P.grid, P.stencil, P.J)
+    Hd = dev(P.packed())
+    Yb, Hbar = plan.rayleigh_ritz_backward(Hd, dev(Yh), dev(Q), dev(tb))
+    assert np.linalg.norm(host(Yb) - Yb_o) <= 1e-12 * np.linalg.norm(Yb_o)
+    Gb = synth.BlockProblem.from_packed(P.grid, P.stencil, P.J, host(Hbar)).blocks
+    assert blocks_rel(Gb, Gb_o) <= 1e-12
+    H0 = g.standard_normal(P.packed_size())
+    _, Hacc = plan.rayleigh_ritz_backward(Hd, dev(Yh), dev(Q), dev(tb), Hbar=dev(H0), accumulate=True)
+    Gb2 = synth.BlockProblem.from_packed(P.grid, P.stencil, P.J, host(Hacc) - H0).blocks
+    assert blocks_rel(Gb2, Gb_o) <= 1e-12
+
+
+def test_loss_forward_alone_matches_the_adjoint_forward(lib):
+    """chefsi_loss runs only the forward and returns exactly the loss that
+    chefsi_loss_backward reports (same arithmetic)."""
+    P, op, X, bounds = oracle_case((3, 3, 3), 8, 24, 6, 16)
+    plan = lib.Plan(P.grid, P.stencil, P.J)
+    Hd, Xd = dev(P.packed()), dev(X)
+    for passes in (1, 2):
+        L0 = plan.loss(Hd, Xd, 6, *bounds, 16, passes)
+        L1 = plan.loss_backward(Hd, Xd, 6, *bounds, 16, passes, 2)[0]
+        assert L0 == L1
+        L_o = oracle.loss_forward(op, X, 6, bounds, 16, passes)[0]
+        assert abs(L0 - L_o) <= 1e-12 * abs(L_o)
+
+
 def test_autograd_functions(lib):
     P, op, X, bounds = oracle_case((3, 3, 3), 8, 24, 6, 16)
     plan = lib.Plan(P.grid, P.stencil, P.J)
@@ -163,8 +247,13 @@ def test_autograd_functions(lib):
     Xd = dev(X).requires_grad_(True)
     L = lib.ChefsiLoss.apply(Hd, Xd, plan, 6, bounds, 16, 2, 4)
     gH, gX = torch.autograd.grad(L, (Hd, Xd))
-    _, Hbar, Xbar = plan.loss_backward(Hd.detach(), Xd.detach(), 6, *bounds, 16, 2, 4)
+    L1, Hbar, Xbar = plan.loss_backward(Hd.detach(), Xd.detach(), 6, *bounds, 16, 2, 4)
+    assert float(L.detach()) == L1
     assert torch.equal(gH, Hbar) and torch.equal(gX, Xbar)
+    # without gradients the forward is chefsi_loss alone
+    with torch.no_grad():
+        L2 = lib.ChefsiLoss.apply(Hd, Xd, plan, 6, bounds, 16, 2, 4)
+    assert float(L2) == plan.loss(Hd.detach(), Xd.detach(), 6, *bounds, 16, 2)
     a, b, a0 = 0.3, 5.0, -1.0
     Y = lib.ChebFilter.apply(Hd, Xd, plan, 5, a, b, a0, 2)
     Ybar = torch.ones_like(Y)
