@@ -160,6 +160,23 @@ int chefsi_filter(chefsi_plan plan, const double* d_H, int m, double a, double b
                   int dtype, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy, int ns,
                   void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of chefsi_filter, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and result as chefsi_filter without
+ * the workspace: the filter's scratch is a static device array of the library,
+ * CHEFSI_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends (its
+ * per-device address is looked up by chefsi_plan_create).  The call allocates
+ * nothing.  Returns CHEFSI_ERR_WORKSPACE when the filter's workspace
+ * (chefsi_workspace_bytes with CHEFSI_OP_FILTER) exceeds the array: e.g.
+ * N * ns * 8 bytes for FP64 plus the packed H and 2.4 MB of coefficients.
+ * Every call on a GPU uses that GPU's one array, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (several streams or host
+ * threads) race and give wrong results.  Asynchronous. */
+#define CHEFSI_NOALLOC_SCRATCH_BYTES (256u * 1024u * 1024u)
+int chefsi_filter_noalloc(chefsi_plan plan, const double* d_H, int m, double a, double b, double a0,
+                          int dtype, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy, int ns,
+                          void* stream);
+
 /* ------------------------------------------------------- orthonormalize ---
  * Algorithm 1 step 3 (Cholesky-QR): S = Y^T Y, U^T U = S, solve Yhat U = Y,
  * in place on d_Y (n x ns, float64).  passes = 2 repeats it once on Yhat

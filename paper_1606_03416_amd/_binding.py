@@ -60,6 +60,7 @@ _sig("chefsi_plan_block_elems", _i64, _vp)
 _sig("chefsi_workspace_bytes", _i, _vp, _i, _i, _i, _i, _i, ctypes.POINTER(_sz))
 _sig("chefsi_bounds", _i, _vp, _vp, _vp, _i, _vp, _i, _vp, _dp, _vp, _sz, _vp)
 _sig("chefsi_filter", _i, _vp, _vp, _i, _d, _d, _d, _i, _vp, _i64, _vp, _i64, _i, _vp, _sz, _vp)
+_sig("chefsi_filter_noalloc", _i, _vp, _vp, _i, _d, _d, _d, _i, _vp, _i64, _vp, _i64, _i, _vp)
 _sig("chefsi_orthonormalize", _i, _i64, _i, _vp, _i64, _i, _vp, _vp, _sz, _vp)
 _sig("chefsi_orthonormalize_workspace_bytes", _i, _i64, _i, _i, ctypes.POINTER(_sz))
 _sig("chefsi_rayleigh_ritz", _i, _vp, _vp, _vp, _i64, _i, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp)
@@ -209,6 +210,22 @@ class Plan:
         ws = _workspace(self.workspace_bytes(OP_FILTER, ns, dtype), X.device)
         _check(lib.chefsi_filter(self._h, _p(H), m, a, b, a0, dtype, _p(X), ldx, _p(out), ldy, ns,
                                  _p(ws), ws.numel(), _stream()))
+        return out
+
+    def filter_noalloc(self, H, X, m: int, a: float, b: float, a0: float, dtype: int = F64,
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """chefsi_filter without a workspace: the library's static per-GPU
+        scratch is used (for callers that cannot allocate; pass `out`)."""
+        self._check_H(H)
+        ldx = _mv(X, "X", self.N, self.device)
+        ns = X.shape[1]
+        if out is None:
+            out = torch.empty((self.N, ns), dtype=torch.float64, device=X.device)
+        ldy = _mv(out, "out", self.N, self.device)
+        if out.shape[1] != ns:
+            raise ValueError("out must have as many columns as X")
+        _check(lib.chefsi_filter_noalloc(self._h, _p(H), m, a, b, a0, dtype, _p(X), ldx, _p(out), ldy, ns,
+                                         _stream()))
         return out
 
     # -- Algorithm 1 steps 4-5

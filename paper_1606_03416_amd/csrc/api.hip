@@ -7,11 +7,43 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <numeric>
 
 #include "common.h"
 
+// Device scratch of chefsi_filter_noalloc: one copy per GPU, held until the
+// process ends.  Host code never uses this name as an address; it uses the
+// per-device pointer that scratch_address() obtains once per device.
+constexpr size_t kNoallocScratchBytes = size_t(256) << 20;
+static __device__ __attribute__((aligned(256))) unsigned char scratch[kNoallocScratchBytes];
+static_assert(kNoallocScratchBytes == CHEFSI_NOALLOC_SCRATCH_BYTES, "header and library agree on the size");
+
 namespace chefsi {
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's address of `scratch` (looked up once per device, with that
+// device current), or null if the lookup failed.
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
 
 void destroy_eig_handle(Plan& p);
 
@@ -854,6 +886,8 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
       delete p;
       return fail(CHEFSI_ERR_HIP, "hipGetDevice failed (no GPU?)");
     }
+    // set-up of the allocation-free filter: this device's scratch address
+    p->scratch = scratch_address(p->device);
     auto up = [&](auto** dst, const auto& vec) -> int {
       using T = typename std::remove_reference<decltype(vec)>::type::value_type;
       const size_t bytes = std::max<size_t>(vec.size(), 1) * sizeof(T);
@@ -1042,6 +1076,26 @@ int chefsi_filter(chefsi_plan plan, const double* d_H, int m, double a, double b
     CHEFSI_TRY(launch_cheb_coef(f.bounds, m, f.coef, st));
     if (m > 0) CHEFSI_TRY(launch_repack(p, d_H, dtype, false, f.panel, st, f.coef + 2));
     return run_filter(p, f.panel, dtype, f.coef, m, d_X, ldx, d_Y, ldy, ns, f, st);
+  });
+}
+
+int chefsi_filter_noalloc(chefsi_plan plan, const double* d_H, int m, double a, double b, double a0, int dtype,
+                          const double* d_X, int64_t ldx, double* d_Y, int64_t ldy, int ns, void* stream) {
+  return guarded([&]() -> int {
+    if (plan == nullptr) return fail(CHEFSI_ERR_ARG, "plan is NULL");
+    Plan& p = *P(plan);
+    if (!valid_dtype(dtype)) return fail(CHEFSI_ERR_ARG, "bad dtype");
+    if (ns < 0) return fail(CHEFSI_ERR_ARG, "ns must be >= 0");
+    size_t need = 0;
+    CHEFSI_TRY(chefsi_workspace_bytes(plan, CHEFSI_OP_FILTER, ns, dtype, 1, 1, &need));
+    if (need > kNoallocScratchBytes)
+      return fail(CHEFSI_ERR_WORKSPACE, "filter_noalloc: the filter needs " + std::to_string(need) +
+                                            " bytes of scratch, more than the library's " +
+                                            std::to_string(kNoallocScratchBytes) + " (use chefsi_filter)");
+    if (p.scratch == nullptr) return fail(CHEFSI_ERR_HIP, "filter_noalloc: the device scratch is unavailable");
+    // every other check, and the filter itself, as chefsi_filter
+    return chefsi_filter(plan, d_H, m, a, b, a0, dtype, d_X, ldx, d_Y, ldy, ns, p.scratch, kNoallocScratchBytes,
+                         stream);
   });
 }
 

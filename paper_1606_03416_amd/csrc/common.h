@@ -92,6 +92,7 @@ struct Plan {
   int64_t sqtot = 0;
   int64_t* d_sqoff = nullptr;   // [M+1]
   void* rocblas = nullptr;      // rocblas_handle for the dense eigensolver
+  void* scratch = nullptr;      // this device's address of the library's static scratch array (or null)
   size_t eig_ws_cache_n = 0, eig_ws_cache_bytes = 0, eig_ws_cache_roc = 0;
 };
 
