@@ -39,13 +39,38 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", src, "-o", obj]
+# Checking build for the CPU test suite: host code under AddressSanitizer and
+# UndefinedBehaviorSanitizer (host pass only), CHEFSI_DEBUG table checks on.
+SAN_DIR = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libchefsi_san.so")
+SAN_FLAGS = [
+    "--offload-arch=gfx950", "-O1", "-g", "-fPIC", "-std=c++17", "-DCHEFSI_DEBUG",
+    "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+    "-I" + os.path.join(ROOT, "include"),
+]
+
+
+def _compile(src: str, flags=None, outdir=None) -> str:
+    obj = os.path.join(outdir or BUILD, os.path.basename(src) + ".o")
+    cmd = [_hipcc(), *(flags or HIPCC_FLAGS), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
     return obj
+
+
+def _link(objs, out: str):
+    tmp = out + ".tmp"
+    cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-o", tmp, *objs,
+           "-L" + os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas",
+           "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, out)
 
 
 def build(verbose: bool = False) -> str:
@@ -53,19 +78,29 @@ def build(verbose: bool = False) -> str:
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-o", tmp, *objs,
-           "-L" + os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas",
-           "-Wl,-rpath," + os.path.join(ROCM, "lib")]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    _link(objs, LIB)
     if verbose:
         print("built", LIB)
     return LIB
 
 
+def build_sanitized(verbose: bool = False) -> str:
+    """The checking build (_build/san/libchefsi_san.so): host code with ASan
+    and UBSan, CHEFSI_DEBUG on.  A program that loads it must itself be linked
+    with -fsanitize=address,undefined (the sanitizer runtimes)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    srcs = sources()
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(lambda s: _compile(s, SAN_FLAGS, SAN_DIR), srcs))
+    _link(objs, SAN_LIB)
+    if verbose:
+        print("built", SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

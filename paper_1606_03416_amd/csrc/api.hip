@@ -389,6 +389,66 @@ int read_status(const int* d_status, int code_if_set, const char* what, hipStrea
   return CHEFSI_OK;
 }
 
+#ifdef CHEFSI_DEBUG
+// Debug builds: every index a kernel takes from the plan's tables stays inside
+// the buffer it indexes (checked on the host before the upload).  A failure is
+// a bug of the library, reported as CHEFSI_ERR_ARG with "table check" in the
+// message.
+int verify_plan_tables(const Plan& p, const std::vector<int32_t>& kmap, const std::vector<int32_t>& kg8,
+                       const std::vector<int32_t>& rowsrc8, const std::vector<int32_t>& order) {
+  auto bad = [](const std::string& what) { return fail(CHEFSI_ERR_ARG, "plan table check: " + what); };
+  const int M = p.M, S = p.stencil;
+  if (p.rowoff.size() != static_cast<size_t>(M) + 1 || p.rowoff[0] != 0 || p.rowoff[M] != p.N) return bad("rowoff");
+  for (int K = 0; K < M; ++K) {
+    if (p.J[K] < 1 || p.J[K] > kMaxJ || p.rowoff[K + 1] - p.rowoff[K] != p.J[K]) return bad("J / rowoff");
+    if (p.rb[K] * 16 < p.J[K] || p.rb[K] > p.maxRB) return bad("rb");
+    int kt = 0;
+    int64_t h = p.hoff[static_cast<size_t>(K) * S];
+    for (int s = 0; s < S; ++s) {
+      const int Kp = p.nbr[static_cast<size_t>(K) * S + s];
+      if (Kp < 0 || Kp >= M) return bad("nbr");
+      if (p.hoff[static_cast<size_t>(K) * S + s] != h) return bad("hoff contiguity");
+      h += static_cast<int64_t>(p.J[K]) * p.J[Kp];
+      kt += p.J[Kp];
+    }
+    if (h > p.h_elems) return bad("hoff range");
+    if (kt != p.ktot[K] || p.kpad[K] < kt || p.kpad[K] % kStepKC != 0 || p.kpad[K] > 7 * kMaxJ) return bad("kpad");
+    if (p.koff[K] + p.kpad[K] > p.kmap_len) return bad("koff");
+    for (int k = 0; k < p.kpad[K]; ++k) {
+      const int32_t g = kmap[p.koff[K] + k];
+      if (k < kt ? (g < 0 || g >= p.N) : (g != -1)) return bad("kmap entry");
+    }
+    if (p.poff[K] + static_cast<int64_t>(p.kpad[K]) * p.rb[K] * 16 > p.panel_elems) return bad("poff");
+    if (p.kpad8[K] % kPadK != 0 || p.kpad8[K] > 7 * kMaxJ) return bad("kpad8");
+    if (p.kgoff[K] + p.kpad8[K] / 8 > static_cast<int64_t>(kg8.size())) return bad("kgoff");
+    for (int t = 0; t < p.kpad8[K] / 8; ++t) {
+      const int32_t G = kg8[p.kgoff[K] + t];
+      if (G < -1 || static_cast<int64_t>(G) * 8 >= p.N8) return bad("kg8 entry");
+    }
+    if (p.poff8[K] + static_cast<int64_t>(p.kpad8[K]) * p.rb[K] * 16 > p.panel8_elems) return bad("poff8");
+    if (p.rowoff8[K + 1] - p.rowoff8[K] != round_up(p.J[K], 8)) return bad("rowoff8");
+    if (p.sqoff[K + 1] - p.sqoff[K] != static_cast<int64_t>(p.J[K]) * p.J[K]) return bad("sqoff");
+  }
+  if (p.rowoff8[M] != p.N8 || static_cast<int64_t>(rowsrc8.size()) != p.N8) return bad("N8");
+  for (int32_t r : rowsrc8)
+    if (r < -1 || r >= p.N) return bad("rowsrc8 entry");
+  std::vector<char> seen(M, 0);
+  for (int32_t K : order) {
+    if (K < 0 || K >= M || seen[K]) return bad("order is not a permutation");
+    seen[K] = 1;
+  }
+  int covered = 0;
+  for (size_t g = 0; g < p.grp_rb.size(); ++g) {
+    if (p.grp_start[g] != covered) return bad("launch groups");
+    for (int e = p.grp_start[g]; e < p.grp_start[g] + p.grp_count[g]; ++e)
+      if (p.rb[order[e]] != p.grp_rb[g]) return bad("group row-block count");
+    covered += p.grp_count[g];
+  }
+  if (covered != M) return bad("launch groups cover");
+  return CHEFSI_OK;
+}
+#endif
+
 int validate_mv(const char* name, const void* d, int64_t ld, int ns) {
   if (ns > 0 && d == nullptr) return fail(CHEFSI_ERR_ARG, std::string(name) + " is NULL");
   if (ld < ns || ld < 1) return fail(CHEFSI_ERR_ARG, std::string(name) + ": leading dimension < ns");
@@ -882,6 +942,15 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
     p->sqoff.assign(M + 1, 0);
     for (int K = 0; K < M; ++K) p->sqoff[K + 1] = p->sqoff[K] + static_cast<int64_t>(p->J[K]) * p->J[K];
     p->sqtot = p->sqoff[M];
+#ifdef CHEFSI_DEBUG
+    {
+      const int rc = verify_plan_tables(*p, kmap, kg8, rowsrc8, order);
+      if (rc != CHEFSI_OK) {
+        delete p;
+        return rc;
+      }
+    }
+#endif
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;
       return fail(CHEFSI_ERR_HIP, "hipGetDevice failed (no GPU?)");
