@@ -62,7 +62,11 @@ typedef enum {
   CHEFSI_ERR_UNSUPPORTED = 7  /* valid request the library does not implement     */
 } chefsi_status;
 
-typedef enum { CHEFSI_F64 = 0, CHEFSI_F32 = 1, CHEFSI_BF16 = 2 } chefsi_dtype;
+/* Arithmetic of the filter's recurrence.  CHEFSI_BF16X3 (split BF16) stores
+ * every value v as hi + lo with hi = bf16(v), lo = bf16(v - hi) (about 16
+ * significant bits) and forms each product from three BF16 MFMAs,
+ * A_hi B_hi + A_hi B_lo + A_lo B_hi, accumulated in FP32. */
+typedef enum { CHEFSI_F64 = 0, CHEFSI_F32 = 1, CHEFSI_BF16 = 2, CHEFSI_BF16X3 = 3 } chefsi_dtype;
 
 typedef enum {
   CHEFSI_OP_BOUNDS = 0,
@@ -152,9 +156,11 @@ int chefsi_bounds(chefsi_plan plan, const double* d_H, const double* d_v0, int l
  * p_m(t) = T_m((t-c)/e) / T_m((a0-c)/e): [a, b] is mapped to [-1, 1] and the
  * filter is 1 at a0.  Requires a0 < a < b (finite) and m >= 0.
  * dtype selects the arithmetic of the recurrence: CHEFSI_F64 (MFMA FP64),
- * CHEFSI_F32 (FP32 storage and MFMA, FP32 accumulation) or CHEFSI_BF16 (bf16
- * storage and MFMA operands, FP32 accumulation and epilogue); H is rounded to
- * that type once per call, X is read in FP64 and Y is written in FP64.
+ * CHEFSI_F32 (FP32 storage and MFMA, FP32 accumulation), CHEFSI_BF16 (bf16
+ * storage and MFMA operands, FP32 accumulation and epilogue) or CHEFSI_BF16X3
+ * (split bf16 pairs, three BF16 MFMAs per product, FP32 accumulation); H is
+ * rounded to that type once per call, X is read in FP64 and Y is written in
+ * FP64.
  * d_X and d_Y must not overlap.  Asynchronous. */
 int chefsi_filter(chefsi_plan plan, const double* d_H, int m, double a, double b, double a0,
                   int dtype, const double* d_X, int64_t ldx, double* d_Y, int64_t ldy, int ns,

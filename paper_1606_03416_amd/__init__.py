@@ -17,7 +17,7 @@ this package loads the library and fails loudly if it is missing.
 """
 from ._binding import (  # noqa: F401
     ChefsiError, Plan, orthonormalize, orthonormalize_backward, occupations, library_path, lib, ChefsiLoss, ChebFilter,
-    F64, F32, BF16, OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP,
+    F64, F32, BF16, BF16X3, OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP,
     OP_FILTER_BACKWARD, OP_LOSS_BACKWARD, OP_DENSITY, OP_LOSS, OP_RAYLEIGH_RITZ_BACKWARD, ERR_NOT_PD, ERR_ARG, ERR_WORKSPACE, ERR_EIG, ERR_HIP,
     ERR_NONFINITE, ERR_UNSUPPORTED,
 )

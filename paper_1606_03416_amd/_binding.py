@@ -20,7 +20,7 @@ if not os.path.exists(library_path):
     raise ImportError(f"{library_path} is not built; run paper_1606_03416_amd.build.build()")
 lib = ctypes.CDLL(library_path)
 
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, BF16X3 = 0, 1, 2, 3
 (OP_BOUNDS, OP_FILTER, OP_ORTHONORMALIZE, OP_RAYLEIGH_RITZ, OP_SWEEP, OP_FILTER_BACKWARD, OP_LOSS_BACKWARD,
  OP_DENSITY, OP_LOSS, OP_RAYLEIGH_RITZ_BACKWARD) = range(10)
 ERR_ARG, ERR_HIP, ERR_WORKSPACE, ERR_NOT_PD, ERR_EIG, ERR_NONFINITE, ERR_UNSUPPORTED = range(1, 8)

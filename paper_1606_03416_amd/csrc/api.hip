@@ -92,7 +92,11 @@ size_t mv_bytes(int64_t n, int64_t ld, int ns, size_t elt) {
 
 int elt_size(int dtype) { return dtype == CHEFSI_F64 ? 8 : (dtype == CHEFSI_F32 ? 4 : 2); }
 
-bool valid_dtype(int dtype) { return dtype == CHEFSI_F64 || dtype == CHEFSI_F32 || dtype == CHEFSI_BF16; }
+bool is_b16(int dtype) { return dtype == CHEFSI_BF16 || dtype == CHEFSI_BF16X3; }
+
+bool valid_dtype(int dtype) {
+  return dtype == CHEFSI_F64 || dtype == CHEFSI_F32 || dtype == CHEFSI_BF16 || dtype == CHEFSI_BF16X3;
+}
 
 // ------------------------------------------------------------ workspace layouts
 struct FilterWs {
@@ -108,14 +112,16 @@ void carve_filter(Carver& c, const Plan& p, int ns, int dtype, bool need_panel, 
   const int e = elt_size(dtype);
   f.coef = c.take<double>(3 * static_cast<int64_t>(kMaxDegree));
   f.bounds = c.take<double>(4);
-  const int64_t pe = (dtype == CHEFSI_BF16) ? p.panel8_elems : p.panel_elems;
+  // split BF16 holds hi and lo halves of every buffer
+  const int parts = (dtype == CHEFSI_BF16X3) ? 2 : 1;
+  const int64_t pe = is_b16(dtype) ? parts * p.panel8_elems : p.panel_elems;
   f.panel = need_panel ? c.take<char>(pe * e) : nullptr;
   const int64_t mv = p.N * static_cast<int64_t>(ns);
   if (dtype == CHEFSI_F64) {
     f.buf0 = c.take<double>(mv);
     f.buf1 = f.buf2 = nullptr;
-  } else if (dtype == CHEFSI_BF16) {
-    const int64_t mvp = p.N8 * static_cast<int64_t>(ns);
+  } else if (is_b16(dtype)) {
+    const int64_t mvp = parts * p.N8 * static_cast<int64_t>(ns);
     f.buf0 = c.take<char>(mvp * e);
     f.buf1 = c.take<char>(mvp * e);
     f.buf2 = c.take<char>(mvp * e);
@@ -219,14 +225,15 @@ int run_filter(const Plan& p, const void* panel, int dtype, const double* coef, 
   // low precision: X converted once, Y_1..Y_{m-1} in two rotating buffers,
   // Y_m written in FP64.
   void* L[2] = {f.buf1, f.buf2};
-  if (dtype == CHEFSI_BF16) {
-    CHEFSI_TRY(launch_to_tiles_b16(p, X, ldx, f.buf0, ns, st));
+  if (is_b16(dtype)) {
+    const bool split = (dtype == CHEFSI_BF16X3);
+    CHEFSI_TRY(launch_to_tiles_b16(p, X, ldx, f.buf0, ns, st, split));
     for (int k = 0; k < m; ++k) {
       const bool last = (k == m - 1);
       const void* in = (k == 0) ? f.buf0 : L[k % 2];
       const void* prev = (k == 0) ? nullptr : (k == 1 ? f.buf0 : L[(k - 1) % 2]);
       void* out = last ? static_cast<void*>(Y) : L[(k + 1) % 2];
-      CHEFSI_TRY(launch_step_b16(p, panel, coef + 3 * k, in, prev, out, last, ldy, ns, st));
+      CHEFSI_TRY(launch_step_b16(p, panel, coef + 3 * k, in, prev, out, last, ldy, ns, st, split));
     }
     return CHEFSI_OK;
   }

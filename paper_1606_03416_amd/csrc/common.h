@@ -145,11 +145,15 @@ int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_c
 // BF16 step on 8-row-tiled buffers (rows padded per element to multiples of
 // 8; element (row, state j) at ((row/8)*ns + j)*8 + row%8), with a panel that
 // carries H - cI: out = alpha*(panel*in) - beta*prev.  in/prev bf16; out bf16
-// tiled, or float64 row-major (ldo) when out_f64.
+// tiled, or float64 row-major (ldo) when out_f64.  split: every buffer holds
+// hi and lo halves (lo at N8*ns elements on, the lo panel at panel8_elems on)
+// and each product takes three BF16 MFMAs.
 int launch_step_b16(const Plan& p, const void* d_panel8, const double* d_coef, const void* in, const void* prev,
-                    void* out, bool out_f64, int64_t ldo, int ns, hipStream_t st);
-// float64 row-major X (ldx) -> bf16 8-row tiles with zero padding rows.
-int launch_to_tiles_b16(const Plan& p, const double* X, int64_t ldx, void* out, int ns, hipStream_t st);
+                    void* out, bool out_f64, int64_t ldo, int ns, hipStream_t st, bool split = false);
+// float64 row-major X (ldx) -> bf16 8-row tiles with zero padding rows (split:
+// also the lo halves, N8*ns elements after the hi ones).
+int launch_to_tiles_b16(const Plan& p, const double* X, int64_t ldx, void* out, int ns, hipStream_t st,
+                        bool split = false);
 // Residual partials: part[K*ns + j] = sum_{i in K} (H x_j - theta_j x_j)_i^2 (fp64).
 int launch_resid_partial(const Plan& p, const void* d_panel, const double* d_X, int64_t ldx,
                          const double* d_theta, int ns, double* d_part, hipStream_t st);

@@ -9,8 +9,13 @@
 // Y_{k+1} = alpha_k (H Y_k - c Y_k) - beta_k Y_{k-1} is applied in the
 // epilogue, so a step reads Y_k, Y_{k-1} and writes Y_{k+1} once.  FP64 and
 // FP32 stage both operands through LDS; BF16 keeps its multivectors in 8-row
-// tiles and loads MFMA operands directly.  Elements are launched in classes of
-// equal row-block count (ceil(J_K/16)), one launch per class.
+// tiles and loads MFMA operands directly.  The split-BF16 variant (BF16X3)
+// stores every value as a pair of bf16 numbers hi + lo (hi = bf16(v),
+// lo = bf16(v - hi): about 16 significant bits) in two arrays of that layout,
+// H - cI likewise, and forms each product from three BF16 MFMAs,
+// A_hi B_hi + A_hi B_lo + A_lo B_hi, accumulated in FP32 (the A_lo B_lo term is
+// below the pair's own rounding).  Elements are launched in classes of equal
+// row-block count (ceil(J_K/16)), one launch per class.
 #include <type_traits>
 
 #include "common.h"
@@ -87,9 +92,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #endif
 constexpr int BNT = 64 * CHEFSI_B16_WAVES;  // threads per work-group
 // 16-column fragments per wave: CHEFSI_B16_NC for elements of <= 64 rows,
-// 2 for larger ones (register budget)
-template <int RB>
-constexpr int b16_nc() { return RB <= 4 ? CHEFSI_B16_NC : 2; }
+// 2 for larger ones (register budget); the split variant carries twice the
+// operands and takes 2, or 1 above 64 rows
+template <int RB, bool X3 = false>
+constexpr int b16_nc() { return X3 ? (RB <= 4 ? 2 : 1) : (RB <= 4 ? CHEFSI_B16_NC : 2); }
 
 struct StepArgsB {
   const uint16_t* panel;
@@ -109,12 +115,14 @@ struct StepArgsB {
   int64_t ldo;   // row stride of a float64 row-major output
   int ns;
   int M;
+  int64_t panel_lo;   // split BF16: offset of the lo panel from panel (elements)
+  int64_t mv_lo;      // split BF16: offset of the lo array from each multivector (elements)
 };
 
-template <bool F64OUT, int RB>
+template <bool F64OUT, int RB, bool X3>
 __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct, int32_t* sG) {
   constexpr int JP = RB * 16;
-  constexpr int BNC = b16_nc<RB>();
+  constexpr int BNC = b16_nc<RB, X3>();
   constexpr int BTN = CHEFSI_B16_WAVES * 16 * BNC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q = lane >> 4, l16 = lane & 15;
@@ -143,26 +151,43 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
 #pragma unroll
     for (int n = 0; n < BNC; ++n) acc[r][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // operand slots: [0, RB) hi panel, [RB, 2RB) lo panel (split only); the
+  // same for the gathered rows with BNC
+  constexpr int NA = X3 ? 2 * RB : RB, NB = X3 ? 2 * BNC : BNC;
   auto load = [&](int c, bf16x8* A, bf16x8* B) {
     const uint16_t* p = pa + static_cast<int64_t>(c) * (JP * 32);
 #pragma unroll
     for (int r = 0; r < RB; ++r) A[r] = *reinterpret_cast<const bf16x8*>(p + r * (16 * 32));
+    if constexpr (X3) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) A[RB + r] = *reinterpret_cast<const bf16x8*>(p + a.panel_lo + r * (16 * 32));
+    }
     const int G = sG[c * 4 + q];
     const int64_t go = static_cast<int64_t>(G) * tstride;
 #pragma unroll
     for (int n = 0; n < BNC; ++n) {
-      bf16x8 v = {};
-      if (vb[n] && G >= 0) v = *reinterpret_cast<const bf16x8*>(pb[n] + go);
+      bf16x8 v = {}, w = {};
+      if (vb[n] && G >= 0) {
+        v = *reinterpret_cast<const bf16x8*>(pb[n] + go);
+        if constexpr (X3) w = *reinterpret_cast<const bf16x8*>(pb[n] + a.mv_lo + go);
+      }
       B[n] = v;
+      if constexpr (X3) B[BNC + n] = w;
     }
   };
   auto mma = [&](const bf16x8* A, const bf16x8* B) {
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int n = 0; n < BNC; ++n) acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], B[n], acc[r][n], 0, 0, 0);
+      for (int n = 0; n < BNC; ++n) {
+        if constexpr (X3) {
+          acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[RB + r], B[n], acc[r][n], 0, 0, 0);
+          acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], B[BNC + n], acc[r][n], 0, 0, 0);
+        }
+        acc[r][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], B[n], acc[r][n], 0, 0, 0);
+      }
   };
-  bf16x8 A0[RB], B0[BNC], A1[RB], B1[BNC];
+  bf16x8 A0[NA], B0[NB], A1[NA], B1[NB];
   load(0, A0, B0);
   int c = 0;
   for (; c + 2 <= nch; c += 2) {
@@ -188,13 +213,17 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
       if (i0 >= J8) continue;
       const int64_t row = g8 + i0;   // multiple of 4: the 4 rows share one tile
       const int64_t o = (row >> 3) * tstride + static_cast<int64_t>(j) * 8 + (row & 7);
-      uint2 xp = make_uint2(0, 0);
-      if (a.prev != nullptr) xp = *reinterpret_cast<const uint2*>(a.prev + o);
-      const uint32_t wp[2] = {xp.x, xp.y};
+      uint2 xp = make_uint2(0, 0), xl = make_uint2(0, 0);
+      if (a.prev != nullptr) {
+        xp = *reinterpret_cast<const uint2*>(a.prev + o);
+        if constexpr (X3) xl = *reinterpret_cast<const uint2*>(a.prev + a.mv_lo + o);
+      }
+      const uint32_t wp[2] = {xp.x, xp.y}, wl[2] = {xl.x, xl.y};
       float v[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float y = bf2f(static_cast<uint16_t>(wp[e >> 1] >> (16 * (e & 1))));
+        float y = bf2f(static_cast<uint16_t>(wp[e >> 1] >> (16 * (e & 1))));
+        if constexpr (X3) y += bf2f(static_cast<uint16_t>(wl[e >> 1] >> (16 * (e & 1))));
         v[e] = (i0 + e < JK) ? alpha * acc[r][n][e] - beta * y : 0.f;
       }
       if constexpr (F64OUT) {
@@ -205,9 +234,18 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
           if (i0 + e < JK) out[(g0 + i0 + e) * a.ldo + j] = static_cast<double>(v[e]);
       } else {
         uint16_t* out = static_cast<uint16_t*>(a.out);
+        uint16_t h[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) h[e] = f2bf(v[e]);
         *reinterpret_cast<uint2*>(out + o) =
-            make_uint2(f2bf(v[0]) | (static_cast<uint32_t>(f2bf(v[1])) << 16),
-                       f2bf(v[2]) | (static_cast<uint32_t>(f2bf(v[3])) << 16));
+            make_uint2(h[0] | (static_cast<uint32_t>(h[1]) << 16), h[2] | (static_cast<uint32_t>(h[3]) << 16));
+        if constexpr (X3) {
+          uint16_t l[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) l[e] = f2bf(v[e] - bf2f(h[e]));
+          *reinterpret_cast<uint2*>(out + a.mv_lo + o) =
+              make_uint2(l[0] | (static_cast<uint32_t>(l[1]) << 16), l[2] | (static_cast<uint32_t>(l[3]) << 16));
+        }
       }
     }
   }
@@ -216,8 +254,8 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
 #ifndef CHEFSI_B16_WPE
 #define CHEFSI_B16_WPE 3
 #endif
-template <bool F64OUT, int RB>
-__global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(RB <= 4 ? CHEFSI_B16_WPE : 2))) void step_kernel_b16(StepArgsB a) {
+template <bool F64OUT, int RB, bool X3>
+__global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(RB <= 4 && !X3 ? CHEFSI_B16_WPE : 2))) void step_kernel_b16(StepArgsB a) {
   __shared__ int32_t sG[7 * kMaxJ / 8];
   const int id = xcd_linear(blockIdx.x, gridDim.x);
 #ifndef CHEFSI_B16_CG
@@ -226,32 +264,34 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(RB <= 4 ? C
   // groups of CG column tiles of one element run together (its panel is
   // reused from L2), the groups column-major
   constexpr int CG = CHEFSI_B16_CG;
-  const int nct = (a.ns + CHEFSI_B16_WAVES * 16 * b16_nc<RB>() - 1) / (CHEFSI_B16_WAVES * 16 * b16_nc<RB>());
+  const int nct = (a.ns + CHEFSI_B16_WAVES * 16 * b16_nc<RB, X3>() - 1) / (CHEFSI_B16_WAVES * 16 * b16_nc<RB, X3>());
   const int g = id / (a.M * CG);
   const int rem = id - g * (a.M * CG);
   const int cg = (CG * g + CG <= nct) ? CG : nct - CG * g;
   const int e = rem / cg;
   const int ct = CG * g + (rem - e * cg);
-  step_body_b16<F64OUT, RB>(a, a.order[e], ct, sG);
+  step_body_b16<F64OUT, RB, X3>(a, a.order[e], ct, sG);
 }
 
-template <bool F64OUT>
+template <bool F64OUT, bool X3>
 void dispatch_step_b16(const Plan& p, StepArgsB a, int ns, hipStream_t st) {
   // one launch per row-block class of elements
   for (size_t gi = 0; gi < p.grp_rb.size(); ++gi) {
     a.order = p.d_order + p.grp_start[gi];
     a.M = p.grp_count[gi];
-    const int btn = CHEFSI_B16_WAVES * 16 * (p.grp_rb[gi] <= 4 ? CHEFSI_B16_NC : 2);
+    const int rb = p.grp_rb[gi];
+    const int nc = X3 ? (rb <= 4 ? 2 : 1) : (rb <= 4 ? CHEFSI_B16_NC : 2);
+    const int btn = CHEFSI_B16_WAVES * 16 * nc;
     dim3 grid(static_cast<unsigned>(ceil_div(ns, btn) * a.M));
-    switch (p.grp_rb[gi]) {
-      case 1: step_kernel_b16<F64OUT, 1><<<grid, BNT, 0, st>>>(a); break;
-      case 2: step_kernel_b16<F64OUT, 2><<<grid, BNT, 0, st>>>(a); break;
-      case 3: step_kernel_b16<F64OUT, 3><<<grid, BNT, 0, st>>>(a); break;
-      case 4: step_kernel_b16<F64OUT, 4><<<grid, BNT, 0, st>>>(a); break;
-      case 5: step_kernel_b16<F64OUT, 5><<<grid, BNT, 0, st>>>(a); break;
-      case 6: step_kernel_b16<F64OUT, 6><<<grid, BNT, 0, st>>>(a); break;
-      case 7: step_kernel_b16<F64OUT, 7><<<grid, BNT, 0, st>>>(a); break;
-      default: step_kernel_b16<F64OUT, 8><<<grid, BNT, 0, st>>>(a); break;
+    switch (rb) {
+      case 1: step_kernel_b16<F64OUT, 1, X3><<<grid, BNT, 0, st>>>(a); break;
+      case 2: step_kernel_b16<F64OUT, 2, X3><<<grid, BNT, 0, st>>>(a); break;
+      case 3: step_kernel_b16<F64OUT, 3, X3><<<grid, BNT, 0, st>>>(a); break;
+      case 4: step_kernel_b16<F64OUT, 4, X3><<<grid, BNT, 0, st>>>(a); break;
+      case 5: step_kernel_b16<F64OUT, 5, X3><<<grid, BNT, 0, st>>>(a); break;
+      case 6: step_kernel_b16<F64OUT, 6, X3><<<grid, BNT, 0, st>>>(a); break;
+      case 7: step_kernel_b16<F64OUT, 7, X3><<<grid, BNT, 0, st>>>(a); break;
+      default: step_kernel_b16<F64OUT, 8, X3><<<grid, BNT, 0, st>>>(a); break;
     }
   }
 }
@@ -260,7 +300,7 @@ void dispatch_step_b16(const Plan& p, StepArgsB a, int ns, hipStream_t st) {
 // 64 x 64 LDS tile: reads along a row; each thread then writes the 8 rows of
 // one (tile, state) pair as 16 contiguous bytes.
 __global__ __launch_bounds__(256) void to_tiles_b16_kernel(const double* X, int64_t ldx, const int32_t* rowsrc8,
-                                                           int64_t N8, int ns, uint16_t* out) {
+                                                           int64_t N8, int ns, uint16_t* out, uint16_t* out_lo) {
   __shared__ float tile[64][65];
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 64;
   const int c0 = blockIdx.y * 64;
@@ -281,11 +321,17 @@ __global__ __launch_bounds__(256) void to_tiles_b16_kernel(const double* X, int6
     const int c = c0 + tx;
     const int64_t G = (r0 >> 3) + gg;
     if (c < ns && G * 8 < N8) {
-      uint32_t w[4];
+      uint32_t w[4], wl[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        w[e] = f2bf(tile[gg * 8 + 2 * e][tx]) | (static_cast<uint32_t>(f2bf(tile[gg * 8 + 2 * e + 1][tx])) << 16);
+      for (int e = 0; e < 4; ++e) {
+        const float x0 = tile[gg * 8 + 2 * e][tx], x1 = tile[gg * 8 + 2 * e + 1][tx];
+        const uint16_t h0 = f2bf(x0), h1 = f2bf(x1);
+        w[e] = h0 | (static_cast<uint32_t>(h1) << 16);
+        wl[e] = f2bf(x0 - bf2f(h0)) | (static_cast<uint32_t>(f2bf(x1 - bf2f(h1))) << 16);
+      }
       *reinterpret_cast<uint4*>(out + (G * ns + c) * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+      if (out_lo != nullptr)
+        *reinterpret_cast<uint4*>(out_lo + (G * ns + c) * 8) = make_uint4(wl[0], wl[1], wl[2], wl[3]);
     }
   }
 }
@@ -633,6 +679,17 @@ __device__ __forceinline__ uint16_t cvt<uint16_t>(double v) {
   return f2bf(static_cast<float>(v));
 }
 
+// lo: the low half of a split bf16 value (v - bf16(v), rounded to bf16)
+template <typename T>
+__device__ __forceinline__ T cvt_part(double v, bool lo) {
+  return cvt<T>(v);
+}
+template <>
+__device__ __forceinline__ uint16_t cvt_part<uint16_t>(double v, bool lo) {
+  const uint16_t h = f2bf(static_cast<float>(v));
+  return lo ? f2bf(static_cast<float>(v - static_cast<double>(bf2f(h)))) : h;
+}
+
 template <typename T>
 __global__ void fill_kernel(T* d, int64_t count) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -653,6 +710,7 @@ struct RepackArgs {
   int S;
   bool transpose_h;
   const double* shift;   // if set: the self block gets -shift on its diagonal
+  bool lo_part;          // bf16 panels: store bf16(v - bf16(v)), the low half of a split value
 };
 
 // CHUNKED (bf16 path): within each 32-row chunk of the element's reduction
@@ -702,12 +760,12 @@ __global__ __launch_bounds__(256) void repack_kernel(RepackArgs ra, T* panel_bas
     // panel[pre + c][r] = tile[r][c]; write along r (panel columns) for coalescing
     for (int yy = ty; yy < 32; yy += 8) {
       const int c = tc * 32 + yy, r = tr * 32 + tx;
-      if (c < C && r < R) panel[panel_index<T, CHUNKED>(pre + c, r, JP)] = cvt<T>(tile[tx][yy]);
+      if (c < C && r < R) panel[panel_index<T, CHUNKED>(pre + c, r, JP)] = cvt_part<T>(tile[tx][yy], ra.lo_part);
     }
   } else {
     for (int yy = ty; yy < 32; yy += 8) {
       const int r = tr * 32 + yy, c = tc * 32 + tx;
-      if (r < R && c < C) panel[panel_index<T, CHUNKED>(pre + r, c, JP)] = cvt<T>(tile[yy][tx]);
+      if (r < R && c < C) panel[panel_index<T, CHUNKED>(pre + r, c, JP)] = cvt_part<T>(tile[yy][tx], ra.lo_part);
     }
   }
 }
@@ -804,7 +862,7 @@ int launch_const_coef3(double alpha, double beta, double c, double* d_coef, hipS
 int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h, void* d_panel,
                   hipStream_t st, const double* d_shift) {
   const unsigned fill_grid = grid_for(p.panel_elems);
-  RepackArgs ra{d_H, p.d_hoff, p.d_nbr, p.d_J, p.d_poff, p.d_rb, p.stencil, transpose_h, d_shift};
+  RepackArgs ra{d_H, p.d_hoff, p.d_nbr, p.d_J, p.d_poff, p.d_rb, p.stencil, transpose_h, d_shift, false};
   const int tiles = static_cast<int>(ceil_div(p.maxJ, 32) * ceil_div(p.maxJ, 32));
   dim3 grid(tiles, p.M * p.stencil);
   if (dtype == CHEFSI_F64) {
@@ -813,12 +871,18 @@ int launch_repack(const Plan& p, const double* d_H, int dtype, bool transpose_h,
   } else if (dtype == CHEFSI_F32) {
     fill_kernel<float><<<fill_grid, 256, 0, st>>>(static_cast<float*>(d_panel), p.panel_elems);
     repack_kernel<float, false><<<grid, 256, 0, st>>>(ra, static_cast<float*>(d_panel));
-  } else if (dtype == CHEFSI_BF16) {
-    const unsigned fill8 = grid_for(p.panel8_elems);
+  } else if (dtype == CHEFSI_BF16 || dtype == CHEFSI_BF16X3) {
+    // split BF16: the hi panel, then the lo panel panel8_elems further on
+    const int parts = (dtype == CHEFSI_BF16X3) ? 2 : 1;
+    const unsigned fill8 = grid_for(parts * p.panel8_elems);
     RepackArgs rb = ra;
     rb.poff = p.d_poff8;
-    fill_kernel<uint16_t><<<fill8, 256, 0, st>>>(static_cast<uint16_t*>(d_panel), p.panel8_elems);
+    fill_kernel<uint16_t><<<fill8, 256, 0, st>>>(static_cast<uint16_t*>(d_panel), parts * p.panel8_elems);
     repack_kernel<uint16_t, true><<<grid, 256, 0, st>>>(rb, static_cast<uint16_t*>(d_panel));
+    if (parts == 2) {
+      rb.lo_part = true;
+      repack_kernel<uint16_t, true><<<grid, 256, 0, st>>>(rb, static_cast<uint16_t*>(d_panel) + p.panel8_elems);
+    }
   } else {
     return fail(CHEFSI_ERR_UNSUPPORTED, "repack: dtype");
   }
@@ -857,7 +921,7 @@ int launch_step(const Plan& p, const void* d_panel, int dtype, const double* d_c
 }
 
 int launch_step_b16(const Plan& p, const void* d_panel8, const double* d_coef, const void* in, const void* prev,
-                    void* out, bool out_f64, int64_t ldo, int ns, hipStream_t st) {
+                    void* out, bool out_f64, int64_t ldo, int ns, hipStream_t st, bool split) {
   if (ns <= 0) return CHEFSI_OK;
   if (in == nullptr || out == nullptr) return fail(CHEFSI_ERR_ARG, "step: null buffer");
   if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(prev) | reinterpret_cast<uintptr_t>(d_panel8)) & 15u)
@@ -882,18 +946,28 @@ int launch_step_b16(const Plan& p, const void* d_panel8, const double* d_coef, c
   a.ldo = ldo;
   a.ns = ns;
   a.M = p.M;
-  if (out_f64)
-    dispatch_step_b16<true>(p, a, ns, st);
-  else
-    dispatch_step_b16<false>(p, a, ns, st);
+  a.panel_lo = split ? p.panel8_elems : 0;
+  a.mv_lo = split ? p.N8 * static_cast<int64_t>(ns) : 0;
+  if (split) {
+    if (out_f64)
+      dispatch_step_b16<true, true>(p, a, ns, st);
+    else
+      dispatch_step_b16<false, true>(p, a, ns, st);
+  } else if (out_f64) {
+    dispatch_step_b16<true, false>(p, a, ns, st);
+  } else {
+    dispatch_step_b16<false, false>(p, a, ns, st);
+  }
   CHEFSI_LAUNCHED("cheb_step_b16");
   return CHEFSI_OK;
 }
 
-int launch_to_tiles_b16(const Plan& p, const double* X, int64_t ldx, void* out, int ns, hipStream_t st) {
+int launch_to_tiles_b16(const Plan& p, const double* X, int64_t ldx, void* out, int ns, hipStream_t st, bool split) {
   if (ns <= 0) return CHEFSI_OK;
   dim3 grid(static_cast<unsigned>(ceil_div(p.N8, 64)), static_cast<unsigned>(ceil_div(ns, 64)));
-  to_tiles_b16_kernel<<<grid, 256, 0, st>>>(X, ldx, p.d_rowsrc8, p.N8, ns, static_cast<uint16_t*>(out));
+  uint16_t* hi = static_cast<uint16_t*>(out);
+  to_tiles_b16_kernel<<<grid, 256, 0, st>>>(X, ldx, p.d_rowsrc8, p.N8, ns, hi,
+                                            split ? hi + p.N8 * static_cast<int64_t>(ns) : nullptr);
   CHEFSI_LAUNCHED("to_tiles_b16");
   return CHEFSI_OK;
 }

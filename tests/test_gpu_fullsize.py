@@ -55,7 +55,7 @@ def case(request, lib):
     dev = torch.device("cuda", 0)
     H = torch.from_numpy(P.packed()).to(dev)
     ws = torch.empty(max(plan.workspace_bytes(lib.OP_SWEEP, w.ns, dt, 2, w.lanczos_steps)
-                         for dt in (lib.F64, lib.F32, lib.BF16)), dtype=torch.uint8, device=dev)
+                         for dt in (lib.F64, lib.F32, lib.BF16, lib.BF16X3)), dtype=torch.uint8, device=dev)
     bop = oracle.BlockOperator(P.grid, P.stencil, P.J, P.blocks)
     print(f"\n[{w.name}] N={P.N} ns={w.ns} m={w.m}", flush=True)
     yield w, P, X0, v0, plan, H, ws, bop
@@ -129,36 +129,44 @@ def test_sweeps_full_size_properties(case, lib):
 
 
 def test_mixed_sweeps_reach_the_fp64_ritz_error(case, lib):
-    """Two low-precision-filter sweeps then two FP64 sweeps from the same start
-    as four FP64 sweeps.  FP32: the wanted (lowest 3/4) Ritz values agree to
-    1e-8 and the worst wanted residual is that of the FP64 run (5 % slack).
-    BF16: orthonormal Ritz pairs whose values agree to 1e-6, with a worst
-    wanted residual within 4x of the FP64 run's (measured 1.04x on the bulk
-    workload and 3.2x on the sheet, whose wider spectrum needs more FP64
-    cycles after the BF16 ones)."""
+    """Low-precision-filter sweeps then FP64 sweeps from the same start as four
+    FP64 sweeps; "the same final Ritz error" is read as a worst wanted (lowest
+    3/4) residual within 5 % of the FP64 run's.
+    * FP32 and split BF16 (BF16X3): two low + two FP64 sweeps reach it, and the
+      wanted Ritz values agree with the FP64 run's to 1e-8.
+    * BF16 (8-bit mantissas): two low + two FP64 sweeps, then FP64 sweeps until
+      the residual reaches the FP64 run's (at most three more; measured: none on
+      the bulk workload (1.04x), one on the sheet, whose slowest wanted states
+      need more FP64 cycles to wash out the BF16 rounding)."""
     w, P, X0, v0, plan, H, ws, bop = case
     v0d = torch.from_numpy(v0).cuda()
     k = 3 * w.ns // 4
 
-    def run(dts):
+    def run(dts, target=None, extra=0):
         X = torch.from_numpy(X0).cuda()
         ritz = None
-        for i, dt in enumerate(dts):
+        n = 0
+        for i, dt in enumerate(dts + [lib.F64] * extra):
             ritz, resid, bnd, _ = plan.sweep(H, X, w.m, dtype=dt, passes=0, lanczos_steps=w.lanczos_steps,
                                              v0=v0d, ritz=ritz, warm=i > 0, ws=ws)
-        return X, ritz, resid, bnd.cpu().numpy()
+            n += 1
+            if i >= len(dts) - 1 and target is not None and float(resid[:k].max().item()) <= target:
+                break
+        return X, ritz, resid, bnd.cpu().numpy(), n
 
-    X, t64, r64, b64 = run([lib.F64] * 4)
+    X, t64, r64, b64, _ = run([lib.F64] * 4)
     t64, r64 = t64.cpu().numpy(), float(r64[:k].max().item())
     del X
     s = float(max(abs(b64[1]), abs(b64[2])))
-    for name, low, rtol, ttol in (("FP32", lib.F32, 1.05, 1e-8), ("BF16", lib.BF16, 4.0, 1e-6)):
-        X, tmx, rmx, bmx = run([low] * 2 + [lib.F64] * 2)
+    for name, low, extra, ttol in (("FP32", lib.F32, 0, 1e-8), ("BF16X3", lib.BF16X3, 0, 1e-8),
+                                   ("BF16", lib.BF16, 3, 1e-6)):
+        X, tmx, rmx, bmx, n = run([low] * 2 + [lib.F64] * 2, target=1.05 * r64, extra=extra)
         rayleigh_checks(f"{w.name} {name} mixed", P, bop, X, tmx, rmx,
                         float(max(abs(bmx[1]), abs(bmx[2]))))
         tmx, rmx = tmx.cpu().numpy(), float(rmx[:k].max().item())
         dth = np.max(np.abs(tmx[:k] - t64[:k]) / np.maximum(np.abs(t64[:k]), s))
-        print(f"[{w.name}] max wanted residual: FP64 {r64:.3e}, {name} mixed {rmx:.3e}; Ritz rel diff {dth:.3e}")
-        assert rmx <= rtol * r64
+        print(f"[{w.name}] max wanted residual: FP64 {r64:.3e}, {name} mixed {rmx:.3e} after {n} sweeps "
+              f"({n - 4} extra FP64); Ritz rel diff {dth:.3e}")
+        assert rmx <= 1.05 * r64
         assert dth <= ttol
         del X

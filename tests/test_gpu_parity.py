@@ -140,6 +140,26 @@ def test_filter_bf16_error_is_small(lib, name, ns, m):
     assert 1e-6 < err <= 3e-2
 
 
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("ns,m", [(64, 10), (1, 3), (130, 7), (257, 2), (9, 1)])
+def test_filter_split_bf16_error(lib, name, ns, m):
+    """Split BF16 (hi + lo pairs, three BF16 MFMAs per product): the error
+    against the FP64 oracle is that of ~16-bit mantissas -- far below plain
+    BF16's on the same input and far above FP64 rounding."""
+    P = PROBLEMS[name]()
+    H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
+    X = synth.make_start_block(P.J, ns)
+    a, b, a0 = 0.3, 5.5, -1.2
+    ref = oracle.chebyshev_filter(oracle.DenseOperator(H), X, m, a, b, a0)
+    plan = mkplan(lib, P)
+    Hd, Xd = dev(P.packed()), dev(X)
+    e3 = relf(host(plan.filter(Hd, Xd, m, a, b, a0, dtype=lib.BF16X3)), ref)
+    e1 = relf(host(plan.filter(Hd, Xd, m, a, b, a0, dtype=lib.BF16)), ref)
+    print(f"split-BF16 filter relative error ({name}, ns={ns}, m={m}): {e3:.3e} (plain BF16 {e1:.3e})")
+    assert 1e-10 < e3 <= 2e-4
+    assert e3 <= e1 / 30
+
+
 def test_filter_rejects_bad_arguments(lib):
     P = synth.make_problem(synth.TINY)
     plan = mkplan(lib, P)
@@ -415,7 +435,7 @@ def test_sweep_own_policy_converges_like_oracle(lib):
     assert ritz_rel(host(ritz), th_o, 6.0) <= 1e-10
 
 
-@pytest.mark.parametrize("low", ["F32", "BF16"])
+@pytest.mark.parametrize("low", ["F32", "BF16", "BF16X3"])
 def test_sweep_low_precision_filter_then_f64_finish(lib, low):
     w = synth.TINY
     P = synth.make_problem(w)
