@@ -105,7 +105,8 @@ const char* chefsi_last_error(void);
 
 /* ---------------------------------------------------------------- plan ----
  * Element grid, stencil and ALB counts (Sec. II A; Sec. II B 1, the element-
- * wise storage of H^DG).  alb_counts: host array of M int32, each in [1, 128].
+ * wise storage of H^DG).  alb_counts: host array of M int32, each in [1, 256]
+ * (the paper's bulk system uses 200 ALBs per element).
  * stencil: 7 (self + 6 faces) or 5 (self + 4 in-plane faces).
  * Builds the neighbour, row-offset and block-offset tables, uploads them to
  * the current HIP device, and keeps no copy of H's values.
@@ -344,7 +345,8 @@ int chefsi_occupations(int ns, const double* d_ritz, double n_occ, double kT, do
  * d_f: ns weights (device; the occupations); d_P: chefsi_plan_block_elems()
  * float64 (device), element K's block row-major at sum_{K'<K} J_K'^2, exactly
  * symmetric.  d_P must not overlap d_X or d_f.  Workspace:
- * chefsi_workspace_bytes(op = CHEFSI_OP_DENSITY, ns).  Asynchronous. */
+ * chefsi_workspace_bytes(op = CHEFSI_OP_DENSITY, ns).  Asynchronous.
+ * Plans with an ALB count above 128 return CHEFSI_ERR_UNSUPPORTED. */
 int chefsi_density_blocks(chefsi_plan plan, const double* d_X, int64_t ldx, int ns, const double* d_f,
                           double* d_P, void* ws, size_t ws_bytes, void* stream);
 
@@ -356,7 +358,8 @@ int chefsi_density_blocks(chefsi_plan plan, const double* d_X, int64_t ldx, int 
  * each) hold, element after element, V_K^T row-major (row j = ALB j's nr
  * samples), element K starting at nr * rowoff[K].  The ALB counts are the
  * plan's for both bases.  d_X must not overlap d_Vnew or d_Vold (d_Vnew may
- * equal d_Vold).  Workspace: chefsi_realign_workspace_bytes.  Asynchronous. */
+ * equal d_Vold).  Workspace: chefsi_realign_workspace_bytes.  Asynchronous.
+ * Plans with an ALB count above 128 return CHEFSI_ERR_UNSUPPORTED. */
 int chefsi_realign(chefsi_plan plan, int nr, const double* d_Vnew, const double* d_Vold, double* d_X,
                    int64_t ldx, int ns, void* ws, size_t ws_bytes, void* stream);
 int chefsi_realign_workspace_bytes(chefsi_plan plan, int nr, size_t* bytes);

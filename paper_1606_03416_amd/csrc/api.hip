@@ -811,7 +811,7 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
     const int M = static_cast<int>(M64);
     for (int K = 0; K < M; ++K)
       if (alb_counts[K] < 1 || alb_counts[K] > kMaxJ)
-        return fail(CHEFSI_ERR_ARG, "alb_counts[" + std::to_string(K) + "] must be in [1, 128]");
+        return fail(CHEFSI_ERR_ARG, "alb_counts[" + std::to_string(K) + "] must be in [1, 256]");
 
     Plan* p = new Plan();
     p->nx = nx;
@@ -923,7 +923,13 @@ int chefsi_plan_create(chefsi_plan* out, int nx, int ny, int nz, int stencil, co
     std::vector<int32_t> order;
     order.reserve(M);
     if (CHEFSI_ELEM_ORDER >= 1) {
-      const int BX = std::min(nx, 4), BY = std::min(ny, 4);
+#ifndef CHEFSI_ORDER_BX
+#define CHEFSI_ORDER_BX 4
+#endif
+#ifndef CHEFSI_ORDER_BY
+#define CHEFSI_ORDER_BY 4
+#endif
+      const int BX = std::min(nx, CHEFSI_ORDER_BX), BY = std::min(ny, CHEFSI_ORDER_BY);
       for (int by = 0; by < ny; by += BY)
         for (int bx = 0; bx < nx; bx += BX)
           for (int z = 0; z < nz; ++z)
@@ -1632,6 +1638,7 @@ int chefsi_density_blocks(chefsi_plan plan, const double* d_X, int64_t ldx, int 
     Plan& p = *P(plan);
     if (ns < 0) return fail(CHEFSI_ERR_ARG, "ns must be >= 0");
     if (d_P == nullptr) return fail(CHEFSI_ERR_ARG, "P is NULL");
+    if (p.maxJ > 128) return fail(CHEFSI_ERR_UNSUPPORTED, "density blocks: ALB counts above 128 are not implemented");
     if (ns > 0 && d_f == nullptr) return fail(CHEFSI_ERR_ARG, "f is NULL");
     CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
     const size_t pb = static_cast<size_t>(p.sqtot) * sizeof(double);
@@ -1671,6 +1678,7 @@ int chefsi_realign(chefsi_plan plan, int nr, const double* d_Vnew, const double*
     if (nr < 1) return fail(CHEFSI_ERR_ARG, "nr must be >= 1");
     if (ns < 0) return fail(CHEFSI_ERR_ARG, "ns must be >= 0");
     if (d_Vnew == nullptr || d_Vold == nullptr) return fail(CHEFSI_ERR_ARG, "Vnew or Vold is NULL");
+    if (p.maxJ > 128) return fail(CHEFSI_ERR_UNSUPPORTED, "re-alignment: ALB counts above 128 are not implemented");
     CHEFSI_TRY(validate_mv("X", d_X, ldx, ns));
     const size_t vb = static_cast<size_t>(p.N) * nr * sizeof(double);
     const size_t xb = mv_bytes(p.N, ldx, ns, 8);

@@ -38,7 +38,7 @@ int fail(int code, const std::string& msg);
   } while (0)
 
 // ---------------------------------------------------------------- sizes
-constexpr int kMaxJ = 128;          // largest ALB count per element supported
+constexpr int kMaxJ = 256;          // largest ALB count per element supported
 constexpr int kMaxLanczos = 64;     // largest Lanczos step count
 constexpr int kStepKC = 16;         // reduction rows of an element padded to this (FP64/FP32 chunks)
 constexpr int kPadK = 32;           // reduction rows of an element padded to this (BF16 chunk)

@@ -278,7 +278,8 @@ __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
 
 // Gradient onto the stored blocks (block-sparse "SDDMM"):
 //   Hbar_{K;s} += alpha * A[rows of K] * B[rows of K'_s]^T,
-// reduction over the ns columns; one work-group per stored block.
+// reduction over the ns columns; one work-group per 128 x 128 tile of a
+// stored block (blocks of up to 256 x 256: blockIdx.y picks the tile).
 struct SddmmArgs {
   const double* A;
   int64_t lda;
@@ -303,6 +304,8 @@ __global__ __launch_bounds__(GNT, 2) void sddmm_kernel(SddmmArgs g) {
   const int K = blk / g.S;
   const int Kp = g.nbr[blk];
   const int m = g.J[K], n = g.J[Kp];
+  const int i0 = (blockIdx.y >> 1) * GT, j0 = (blockIdx.y & 1) * GT;
+  if (i0 >= m || j0 >= n) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   d4 acc[4][4];
 #pragma unroll
@@ -310,17 +313,17 @@ __global__ __launch_bounds__(GNT, 2) void sddmm_kernel(SddmmArgs g) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
   tile_mma<false, false, VEC>(g.A + g.rowoff[K] * g.lda, g.lda, g.B + g.rowoff[Kp] * g.ldb, g.ldb, m, n, 0,
-                              g.ns, 0, 0, sA, sB, acc);
+                              g.ns, i0, j0, sA, sB, acc);
   double* C = g.Hbar + g.hoff[blk];
   const double alpha = g.alpha * (g.alpha_dev ? *g.alpha_dev : 1.0);
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = out_row(wave, lane, p, v);
+      const int i = i0 + out_row(wave, lane, p, v);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int j = out_col(wave, lane, q);
+        const int j = j0 + out_col(wave, lane, q);
         if (i < m && j < n) C[i * n + j] += alpha * acc[p][q][v];
       }
     }
@@ -697,10 +700,11 @@ int sddmm_accumulate(const Plan& p, const double* A, int64_t lda, const double* 
                      double alpha, const double* d_alpha, double* d_Hbar, hipStream_t st) {
   if (ns <= 0) return CHEFSI_OK;
   SddmmArgs g{A, lda, B, ldb, d_Hbar, p.d_hoff, p.d_nbr, p.d_J, p.d_rowoff, p.stencil, ns, alpha, d_alpha};
+  const dim3 grid(static_cast<unsigned>(p.M * p.stencil), p.maxJ > GT ? 4u : 1u);
   if (vec_ok(A, lda) && vec_ok(B, ldb))
-    sddmm_kernel<true><<<static_cast<unsigned>(p.M * p.stencil), GNT, 0, st>>>(g);
+    sddmm_kernel<true><<<grid, GNT, 0, st>>>(g);
   else
-    sddmm_kernel<false><<<static_cast<unsigned>(p.M * p.stencil), GNT, 0, st>>>(g);
+    sddmm_kernel<false><<<grid, GNT, 0, st>>>(g);
   CHEFSI_LAUNCHED("sddmm");
   return CHEFSI_OK;
 }

@@ -94,8 +94,13 @@ constexpr int BNT = 64 * CHEFSI_B16_WAVES;  // threads per work-group
 // 16-column fragments per wave: CHEFSI_B16_NC for elements of <= 64 rows,
 // 2 for larger ones (register budget); the split variant carries twice the
 // operands and takes 2, or 1 above 64 rows
+#ifndef CHEFSI_B16X3_NC
+#define CHEFSI_B16X3_NC 4
+#endif
 template <int RB, bool X3 = false>
-constexpr int b16_nc() { return X3 ? (RB <= 4 ? 2 : 1) : (RB <= 4 ? CHEFSI_B16_NC : 2); }
+constexpr int b16_nc() {
+  return X3 ? (RB <= 4 ? CHEFSI_B16X3_NC : 1) : (RB <= 4 ? CHEFSI_B16_NC : (RB <= 8 ? 2 : 1));
+}
 
 struct StepArgsB {
   const uint16_t* panel;
@@ -119,23 +124,24 @@ struct StepArgsB {
   int64_t mv_lo;      // split BF16: offset of the lo array from each multivector (elements)
 };
 
-template <bool F64OUT, int RB, bool X3>
-__device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct, int32_t* sG) {
-  constexpr int JP = RB * 16;
-  constexpr int BNC = b16_nc<RB, X3>();
+// Row blocks [rb0, rb0 + RB) of element K (nrb row blocks in all; blocks at
+// or beyond nrb are computed from a repeated valid block and not stored) for
+// one tile of columns.  sG holds the element's gathered tile indices.
+template <bool F64OUT, int RB, bool X3, int BNC>
+__device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct, const int32_t* sG, int nrb,
+                                              int rb0) {
   constexpr int BTN = CHEFSI_B16_WAVES * 16 * BNC;
+  const int JP = nrb * 16;   // panel rows of the element (chunk stride / 32)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q = lane >> 4, l16 = lane & 15;
   const int ngrp = a.kpad8[K] >> 3;
-  {
-    const int32_t* kg = a.kg8 + a.kgoff[K];
-    for (int t = tid; t < ngrp; t += BNT) sG[t] = kg[t];
-  }
-  __syncthreads();
   const int nch = ngrp >> 2;
   const int ns = a.ns;
   const int jb = ct * BTN + wave * (16 * BNC) + l16;
   const uint16_t* pa = a.panel + a.poff8[K] + l16 * 32 + 8 * q;
+  int rofs[RB];   // offset of row block rb0 + r in a chunk (a valid block for every r)
+#pragma unroll
+  for (int r = 0; r < RB; ++r) rofs[r] = min(rb0 + r, nrb - 1) * (16 * 32);
   const uint16_t* pb[BNC];
   bool vb[BNC];
 #pragma unroll
@@ -157,10 +163,10 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
   auto load = [&](int c, bf16x8* A, bf16x8* B) {
     const uint16_t* p = pa + static_cast<int64_t>(c) * (JP * 32);
 #pragma unroll
-    for (int r = 0; r < RB; ++r) A[r] = *reinterpret_cast<const bf16x8*>(p + r * (16 * 32));
+    for (int r = 0; r < RB; ++r) A[r] = *reinterpret_cast<const bf16x8*>(p + rofs[r]);
     if constexpr (X3) {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) A[RB + r] = *reinterpret_cast<const bf16x8*>(p + a.panel_lo + r * (16 * 32));
+      for (int r = 0; r < RB; ++r) A[RB + r] = *reinterpret_cast<const bf16x8*>(p + a.panel_lo + rofs[r]);
     }
     const int G = sG[c * 4 + q];
     const int64_t go = static_cast<int64_t>(G) * tstride;
@@ -209,8 +215,8 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
     if (!vb[n]) continue;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const int i0 = r * 16 + 4 * q;
-      if (i0 >= J8) continue;
+      const int i0 = (rb0 + r) * 16 + 4 * q;
+      if (rb0 + r >= nrb || i0 >= J8) continue;
       const int64_t row = g8 + i0;   // multiple of 4: the 4 rows share one tile
       const int64_t o = (row >> 3) * tstride + static_cast<int64_t>(j) * 8 + (row & 7);
       uint2 xp = make_uint2(0, 0), xl = make_uint2(0, 0);
@@ -254,9 +260,17 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
 #ifndef CHEFSI_B16_WPE
 #define CHEFSI_B16_WPE 3
 #endif
+// RB row blocks per element; above 8 the rows are computed in two passes of
+// RBS = ceil(RB / 2) blocks over the same gathered tiles (register budget).
+template <int RB>
+constexpr int b16_rbs() { return RB <= 8 ? RB : (RB + 1) / 2; }
+
 template <bool F64OUT, int RB, bool X3>
 __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(RB <= 4 && !X3 ? CHEFSI_B16_WPE : 2))) void step_kernel_b16(StepArgsB a) {
   __shared__ int32_t sG[7 * kMaxJ / 8];
+  static_assert(RB * 16 <= kMaxJ, "row blocks beyond the largest ALB count");
+  constexpr int RBS = b16_rbs<RB>();
+  constexpr int BNC = b16_nc<RB, X3>();
   const int id = xcd_linear(blockIdx.x, gridDim.x);
 #ifndef CHEFSI_B16_CG
 #define CHEFSI_B16_CG 1
@@ -264,13 +278,27 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(RB <= 4 && 
   // groups of CG column tiles of one element run together (its panel is
   // reused from L2), the groups column-major
   constexpr int CG = CHEFSI_B16_CG;
-  const int nct = (a.ns + CHEFSI_B16_WAVES * 16 * b16_nc<RB, X3>() - 1) / (CHEFSI_B16_WAVES * 16 * b16_nc<RB, X3>());
+  const int nct = (a.ns + CHEFSI_B16_WAVES * 16 * BNC - 1) / (CHEFSI_B16_WAVES * 16 * BNC);
   const int g = id / (a.M * CG);
   const int rem = id - g * (a.M * CG);
   const int cg = (CG * g + CG <= nct) ? CG : nct - CG * g;
   const int e = rem / cg;
   const int ct = CG * g + (rem - e * cg);
-  step_body_b16<F64OUT, RB, X3>(a, a.order[e], ct, sG);
+  const int K = a.order[e];
+  {
+    const int ngrp = a.kpad8[K] >> 3;
+    const int32_t* kg = a.kg8 + a.kgoff[K];
+    for (int t = threadIdx.x; t < ngrp; t += BNT) sG[t] = kg[t];
+  }
+  __syncthreads();
+  for (int rb0 = 0; rb0 < RB; rb0 += RBS) step_body_b16<F64OUT, RBS, X3, BNC>(a, K, ct, sG, RB, rb0);
+}
+
+template <bool F64OUT, int RB, bool X3>
+void launch_b16(const StepArgsB& a, int ns, hipStream_t st) {
+  const int btn = CHEFSI_B16_WAVES * 16 * b16_nc<RB, X3>();
+  dim3 grid(static_cast<unsigned>(ceil_div(ns, btn) * a.M));
+  step_kernel_b16<F64OUT, RB, X3><<<grid, BNT, 0, st>>>(a);
 }
 
 template <bool F64OUT, bool X3>
@@ -279,19 +307,23 @@ void dispatch_step_b16(const Plan& p, StepArgsB a, int ns, hipStream_t st) {
   for (size_t gi = 0; gi < p.grp_rb.size(); ++gi) {
     a.order = p.d_order + p.grp_start[gi];
     a.M = p.grp_count[gi];
-    const int rb = p.grp_rb[gi];
-    const int nc = X3 ? (rb <= 4 ? 2 : 1) : (rb <= 4 ? CHEFSI_B16_NC : 2);
-    const int btn = CHEFSI_B16_WAVES * 16 * nc;
-    dim3 grid(static_cast<unsigned>(ceil_div(ns, btn) * a.M));
-    switch (rb) {
-      case 1: step_kernel_b16<F64OUT, 1, X3><<<grid, BNT, 0, st>>>(a); break;
-      case 2: step_kernel_b16<F64OUT, 2, X3><<<grid, BNT, 0, st>>>(a); break;
-      case 3: step_kernel_b16<F64OUT, 3, X3><<<grid, BNT, 0, st>>>(a); break;
-      case 4: step_kernel_b16<F64OUT, 4, X3><<<grid, BNT, 0, st>>>(a); break;
-      case 5: step_kernel_b16<F64OUT, 5, X3><<<grid, BNT, 0, st>>>(a); break;
-      case 6: step_kernel_b16<F64OUT, 6, X3><<<grid, BNT, 0, st>>>(a); break;
-      case 7: step_kernel_b16<F64OUT, 7, X3><<<grid, BNT, 0, st>>>(a); break;
-      default: step_kernel_b16<F64OUT, 8, X3><<<grid, BNT, 0, st>>>(a); break;
+    switch (p.grp_rb[gi]) {
+      case 1: launch_b16<F64OUT, 1, X3>(a, ns, st); break;
+      case 2: launch_b16<F64OUT, 2, X3>(a, ns, st); break;
+      case 3: launch_b16<F64OUT, 3, X3>(a, ns, st); break;
+      case 4: launch_b16<F64OUT, 4, X3>(a, ns, st); break;
+      case 5: launch_b16<F64OUT, 5, X3>(a, ns, st); break;
+      case 6: launch_b16<F64OUT, 6, X3>(a, ns, st); break;
+      case 7: launch_b16<F64OUT, 7, X3>(a, ns, st); break;
+      case 8: launch_b16<F64OUT, 8, X3>(a, ns, st); break;
+      case 9: launch_b16<F64OUT, 9, X3>(a, ns, st); break;
+      case 10: launch_b16<F64OUT, 10, X3>(a, ns, st); break;
+      case 11: launch_b16<F64OUT, 11, X3>(a, ns, st); break;
+      case 12: launch_b16<F64OUT, 12, X3>(a, ns, st); break;
+      case 13: launch_b16<F64OUT, 13, X3>(a, ns, st); break;
+      case 14: launch_b16<F64OUT, 14, X3>(a, ns, st); break;
+      case 15: launch_b16<F64OUT, 15, X3>(a, ns, st); break;
+      default: launch_b16<F64OUT, 16, X3>(a, ns, st); break;
     }
   }
 }
@@ -406,7 +438,7 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
   constexpr int BROWS = NT * W / TNF;                // gathered rows per load round
   constexpr int BV = KC2 / BROWS;
   constexpr int S = KC2 / 4;                         // reduction steps per chunk
-  static_assert(AV >= 1 && AV <= 2 && BV >= 1 && S % 2 == 0, "chunk shape");
+  static_assert(AV >= 1 && AV <= 4 && BV >= 1 && S % 2 == 0, "chunk shape");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ns = a.ns;
   {
@@ -425,13 +457,13 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
   const int bcol = j0 + W * bcp;
   __syncthreads();
 
-  // panel chunk: this thread's pieces tid and tid + NT (the second only when
-  // the chunk has that many; clamped to a valid address otherwise)
-  V ra0, ra1, rb[BV];
+  // panel chunk: this thread's pieces tid + v NT, v < AV (clamped to a valid
+  // address where the chunk has fewer pieces)
+  V ra[AV], rb[BV];
   auto gload = [&](int c) {
     const TC* pa = panel + static_cast<int64_t>(c) * (KC2 * JP);
-    ra0 = *reinterpret_cast<const V*>(pa + W * min(tid, APC - 1));
-    if constexpr (AV == 2) ra1 = *reinterpret_cast<const V*>(pa + W * min(tid + NT, APC - 1));
+#pragma unroll
+    for (int v = 0; v < AV; ++v) ra[v] = *reinterpret_cast<const V*>(pa + W * min(tid + v * NT, APC - 1));
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int g = sK[c * KC2 + v * BROWS + brow];
@@ -450,10 +482,10 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
     }
   };
   auto sstore = [&](TC* A, TC* B) {
-    if (tid < APC) *reinterpret_cast<V*>(A + ((W * tid) / JP) * LDA + (W * tid) % JP) = ra0;
-    if constexpr (AV == 2) {
-      const int i1 = tid + NT;
-      if (i1 < APC) *reinterpret_cast<V*>(A + ((W * i1) / JP) * LDA + (W * i1) % JP) = ra1;
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int i1 = tid + v * NT;
+      if (i1 < APC) *reinterpret_cast<V*>(A + ((W * i1) / JP) * LDA + (W * i1) % JP) = ra[v];
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) *reinterpret_cast<V*>(B + (v * BROWS + brow) * LDB + W * bcp) = rb[v];
@@ -557,40 +589,59 @@ __global__ __launch_bounds__(NT, CHEFSI_MF_LB) void step_kernel_mf(StepArgs a) {
   __shared__ __attribute__((aligned(16))) TC sA[2 * T::KC * T::lda(RB)];
   __shared__ __attribute__((aligned(16))) TC sB[2 * T::KC * T::ldb(64 * NCF)];
   __shared__ int32_t sK[7 * kMaxJ];
+  static_assert(RB * 16 <= kMaxJ, "row blocks beyond the largest ALB count");
   const int id = xcd_linear(blockIdx.x, gridDim.x);
-  // groups of two column tiles of one element run together (its panel is
+  // groups of CG column tiles of one element run together (its panel is
   // reused from L2), the groups column-major
+#ifndef CHEFSI_MF_CG
+#define CHEFSI_MF_CG 2
+#endif
+  constexpr int CG = CHEFSI_MF_CG;
   const int nct = (a.ns + 64 * NCF - 1) / (64 * NCF);
-  const int g = id / (a.M * 2);
-  const int rem = id - g * (a.M * 2);
-  const int cg = (2 * g + 2 <= nct) ? 2 : 1;
+  const int g = id / (a.M * CG);
+  const int rem = id - g * (a.M * CG);
+  const int cg = (CG * g + CG <= nct) ? CG : nct - CG * g;
   const int e = rem / cg;
-  const int ct = 2 * g + (rem - e * cg);
+  const int ct = CG * g + (rem - e * cg);
   step_body_mf<TC, TOUT, EPI, RB, NCF>(a, a.order[e], ct, sA, sB, sK);
 }
 
 #ifndef CHEFSI_MF_NCF
 #define CHEFSI_MF_NCF 2
 #endif
+template <typename TC, typename TOUT, int EPI, int RB>
+void launch_mf(const StepArgs& a, int ns, hipStream_t st) {
+  // elements of more than 128 rows: 64 columns per work-group (register budget)
+  constexpr int NCF = RB <= 8 ? CHEFSI_MF_NCF : 1;
+  dim3 grid(static_cast<unsigned>(ceil_div(ns, 64 * NCF) * a.M)), block(NT);
+  step_kernel_mf<TC, TOUT, EPI, RB, NCF><<<grid, block, 0, st>>>(a);
+}
+
 template <typename TC, typename TOUT, int EPI>
 int dispatch_step_mf(const Plan& p, StepArgs a, int ns, hipStream_t st) {
-  // one launch per row-block class of elements, 64*NCF columns per work-group
-  constexpr int NCF = CHEFSI_MF_NCF;
+  // one launch per row-block class of elements
   for (size_t gi = 0; gi < p.grp_rb.size(); ++gi) {
     a.order = p.d_order + p.grp_start[gi];
     a.M = p.grp_count[gi];
-    const int64_t nwg = ceil_div(ns, 64 * NCF) * a.M;
-    if (nwg > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
-    dim3 grid(static_cast<unsigned>(nwg)), block(NT);
+    if (ceil_div(ns, 64) * a.M > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
     switch (p.grp_rb[gi]) {
-      case 1: step_kernel_mf<TC, TOUT, EPI, 1, NCF><<<grid, block, 0, st>>>(a); break;
-      case 2: step_kernel_mf<TC, TOUT, EPI, 2, NCF><<<grid, block, 0, st>>>(a); break;
-      case 3: step_kernel_mf<TC, TOUT, EPI, 3, NCF><<<grid, block, 0, st>>>(a); break;
-      case 4: step_kernel_mf<TC, TOUT, EPI, 4, NCF><<<grid, block, 0, st>>>(a); break;
-      case 5: step_kernel_mf<TC, TOUT, EPI, 5, NCF><<<grid, block, 0, st>>>(a); break;
-      case 6: step_kernel_mf<TC, TOUT, EPI, 6, NCF><<<grid, block, 0, st>>>(a); break;
-      case 7: step_kernel_mf<TC, TOUT, EPI, 7, NCF><<<grid, block, 0, st>>>(a); break;
-      default: step_kernel_mf<TC, TOUT, EPI, 8, NCF><<<grid, block, 0, st>>>(a); break;
+      case 1: launch_mf<TC, TOUT, EPI, 1>(a, ns, st); break;
+      case 2: launch_mf<TC, TOUT, EPI, 2>(a, ns, st); break;
+      case 3: launch_mf<TC, TOUT, EPI, 3>(a, ns, st); break;
+      case 4: launch_mf<TC, TOUT, EPI, 4>(a, ns, st); break;
+      case 5: launch_mf<TC, TOUT, EPI, 5>(a, ns, st); break;
+      case 6: launch_mf<TC, TOUT, EPI, 6>(a, ns, st); break;
+      case 7: launch_mf<TC, TOUT, EPI, 7>(a, ns, st); break;
+      case 8: launch_mf<TC, TOUT, EPI, 8>(a, ns, st); break;
+      case 9: launch_mf<TC, TOUT, EPI, 9>(a, ns, st); break;
+      case 10: launch_mf<TC, TOUT, EPI, 10>(a, ns, st); break;
+      case 11: launch_mf<TC, TOUT, EPI, 11>(a, ns, st); break;
+      case 12: launch_mf<TC, TOUT, EPI, 12>(a, ns, st); break;
+      case 13: launch_mf<TC, TOUT, EPI, 13>(a, ns, st); break;
+      case 14: launch_mf<TC, TOUT, EPI, 14>(a, ns, st); break;
+      case 15: launch_mf<TC, TOUT, EPI, 15>(a, ns, st); break;
+      case 16: launch_mf<TC, TOUT, EPI, 16>(a, ns, st); break;
+      default: return fail(CHEFSI_ERR_UNSUPPORTED, "step: more than 16 row blocks");
     }
   }
   CHEFSI_LAUNCHED("cheb_step");

@@ -51,10 +51,11 @@ __global__ __launch_bounds__(LT) void lanczos_init_kernel(const double* v0, int6
 }
 
 // y = H x for one vector, straight from the FP64 panel: one work-group of
-// kSpmvThreads per element.  Rows of up to 64 ALBs take 4 waves and rows of up
-// to 128 take 2 (lane group = row), each wave a quarter or a half of the
-// concatenated neighbour rows (pairs k, k+1 interleaved), and the parts are
-// added in a fixed order (HBM-bound; the panel is read once).
+// kSpmvThreads per element.  Rows of up to 64 ALBs take 4 waves, rows of up
+// to 128 take 2 and rows of up to 256 one (lane group = row), each wave a
+// quarter, a half or all of the concatenated neighbour rows (pairs k, k+1
+// interleaved), and the parts are added in a fixed order (HBM-bound; the
+// panel is read once).
 constexpr int kSpmvThreads = 256;
 
 __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(const double* panel, const int64_t* poff,
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(const double* panel,
   __shared__ double red[kSpmvThreads];
   const int K = blockIdx.x;
   const int JK = J[K];
-  const int splits = (JK <= 64) ? 4 : 2;
+  const int splits = (JK <= 64) ? 4 : (JK <= 128 ? 2 : 1);
   const int rows = kSpmvThreads / splits;
   const int i = threadIdx.x % rows, sp = threadIdx.x / rows;
   double a0 = 0.0, a1 = 0.0;

@@ -40,11 +40,11 @@ int main(void) {
   for (int i = 0; i < 6; ++i) J6[i] = 24;
   for (int i = 0; i < 27; ++i) J27[i] = 40;
   {
-    const int32_t mix[12] = {8, 16, 13, 40, 64, 128, 72, 88, 104, 127, 56, 1};
+    const int32_t mix[12] = {8, 16, 13, 40, 64, 128, 200, 256, 129, 127, 56, 1};
     memcpy(J12, mix, sizeof(mix));
   }
   J2[0] = 1;
-  J2[1] = 128;
+  J2[1] = 256;
 
   ++checks;
   if (chefsi_version() == NULL || strncmp(chefsi_version(), "chefsi", 6) != 0) {
@@ -61,8 +61,8 @@ int main(void) {
     expect(chefsi_plan_create(&p, 2, 2, 2, 7, NULL), CHEFSI_ERR_ARG, "plan counts NULL");
     J8[3] = 0;
     expect(chefsi_plan_create(&p, 2, 2, 2, 7, J8), CHEFSI_ERR_ARG, "plan J 0");
-    J8[3] = 129;
-    expect(chefsi_plan_create(&p, 2, 2, 2, 7, J8), CHEFSI_ERR_ARG, "plan J 129");
+    J8[3] = 257;
+    expect(chefsi_plan_create(&p, 2, 2, 2, 7, J8), CHEFSI_ERR_ARG, "plan J 257");
     J8[3] = 32;
     expect(chefsi_plan_create(&p, 4096, 4096, 4096, 7, J8), CHEFSI_ERR_ARG, "plan too many elements");
   }
@@ -72,7 +72,7 @@ int main(void) {
   plan_case(4, 3, 1, 5, J12, "mixed sheet 4x3");
   plan_case(3, 2, 1, 7, J6, "length-1 z under the 7-point stencil");
   plan_case(3, 3, 3, 7, J27, "odd 3x3x3");
-  plan_case(2, 1, 1, 7, J2, "extreme counts 1 and 128");
+  plan_case(2, 1, 1, 7, J2, "extreme counts 1 and 256");
   plan_case(2, 1, 1, 5, J2, "extreme counts, 5-point");
 
   /* entry points that validate without a plan or before using it */

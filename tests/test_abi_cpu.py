@@ -56,7 +56,7 @@ def test_plan_create_rejects_bad_arguments_on_host(raw):
     bad[3] = 0
     assert raw.chefsi_plan_create(ctypes.byref(h), 2, 2, 2, 7, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == 1
     assert b"alb_counts[3]" in raw.chefsi_last_error()
-    big = _J(8, 129)
+    big = _J(8, 257)
     assert raw.chefsi_plan_create(ctypes.byref(h), 2, 2, 2, 7, big.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == 1
     assert raw.chefsi_plan_create(None, 2, 2, 2, 7, ptr) == 1
 

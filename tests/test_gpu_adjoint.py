@@ -50,6 +50,7 @@ def oracle_case(grid, nb, ns, m, k):
     ((4, 4, 4), 16, 64, 12, 48, 2, 4),
     ((3, 3, 3), 8, 24, 6, 16, 1, 6),
     ((2, 3, 2), 12, 30, 5, 20, 2, 2),
+    ((2, 2, 1), 200, 40, 5, 30, 2, 2),     # blocks above 128 x 128 (gradient tiles)
 ])
 def test_loss_backward_matches_oracle(lib, grid, nb, ns, m, k, passes, cs):
     P, op, X, bounds = oracle_case(grid, nb, ns, m, k)

@@ -40,11 +40,20 @@ def mixed_problem():
     return synth.make_blocks((4, 3, 1), 5, J)
 
 
+def large_alb_problem():
+    """ALB counts above 128 up to 256 (the paper's bulk system has 200 per
+    element), mixed with small ones, on a 3 x 2 sheet."""
+    J = np.array([200, 256, 129, 64, 144, 16], dtype=np.int32)
+    return synth.make_blocks((3, 2, 1), 5, J)
+
+
 PROBLEMS = {
     "tiny": lambda: synth.make_problem(synth.TINY),
     "len1_z_7pt": lambda: synth.make_blocks((3, 2, 1), 7, np.full(6, 24, dtype=np.int32)),
     "mixed_5pt": mixed_problem,
     "odd_3x3x3_nb40": lambda: synth.make_blocks((3, 3, 3), 7, np.full(27, 40, dtype=np.int32)),
+    "large_alb_5pt": large_alb_problem,
+    "alb200_2x2x2": lambda: synth.make_blocks((2, 2, 2), 7, np.full(8, 200, dtype=np.int32)),
 }
 
 
@@ -289,7 +298,8 @@ def test_binding_rejects_short_or_foreign_tensors_before_the_call(lib):
 
 
 # ---------------------------------------------------------------- Rayleigh-Ritz
-@pytest.mark.parametrize("name,ns", [("tiny", 48), ("mixed_5pt", 100), ("odd_3x3x3_nb40", 300)])
+@pytest.mark.parametrize("name,ns", [("tiny", 48), ("mixed_5pt", 100), ("odd_3x3x3_nb40", 300),
+                                     ("large_alb_5pt", 130), ("alb200_2x2x2", 260)])
 def test_rayleigh_ritz_matches_oracle(lib, name, ns):
     P = PROBLEMS[name]()
     H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
@@ -374,7 +384,7 @@ def test_rayleigh_ritz_diagonal_projection(lib):
 
 
 # ---------------------------------------------------------------- bounds
-@pytest.mark.parametrize("name", ["tiny", "mixed_5pt"])
+@pytest.mark.parametrize("name", ["tiny", "mixed_5pt", "large_alb_5pt"])
 def test_bounds_match_oracle(lib, name):
     P = PROBLEMS[name]()
     H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)

@@ -199,3 +199,20 @@ def test_full_size_density_and_realign_sampled_elements(lib, wname):
     assert err <= 1e-13
     del Xd
     torch.cuda.empty_cache()
+
+
+def test_post_cycle_kernels_report_unsupported_above_128_albs(lib):
+    """Density-matrix blocks and re-alignment are built for ALB counts up to
+    128; larger plans are refused on the host before any launch."""
+    J = np.array([200, 64, 32, 129], dtype=np.int32)
+    P = synth.make_blocks((2, 2, 1), 5, J)
+    plan = lib.Plan(P.grid, P.stencil, P.J)
+    X = torch.zeros((P.N, 8), dtype=torch.float64, device="cuda")
+    f = torch.ones(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.ChefsiError) as e:
+        plan.density_blocks(X, f)
+    assert e.value.code == lib.ERR_UNSUPPORTED
+    V = torch.zeros(P.N * 256, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.ChefsiError) as e:
+        plan.realign(X, V, V, 256)
+    assert e.value.code == lib.ERR_UNSUPPORTED
