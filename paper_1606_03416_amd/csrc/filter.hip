@@ -423,14 +423,15 @@ struct MT<float> {
   }
 };
 
-template <typename TC, typename TOUT, int EPI, int RB, int NCF>
+template <typename TC, typename TOUT, int EPI, int RB, int NCF, int NW>
 __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, TC* sA, TC* sB, int32_t* sK) {
   using T = MT<TC>;
   using V = typename T::V;
+  constexpr int NT = 64 * NW;                        // threads of the work-group
   constexpr int KC2 = T::KC, W = T::W;
   constexpr int JP = RB * 16;
   constexpr int LDA = T::lda(RB);
-  constexpr int TNF = 64 * NCF;
+  constexpr int TNF = 16 * NW * NCF;                 // columns of the work-group
   constexpr int LDB = T::ldb(TNF);
   constexpr int ASZ = KC2 * LDA, BSZ = KC2 * LDB;
   constexpr int APC = KC2 * JP / W;                  // 16-byte pieces of a panel chunk
@@ -458,12 +459,15 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
   __syncthreads();
 
   // panel chunk: this thread's pieces tid + v NT, v < AV (clamped to a valid
-  // address where the chunk has fewer pieces)
-  V ra[AV], rb[BV];
+  // address where the chunk has fewer pieces); named registers, not an array,
+  // so that they never go to scratch memory
+  V ra0, ra1, ra2, ra3, rb[BV];
   auto gload = [&](int c) {
     const TC* pa = panel + static_cast<int64_t>(c) * (KC2 * JP);
-#pragma unroll
-    for (int v = 0; v < AV; ++v) ra[v] = *reinterpret_cast<const V*>(pa + W * min(tid + v * NT, APC - 1));
+    ra0 = *reinterpret_cast<const V*>(pa + W * min(tid, APC - 1));
+    if constexpr (AV > 1) ra1 = *reinterpret_cast<const V*>(pa + W * min(tid + NT, APC - 1));
+    if constexpr (AV > 2) ra2 = *reinterpret_cast<const V*>(pa + W * min(tid + 2 * NT, APC - 1));
+    if constexpr (AV > 3) ra3 = *reinterpret_cast<const V*>(pa + W * min(tid + 3 * NT, APC - 1));
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int g = sK[c * KC2 + v * BROWS + brow];
@@ -482,11 +486,13 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
     }
   };
   auto sstore = [&](TC* A, TC* B) {
-#pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int i1 = tid + v * NT;
-      if (i1 < APC) *reinterpret_cast<V*>(A + ((W * i1) / JP) * LDA + (W * i1) % JP) = ra[v];
-    }
+    auto put = [&](int i1, const V& x) {
+      if (i1 < APC) *reinterpret_cast<V*>(A + ((W * i1) / JP) * LDA + (W * i1) % JP) = x;
+    };
+    put(tid, ra0);
+    if constexpr (AV > 1) put(tid + NT, ra1);
+    if constexpr (AV > 2) put(tid + 2 * NT, ra2);
+    if constexpr (AV > 3) put(tid + 3 * NT, ra3);
 #pragma unroll
     for (int v = 0; v < BV; ++v) *reinterpret_cast<V*>(B + (v * BROWS + brow) * LDB + W * bcp) = rb[v];
   };
@@ -583,12 +589,15 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
 #ifndef CHEFSI_MF_LB
 #define CHEFSI_MF_LB 2
 #endif
-template <typename TC, typename TOUT, int EPI, int RB, int NCF>
-__global__ __launch_bounds__(NT, CHEFSI_MF_LB) void step_kernel_mf(StepArgs a) {
+template <typename TC, typename TOUT, int EPI, int RB, int NCF, int NW>
+__global__ __launch_bounds__(64 * NW, CHEFSI_MF_LB) void step_kernel_mf(StepArgs a) {
   using T = MT<TC>;
   __shared__ __attribute__((aligned(16))) TC sA[2 * T::KC * T::lda(RB)];
-  __shared__ __attribute__((aligned(16))) TC sB[2 * T::KC * T::ldb(64 * NCF)];
-  __shared__ int32_t sK[7 * kMaxJ];
+  __shared__ __attribute__((aligned(16))) TC sB[2 * T::KC * T::ldb(16 * NW * NCF)];
+#ifndef CHEFSI_SK_LEN
+#define CHEFSI_SK_LEN (7 * kMaxJ)
+#endif
+  __shared__ int32_t sK[CHEFSI_SK_LEN];
   static_assert(RB * 16 <= kMaxJ, "row blocks beyond the largest ALB count");
   const int id = xcd_linear(blockIdx.x, gridDim.x);
   // groups of CG column tiles of one element run together (its panel is
@@ -597,24 +606,32 @@ __global__ __launch_bounds__(NT, CHEFSI_MF_LB) void step_kernel_mf(StepArgs a) {
 #define CHEFSI_MF_CG 2
 #endif
   constexpr int CG = CHEFSI_MF_CG;
-  const int nct = (a.ns + 64 * NCF - 1) / (64 * NCF);
+  const int nct = (a.ns + 16 * NW * NCF - 1) / (16 * NW * NCF);
   const int g = id / (a.M * CG);
   const int rem = id - g * (a.M * CG);
   const int cg = (CG * g + CG <= nct) ? CG : nct - CG * g;
   const int e = rem / cg;
   const int ct = CG * g + (rem - e * cg);
-  step_body_mf<TC, TOUT, EPI, RB, NCF>(a, a.order[e], ct, sA, sB, sK);
+  step_body_mf<TC, TOUT, EPI, RB, NCF, NW>(a, a.order[e], ct, sA, sB, sK);
 }
 
 #ifndef CHEFSI_MF_NCF
 #define CHEFSI_MF_NCF 2
 #endif
+#ifndef CHEFSI_MF_WAVES
+#define CHEFSI_MF_WAVES 4
+#endif
+#ifndef CHEFSI_MF_WAVES_RB
+#define CHEFSI_MF_WAVES_RB 4
+#endif
 template <typename TC, typename TOUT, int EPI, int RB>
 void launch_mf(const StepArgs& a, int ns, hipStream_t st) {
-  // elements of more than 128 rows: 64 columns per work-group (register budget)
+  // elements of more than 128 rows: 16 columns per wave (register budget);
+  // elements of up to CHEFSI_MF_WAVES_RB row blocks: CHEFSI_MF_WAVES waves
   constexpr int NCF = RB <= 8 ? CHEFSI_MF_NCF : 1;
-  dim3 grid(static_cast<unsigned>(ceil_div(ns, 64 * NCF) * a.M)), block(NT);
-  step_kernel_mf<TC, TOUT, EPI, RB, NCF><<<grid, block, 0, st>>>(a);
+  constexpr int NW = RB <= CHEFSI_MF_WAVES_RB ? CHEFSI_MF_WAVES : 4;
+  dim3 grid(static_cast<unsigned>(ceil_div(ns, 16 * NW * NCF) * a.M)), block(64 * NW);
+  step_kernel_mf<TC, TOUT, EPI, RB, NCF, NW><<<grid, block, 0, st>>>(a);
 }
 
 template <typename TC, typename TOUT, int EPI>
