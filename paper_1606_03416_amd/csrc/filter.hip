@@ -91,15 +91,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #define CHEFSI_B16_WAVES 4
 #endif
 constexpr int BNT = 64 * CHEFSI_B16_WAVES;  // threads per work-group
-// 16-column fragments per wave: CHEFSI_B16_NC for elements of <= 64 rows,
-// 2 for larger ones (register budget); the split variant carries twice the
-// operands and takes 2, or 1 above 64 rows
+// 16-column fragments per wave: CHEFSI_B16_NC (split: CHEFSI_B16X3_NC) for
+// elements of <= 64 rows, 2 up to 128 rows and 1 above (register budget)
 #ifndef CHEFSI_B16X3_NC
 #define CHEFSI_B16X3_NC 4
 #endif
 template <int RB, bool X3 = false>
 constexpr int b16_nc() {
-  return X3 ? (RB <= 4 ? CHEFSI_B16X3_NC : 1) : (RB <= 4 ? CHEFSI_B16_NC : (RB <= 8 ? 2 : 1));
+  return X3 ? (RB <= 4 ? CHEFSI_B16X3_NC : (RB <= 8 ? 2 : 1)) : (RB <= 4 ? CHEFSI_B16_NC : (RB <= 8 ? 2 : 1));
 }
 
 struct StepArgsB {
