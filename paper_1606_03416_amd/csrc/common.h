@@ -40,7 +40,10 @@ int fail(int code, const std::string& msg);
 // ---------------------------------------------------------------- sizes
 constexpr int kMaxJ = 256;          // largest ALB count per element supported
 constexpr int kMaxLanczos = 64;     // largest Lanczos step count
-constexpr int kStepKC = 16;         // reduction rows of an element padded to this (FP64/FP32 chunks)
+#ifndef CHEFSI_STEP_KC
+#define CHEFSI_STEP_KC 16
+#endif
+constexpr int kStepKC = CHEFSI_STEP_KC;  // reduction rows of an element padded to this (FP64/FP32 chunks)
 constexpr int kPadK = 32;           // reduction rows of an element padded to this (BF16 chunk)
 
 __host__ __device__ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }

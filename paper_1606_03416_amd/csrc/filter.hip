@@ -383,6 +383,12 @@ __global__ __launch_bounds__(256) void to_tiles_b16_kernel(const double* X, int6
 #ifndef CHEFSI_MF_KC32
 #define CHEFSI_MF_KC32 16
 #endif
+#ifndef CHEFSI_MF_EARLY
+#define CHEFSI_MF_EARLY 1
+#endif
+#ifndef CHEFSI_MF_KC_RB
+#define CHEFSI_MF_KC_RB 16
+#endif
 template <typename TC>
 struct MT;
 
@@ -390,7 +396,9 @@ template <>
 struct MT<double> {
   typedef double2 V;                     // one 16-byte load
   static constexpr int W = 2;            // elements per load
-  static constexpr int KC = CHEFSI_MF_KC64;   // reduction rows per LDS chunk
+  // reduction rows per LDS chunk (elements of more than CHEFSI_MF_KC_RB row
+  // blocks: 8, so that a thread stages at most four panel pieces)
+  static constexpr int kc(int rb) { return rb <= CHEFSI_MF_KC_RB ? CHEFSI_MF_KC64 : 8; }
   typedef double acc_t __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -407,7 +415,7 @@ template <>
 struct MT<float> {
   typedef float4 V;
   static constexpr int W = 4;
-  static constexpr int KC = CHEFSI_MF_KC32;
+  static constexpr int kc(int rb) { return rb <= CHEFSI_MF_KC_RB ? CHEFSI_MF_KC32 : 16; }
   typedef float acc_t __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -422,12 +430,105 @@ struct MT<float> {
   }
 };
 
+// Epilogue shared by the FP64 / FP32 step kernels.  acc holds the wave's
+// RB x NCF sixteen-square fragments of element K; the wave's columns start at
+// jb.  EPI 0: Y_out = alpha (acc - c Y_in) - beta Y_prev; EPI 2: the panel
+// already carries H - cI, Y_out = alpha acc - beta Y_prev; EPI 1: per-column
+// partial sums of the squared residual rows.
+template <typename TC, typename TOUT, int EPI, int RB, int NCF>
+__device__ __forceinline__ void step_epilogue(const StepArgs& a, int K, int jb,
+                                              const typename MT<TC>::acc_t (&acc)[RB][NCF]) {
+  using T = MT<TC>;
+  const int lane = threadIdx.x & 63;
+  const int ns = a.ns;
+  const TC* in = static_cast<const TC*>(a.in);
+  const int64_t ldi = a.ldi;
+  const int JK = a.J[K];
+  const int64_t g0 = a.rowoff[K];
+  // every load goes to a clamped, valid address and only the stores are
+  // predicated, so that the loads of a row block issue together instead of
+  // one branch (and one wait) per value
+  int jc[NCF];
+  bool jok[NCF];
+#pragma unroll
+  for (int q = 0; q < NCF; ++q) {
+    const int j = jb + 16 * q + (lane & 15);
+    jok[q] = j < ns;
+    jc[q] = jok[q] ? j : ns - 1;
+  }
+  if constexpr (EPI == 0 || EPI == 2) {
+    // EPI 2: the panel carries H - cI
+    const TC alpha = static_cast<TC>(a.coef[0]), beta = static_cast<TC>(a.coef[1]);
+    const TC cc = static_cast<TC>(a.coef[2]);
+    const TC* prev = static_cast<const TC*>(a.prev);
+    TOUT* out = static_cast<TOUT*>(a.out);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      TC pv[4][NCF], iv[4][NCF];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t g = g0 + min(16 * r + T::row(lane, v), JK - 1);
+#pragma unroll
+        for (int q = 0; q < NCF; ++q) {
+          pv[v][q] = (prev != nullptr) ? prev[g * a.ldp + jc[q]] : TC(0);
+          if constexpr (EPI == 0) iv[v][q] = in[g * ldi + jc[q]];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * r + T::row(lane, v);
+        const int64_t g = g0 + i;
+#pragma unroll
+        for (int q = 0; q < NCF; ++q) {
+          TC y = (EPI == 2) ? alpha * acc[r][q][v] : alpha * (acc[r][q][v] - cc * iv[v][q]);
+          y -= beta * pv[v][q];
+          if (i < JK && jok[q]) out[g * a.ldo + jc[q]] = static_cast<TOUT>(y);
+        }
+      }
+    }
+  } else {
+    // residual partial sums over the element's rows: sum_i (H x - theta x)_i^2;
+    // each wave owns whole columns, so the sum needs no cross-wave step
+    static_assert(std::is_same<TC, double>::value, "residual epilogue is FP64");
+    double sum[NCF];
+#pragma unroll
+    for (int q = 0; q < NCF; ++q) sum[q] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      double iv[4][NCF];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t g = g0 + min(16 * r + T::row(lane, v), JK - 1);
+#pragma unroll
+        for (int q = 0; q < NCF; ++q) iv[v][q] = in[g * ldi + jc[q]];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * r + T::row(lane, v);
+#pragma unroll
+        for (int q = 0; q < NCF; ++q) {
+          const double th = a.theta[jc[q]];
+          const double d = acc[r][q][v] - th * iv[v][q];
+          if (i < JK) sum[q] += d * d;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NCF; ++q) {
+      double t = sum[q];
+      t += __shfl_xor(t, 16);
+      t += __shfl_xor(t, 32);
+      if (lane < 16 && jok[q]) a.part[static_cast<int64_t>(K) * ns + jc[q]] = t;
+    }
+  }
+}
+
 template <typename TC, typename TOUT, int EPI, int RB, int NCF, int NW>
 __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, TC* sA, TC* sB, int32_t* sK) {
   using T = MT<TC>;
   using V = typename T::V;
   constexpr int NT = 64 * NW;                        // threads of the work-group
-  constexpr int KC2 = T::KC, W = T::W;
+  constexpr int KC2 = T::kc(RB), W = T::W;
   constexpr int JP = RB * 16;
   constexpr int LDA = T::lda(RB);
   constexpr int TNF = 16 * NW * NCF;                 // columns of the work-group
@@ -439,6 +540,7 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
   constexpr int BV = KC2 / BROWS;
   constexpr int S = KC2 / 4;                         // reduction steps per chunk
   static_assert(AV >= 1 && AV <= 4 && BV >= 1 && S % 2 == 0, "chunk shape");
+  static_assert(kStepKC % KC2 == 0, "element reduction rows are padded to whole chunks");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ns = a.ns;
   {
@@ -517,101 +619,161 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
 #pragma unroll
       for (int q = 0; q < NCF; ++q) acc[r][q] = T::mma(fa[slot][r], fb[slot][q], acc[r][q]);
   };
+  // The staging registers take chunk c + 2 as soon as chunk c + 1 has gone
+  // to LDS, so a chunk's loads have a whole chunk of MFMA work to arrive in.
   gload(0);
   sstore(sA, sB);
+#if CHEFSI_MF_EARLY
+  if (nch > 1) gload(1);
+#endif
   __syncthreads();
   if (nch > 0) rd(sA, sB, 0, 0);
   for (int c = 0; c < nch; ++c) {
     const int buf = c & 1;
+#if !CHEFSI_MF_EARLY
     if (c + 1 < nch) gload(c + 1);
+#endif
 #pragma unroll
     for (int kk = 1; kk < S; ++kk) {
       rd(sA + buf * ASZ, sB + buf * BSZ, kk, kk & 1);
       mm((kk - 1) & 1);
     }
     if (c + 1 < nch) sstore(sA + (buf ^ 1) * ASZ, sB + (buf ^ 1) * BSZ);
+#if CHEFSI_MF_EARLY
+    if (c + 2 < nch) gload(c + 2);
+#endif
     __syncthreads();
     if (c + 1 < nch) rd(sA + (buf ^ 1) * ASZ, sB + (buf ^ 1) * BSZ, 0, 0);
     mm((S - 1) & 1);
   }
 
-  const int JK = a.J[K];
-  const int64_t g0 = a.rowoff[K];
-  if constexpr (EPI == 0 || EPI == 2) {
-    // EPI 2: the panel carries H - cI
-    const TC alpha = static_cast<TC>(a.coef[0]), beta = static_cast<TC>(a.coef[1]);
-    const TC cc = static_cast<TC>(a.coef[2]);
-    const TC* prev = static_cast<const TC*>(a.prev);
-    TOUT* out = static_cast<TOUT*>(a.out);
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = 16 * r + T::row(lane, v);
-#pragma unroll
-        for (int q = 0; q < NCF; ++q) {
-          const int j = j0 + cb + 16 * q + (lane & 15);
-          if (i < JK && j < ns) {
-            const int64_t g = g0 + i;
-            TC y = (EPI == 2) ? alpha * acc[r][q][v] : alpha * (acc[r][q][v] - cc * in[g * ldi + j]);
-            if (prev != nullptr) y -= beta * prev[g * a.ldp + j];
-            out[g * a.ldo + j] = static_cast<TOUT>(y);
-          }
-        }
-      }
-  } else {
-    // residual partial sums over the element's rows: sum_i (H x - theta x)_i^2;
-    // each wave owns whole columns, so the sum needs no cross-wave step
-    static_assert(std::is_same<TC, double>::value, "residual epilogue is FP64");
-#pragma unroll
-    for (int q = 0; q < NCF; ++q) {
-      const int j = j0 + cb + 16 * q + (lane & 15);
-      const double th = (j < ns) ? a.theta[j] : 0.0;
-      double sum = 0.0;
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 16 * r + T::row(lane, v);
-          if (i < JK && j < ns) {
-            const double d = acc[r][q][v] - th * in[(g0 + i) * ldi + j];
-            sum += d * d;
-          }
-        }
-      sum += __shfl_xor(sum, 16);
-      sum += __shfl_xor(sum, 32);
-      if (lane < 16 && j < ns) a.part[static_cast<int64_t>(K) * ns + j] = sum;
-    }
-  }
+  step_epilogue<TC, TOUT, EPI, RB, NCF>(a, K, j0 + cb, acc);
+}
+
+// Work-group id -> (element slot e, column tile ct): groups of CG column tiles
+// of one element run together (its panel is reused from L2), the groups
+// column-major.
+#ifndef CHEFSI_MF_CG
+#define CHEFSI_MF_CG 2
+#endif
+__device__ __forceinline__ void step_tile(int id, int M, int nct, int& e, int& ct) {
+  constexpr int CG = CHEFSI_MF_CG;
+  const int g = id / (M * CG);
+  const int rem = id - g * (M * CG);
+  const int cg = (CG * g + CG <= nct) ? CG : nct - CG * g;
+  e = rem / cg;
+  ct = CG * g + (rem - e * cg);
 }
 
 #ifndef CHEFSI_MF_LB
 #define CHEFSI_MF_LB 2
 #endif
-template <typename TC, typename TOUT, int EPI, int RB, int NCF, int NW>
-__global__ __launch_bounds__(64 * NW, CHEFSI_MF_LB) void step_kernel_mf(StepArgs a) {
-  using T = MT<TC>;
-  __shared__ __attribute__((aligned(16))) TC sA[2 * T::KC * T::lda(RB)];
-  __shared__ __attribute__((aligned(16))) TC sB[2 * T::KC * T::ldb(16 * NW * NCF)];
 #ifndef CHEFSI_SK_LEN
 #define CHEFSI_SK_LEN (7 * kMaxJ)
 #endif
+template <typename TC, typename TOUT, int EPI, int RB, int NCF, int NW>
+__global__ __launch_bounds__(64 * NW, CHEFSI_MF_LB) void step_kernel_mf(StepArgs a) {
+  using T = MT<TC>;
+  __shared__ __attribute__((aligned(16))) TC sA[2 * T::kc(RB) * T::lda(RB)];
+  __shared__ __attribute__((aligned(16))) TC sB[2 * T::kc(RB) * T::ldb(16 * NW * NCF)];
   __shared__ int32_t sK[CHEFSI_SK_LEN];
   static_assert(RB * 16 <= kMaxJ, "row blocks beyond the largest ALB count");
   const int id = xcd_linear(blockIdx.x, gridDim.x);
-  // groups of CG column tiles of one element run together (its panel is
-  // reused from L2), the groups column-major
-#ifndef CHEFSI_MF_CG
-#define CHEFSI_MF_CG 2
-#endif
-  constexpr int CG = CHEFSI_MF_CG;
-  const int nct = (a.ns + 16 * NW * NCF - 1) / (16 * NW * NCF);
-  const int g = id / (a.M * CG);
-  const int rem = id - g * (a.M * CG);
-  const int cg = (CG * g + CG <= nct) ? CG : nct - CG * g;
-  const int e = rem / cg;
-  const int ct = CG * g + (rem - e * cg);
+  int e, ct;
+  step_tile(id, a.M, (a.ns + 16 * NW * NCF - 1) / (16 * NW * NCF), e, ct);
   step_body_mf<TC, TOUT, EPI, RB, NCF, NW>(a, a.order[e], ct, sA, sB, sK);
+}
+
+// ------------------------------------------ FP64 / FP32, direct MFMA operands
+// Each wave loads its MFMA operands straight from memory in the MFMA lane
+// layout -- lane l takes panel entry (k = 4s + l/16, row 16r + l%16) and the
+// gathered entry (k = 4s + l/16, column 16q + l%16), so sixteen lanes read
+// 16 consecutive values of one row -- into a ring of P reduction steps of
+// registers.  No operand goes through LDS and the waves never wait for each
+// other after the element's reduction-row map is in LDS; the waves of a
+// work-group take neighbouring columns of the same element, so they share its
+// panel rows through the L1 cache.  Padded reduction rows (kmap < 0) gather the
+// element's first row, against the zero rows of the padded panel.
+#ifndef CHEFSI_DL_P
+#define CHEFSI_DL_P 2
+#endif
+template <typename TC, typename TOUT, int EPI, int RB, int NCF, int NW>
+__device__ __forceinline__ void step_body_dl(const StepArgs& a, int K, int ct, int32_t* sK) {
+  using T = MT<TC>;
+  using acc_t = typename T::acc_t;
+  constexpr int JP = RB * 16, TNF = 16 * NW * NCF, P = CHEFSI_DL_P;
+  static_assert(P == 1 || P == 2 || P == 4, "the ring of P steps divides the steps of a padded element");
+  static_assert(kStepKC % (4 * P) == 0, "element reduction rows are padded to whole rings");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ns = a.ns;
+  const int kp = a.kpad[K];
+  {
+    const int32_t* km = a.kmap + a.koff[K];
+    const int32_t self = static_cast<int32_t>(a.rowoff[K]);
+    for (int t = tid; t < kp; t += 64 * NW) {
+      const int32_t g = km[t];
+      sK[t] = g >= 0 ? g : self;
+    }
+  }
+  __syncthreads();
+  const TC* panel = static_cast<const TC*>(a.panel) + a.poff[K] + (lane >> 4) * JP + (lane & 15);
+  const TC* in = static_cast<const TC*>(a.in);
+  const int64_t ldi = a.ldi;
+  const int jb = ct * TNF + wave * (16 * NCF);
+  int cofs[NCF];   // the wave's columns, clamped into the block (outputs beyond ns are not stored)
+#pragma unroll
+  for (int q = 0; q < NCF; ++q) cofs[q] = min(jb + 16 * q + (lane & 15), ns - 1);
+  const int32_t* sk = sK + (lane >> 4);
+  const int nk = kp >> 2;   // reduction steps of four rows
+  TC fa[P][RB], fb[P][NCF];
+  auto ld = [&](int st, int slot) {
+    const TC* ps = panel + static_cast<int64_t>(st) * (4 * JP);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) fa[slot][r] = ps[16 * r];
+    const TC* xs = in + static_cast<int64_t>(sk[4 * st]) * ldi;
+#pragma unroll
+    for (int q = 0; q < NCF; ++q) fb[slot][q] = xs[cofs[q]];
+  };
+  acc_t acc[RB][NCF];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int q = 0; q < NCF; ++q) acc[r][q] = acc_t{};
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    ld(min(t, nk - 1), t);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  for (int s0 = 0; s0 < nk; s0 += P) {
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int q = 0; q < NCF; ++q) acc[r][q] = T::mma(fa[t][r], fb[t][q], acc[r][q]);
+      // the ring slot is refilled with step s0 + P + t (the last step again
+      // past the end: loads stay in bounds, the values are not used); the
+      // scheduling barriers keep the compiler from moving the loads next to
+      // their use
+      __builtin_amdgcn_sched_barrier(0);
+      ld(min(s0 + P + t, nk - 1), t);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  step_epilogue<TC, TOUT, EPI, RB, NCF>(a, K, jb, acc);
+}
+
+#ifndef CHEFSI_DL_LB
+#define CHEFSI_DL_LB 2
+#endif
+template <typename TC, typename TOUT, int EPI, int RB, int NCF, int NW>
+__global__ __launch_bounds__(64 * NW, CHEFSI_DL_LB) void step_kernel_dl(StepArgs a) {
+  __shared__ int32_t sK[CHEFSI_SK_LEN];
+  static_assert(RB * 16 <= kMaxJ, "row blocks beyond the largest ALB count");
+  const int id = xcd_linear(blockIdx.x, gridDim.x);
+  int e, ct;
+  step_tile(id, a.M, (a.ns + 16 * NW * NCF - 1) / (16 * NW * NCF), e, ct);
+  step_body_dl<TC, TOUT, EPI, RB, NCF, NW>(a, a.order[e], ct, sK);
 }
 
 #ifndef CHEFSI_MF_NCF
@@ -633,6 +795,39 @@ void launch_mf(const StepArgs& a, int ns, hipStream_t st) {
   step_kernel_mf<TC, TOUT, EPI, RB, NCF, NW><<<grid, block, 0, st>>>(a);
 }
 
+#ifndef CHEFSI_DL_NCF
+#define CHEFSI_DL_NCF 4
+#endif
+#ifndef CHEFSI_DL_NCF6
+#define CHEFSI_DL_NCF6 2
+#endif
+#ifndef CHEFSI_DL_NCF8
+#define CHEFSI_DL_NCF8 2
+#endif
+template <typename TC, typename TOUT, int EPI, int RB>
+void launch_dl(const StepArgs& a, int ns, hipStream_t st) {
+  // sixteen-column fragments per wave: CHEFSI_DL_NCF up to 64 rows,
+  // CHEFSI_DL_NCF6 up to 96, CHEFSI_DL_NCF8 up to 128, one beyond (register
+  // budget)
+  constexpr int NCF = RB <= 4 ? CHEFSI_DL_NCF : (RB <= 6 ? CHEFSI_DL_NCF6 : (RB <= 8 ? CHEFSI_DL_NCF8 : 1));
+  constexpr int NW = 4;
+  dim3 grid(static_cast<unsigned>(ceil_div(ns, 16 * NW * NCF) * a.M)), block(64 * NW);
+  step_kernel_dl<TC, TOUT, EPI, RB, NCF, NW><<<grid, block, 0, st>>>(a);
+}
+
+// FP64 steps take the direct-operand kernel, FP32 steps the LDS-staged one
+// (at twice the MFMA rate, FP32 operands cannot come as 4-byte lane loads)
+#ifndef CHEFSI_STEP_DL
+#define CHEFSI_STEP_DL 1
+#endif
+template <typename TC, typename TOUT, int EPI, int RB>
+void launch_step(const StepArgs& a, int ns, hipStream_t st) {
+  if constexpr (CHEFSI_STEP_DL != 0 && std::is_same<TC, double>::value)
+    launch_dl<TC, TOUT, EPI, RB>(a, ns, st);
+  else
+    launch_mf<TC, TOUT, EPI, RB>(a, ns, st);
+}
+
 template <typename TC, typename TOUT, int EPI>
 int dispatch_step_mf(const Plan& p, StepArgs a, int ns, hipStream_t st) {
   // one launch per row-block class of elements
@@ -641,22 +836,22 @@ int dispatch_step_mf(const Plan& p, StepArgs a, int ns, hipStream_t st) {
     a.M = p.grp_count[gi];
     if (ceil_div(ns, 64) * a.M > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "step: too many work-groups");
     switch (p.grp_rb[gi]) {
-      case 1: launch_mf<TC, TOUT, EPI, 1>(a, ns, st); break;
-      case 2: launch_mf<TC, TOUT, EPI, 2>(a, ns, st); break;
-      case 3: launch_mf<TC, TOUT, EPI, 3>(a, ns, st); break;
-      case 4: launch_mf<TC, TOUT, EPI, 4>(a, ns, st); break;
-      case 5: launch_mf<TC, TOUT, EPI, 5>(a, ns, st); break;
-      case 6: launch_mf<TC, TOUT, EPI, 6>(a, ns, st); break;
-      case 7: launch_mf<TC, TOUT, EPI, 7>(a, ns, st); break;
-      case 8: launch_mf<TC, TOUT, EPI, 8>(a, ns, st); break;
-      case 9: launch_mf<TC, TOUT, EPI, 9>(a, ns, st); break;
-      case 10: launch_mf<TC, TOUT, EPI, 10>(a, ns, st); break;
-      case 11: launch_mf<TC, TOUT, EPI, 11>(a, ns, st); break;
-      case 12: launch_mf<TC, TOUT, EPI, 12>(a, ns, st); break;
-      case 13: launch_mf<TC, TOUT, EPI, 13>(a, ns, st); break;
-      case 14: launch_mf<TC, TOUT, EPI, 14>(a, ns, st); break;
-      case 15: launch_mf<TC, TOUT, EPI, 15>(a, ns, st); break;
-      case 16: launch_mf<TC, TOUT, EPI, 16>(a, ns, st); break;
+      case 1: launch_step<TC, TOUT, EPI, 1>(a, ns, st); break;
+      case 2: launch_step<TC, TOUT, EPI, 2>(a, ns, st); break;
+      case 3: launch_step<TC, TOUT, EPI, 3>(a, ns, st); break;
+      case 4: launch_step<TC, TOUT, EPI, 4>(a, ns, st); break;
+      case 5: launch_step<TC, TOUT, EPI, 5>(a, ns, st); break;
+      case 6: launch_step<TC, TOUT, EPI, 6>(a, ns, st); break;
+      case 7: launch_step<TC, TOUT, EPI, 7>(a, ns, st); break;
+      case 8: launch_step<TC, TOUT, EPI, 8>(a, ns, st); break;
+      case 9: launch_step<TC, TOUT, EPI, 9>(a, ns, st); break;
+      case 10: launch_step<TC, TOUT, EPI, 10>(a, ns, st); break;
+      case 11: launch_step<TC, TOUT, EPI, 11>(a, ns, st); break;
+      case 12: launch_step<TC, TOUT, EPI, 12>(a, ns, st); break;
+      case 13: launch_step<TC, TOUT, EPI, 13>(a, ns, st); break;
+      case 14: launch_step<TC, TOUT, EPI, 14>(a, ns, st); break;
+      case 15: launch_step<TC, TOUT, EPI, 15>(a, ns, st); break;
+      case 16: launch_step<TC, TOUT, EPI, 16>(a, ns, st); break;
       default: return fail(CHEFSI_ERR_UNSUPPORTED, "step: more than 16 row blocks");
     }
   }
