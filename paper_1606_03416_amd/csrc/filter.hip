@@ -57,6 +57,35 @@ __device__ __forceinline__ int xcd_linear(int b, int nwg) {
   return x * q + (x < r ? x : r) + i;
 }
 
+// Streamed data of the step kernels (the previous block, the output) carries
+// the non-temporal hint, so that the L2 keeps the gathered neighbour rows,
+// which several work-groups read.  (The same hint on the panels, which the
+// work-groups of an element share, costs time.)
+#ifndef CHEFSI_NT_STREAM
+#define CHEFSI_NT_STREAM 1
+#endif
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  if constexpr (CHEFSI_NT_STREAM != 0) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+  if constexpr (CHEFSI_NT_STREAM != 0) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint2 ld_stream(const uint2* p) {
+  const u32x2 v = ld_stream(reinterpret_cast<const u32x2*>(p));
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(uint2* p, uint2 v) {
+  u32x2 w;
+  w.x = v.x;
+  w.y = v.y;
+  st_stream(reinterpret_cast<u32x2*>(p), w);
+}
+
 // float <-> bf16 (round to nearest even; NaN stays NaN)
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -220,8 +249,8 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
       const int64_t o = (row >> 3) * tstride + static_cast<int64_t>(j) * 8 + (row & 7);
       uint2 xp = make_uint2(0, 0), xl = make_uint2(0, 0);
       if (a.prev != nullptr) {
-        xp = *reinterpret_cast<const uint2*>(a.prev + o);
-        if constexpr (X3) xl = *reinterpret_cast<const uint2*>(a.prev + a.mv_lo + o);
+        xp = ld_stream(reinterpret_cast<const uint2*>(a.prev + o));
+        if constexpr (X3) xl = ld_stream(reinterpret_cast<const uint2*>(a.prev + a.mv_lo + o));
       }
       const uint32_t wp[2] = {xp.x, xp.y}, wl[2] = {xl.x, xl.y};
       float v[4];
@@ -242,14 +271,14 @@ __device__ __forceinline__ void step_body_b16(const StepArgsB& a, int K, int ct,
         uint16_t h[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) h[e] = f2bf(v[e]);
-        *reinterpret_cast<uint2*>(out + o) =
-            make_uint2(h[0] | (static_cast<uint32_t>(h[1]) << 16), h[2] | (static_cast<uint32_t>(h[3]) << 16));
+        st_stream(reinterpret_cast<uint2*>(out + o),
+                  make_uint2(h[0] | (static_cast<uint32_t>(h[1]) << 16), h[2] | (static_cast<uint32_t>(h[3]) << 16)));
         if constexpr (X3) {
           uint16_t l[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) l[e] = f2bf(v[e] - bf2f(h[e]));
-          *reinterpret_cast<uint2*>(out + a.mv_lo + o) =
-              make_uint2(l[0] | (static_cast<uint32_t>(l[1]) << 16), l[2] | (static_cast<uint32_t>(l[3]) << 16));
+          st_stream(reinterpret_cast<uint2*>(out + a.mv_lo + o),
+                    make_uint2(l[0] | (static_cast<uint32_t>(l[1]) << 16), l[2] | (static_cast<uint32_t>(l[3]) << 16)));
         }
       }
     }
@@ -470,7 +499,7 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& a, int K, int jb,
         const int64_t g = g0 + min(16 * r + T::row(lane, v), JK - 1);
 #pragma unroll
         for (int q = 0; q < NCF; ++q) {
-          pv[v][q] = (prev != nullptr) ? prev[g * a.ldp + jc[q]] : TC(0);
+          pv[v][q] = (prev != nullptr) ? ld_stream(prev + g * a.ldp + jc[q]) : TC(0);
           if constexpr (EPI == 0) iv[v][q] = in[g * ldi + jc[q]];
         }
       }
@@ -482,7 +511,7 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& a, int K, int jb,
         for (int q = 0; q < NCF; ++q) {
           TC y = (EPI == 2) ? alpha * acc[r][q][v] : alpha * (acc[r][q][v] - cc * iv[v][q]);
           y -= beta * pv[v][q];
-          if (i < JK && jok[q]) out[g * a.ldo + jc[q]] = static_cast<TOUT>(y);
+          if (i < JK && jok[q]) st_stream(out + g * a.ldo + jc[q], static_cast<TOUT>(y));
         }
       }
     }
