@@ -205,6 +205,12 @@ def filter_mode(args, w, P, plan, H, X0d, chefsi, torch):
         pk = PEAK[args.filter_dtype]
         roof = {"kernel": f"cheb_step {args.filter_dtype.upper()}", "bound": "mfma", "achieved": round(achieved, 2),
                 "peak": pk, "unit": "TFLOP/s", "frac": round(achieved / pk, 4), "flops_per_launch": f_step}
+    # HBM bytes from the committed counter summary (full width only: the
+    # counters were taken on all N_s columns)
+    traffic, traffic_src = (None, None) if ns != w.ns else counter_traffic(f"cheb_step_{args.filter_dtype}",
+                                                                           args.workload)
+    roof["traffic"] = traffic
+    roof["traffic_source"] = traffic_src
     out = {
         "mode": "filter", "workload": w.name, "N": P.N, "ns": ns, "filter_degree": m,
         "columns_of": w.ns,
