@@ -303,9 +303,13 @@ __global__ __launch_bounds__(BNT) __attribute__((amdgpu_waves_per_eu(RB <= 4 && 
 #ifndef CHEFSI_B16_CG
 #define CHEFSI_B16_CG 1
 #endif
+#ifndef CHEFSI_B16_CG8
+#define CHEFSI_B16_CG8 8
+#endif
   // groups of CG column tiles of one element run together (its panel is
-  // reused from L2), the groups column-major
-  constexpr int CG = CHEFSI_B16_CG;
+  // reused from L2), the groups column-major; elements of more than 64 rows
+  // have narrower column tiles and larger panels, so more tiles share one
+  constexpr int CG = RB <= 4 ? CHEFSI_B16_CG : CHEFSI_B16_CG8;
   const int nct = (a.ns + CHEFSI_B16_WAVES * 16 * BNC - 1) / (CHEFSI_B16_WAVES * 16 * BNC);
   const int g = id / (a.M * CG);
   const int rem = id - g * (a.M * CG);
@@ -685,8 +689,11 @@ __device__ __forceinline__ void step_body_mf(const StepArgs& a, int K, int ct, T
 #ifndef CHEFSI_MF_CG
 #define CHEFSI_MF_CG 2
 #endif
+#ifndef CHEFSI_MF_CG8
+#define CHEFSI_MF_CG8 8
+#endif
+template <int CG>
 __device__ __forceinline__ void step_tile(int id, int M, int nct, int& e, int& ct) {
-  constexpr int CG = CHEFSI_MF_CG;
   const int g = id / (M * CG);
   const int rem = id - g * (M * CG);
   const int cg = (CG * g + CG <= nct) ? CG : nct - CG * g;
@@ -709,7 +716,7 @@ __global__ __launch_bounds__(64 * NW, CHEFSI_MF_LB) void step_kernel_mf(StepArgs
   static_assert(RB * 16 <= kMaxJ, "row blocks beyond the largest ALB count");
   const int id = xcd_linear(blockIdx.x, gridDim.x);
   int e, ct;
-  step_tile(id, a.M, (a.ns + 16 * NW * NCF - 1) / (16 * NW * NCF), e, ct);
+  step_tile<CHEFSI_MF_CG>(id, a.M, (a.ns + 16 * NW * NCF - 1) / (16 * NW * NCF), e, ct);
   step_body_mf<TC, TOUT, EPI, RB, NCF, NW>(a, a.order[e], ct, sA, sB, sK);
 }
 
@@ -801,7 +808,8 @@ __global__ __launch_bounds__(64 * NW, CHEFSI_DL_LB) void step_kernel_dl(StepArgs
   static_assert(RB * 16 <= kMaxJ, "row blocks beyond the largest ALB count");
   const int id = xcd_linear(blockIdx.x, gridDim.x);
   int e, ct;
-  step_tile(id, a.M, (a.ns + 16 * NW * NCF - 1) / (16 * NW * NCF), e, ct);
+  // elements of more than 64 rows: narrower column tiles, larger panels
+  step_tile<RB <= 4 ? CHEFSI_MF_CG : CHEFSI_MF_CG8>(id, a.M, (a.ns + 16 * NW * NCF - 1) / (16 * NW * NCF), e, ct);
   step_body_dl<TC, TOUT, EPI, RB, NCF, NW>(a, a.order[e], ct, sK);
 }
 
