@@ -14,6 +14,8 @@ this package loads the library and fails loudly if it is missing.
     f, mu = chefsi.occupations(ritz, n_occ, kT)        # Fermi-Dirac occupations
     P = plan.density_blocks(X, f)                      # diagonal density-matrix blocks
     plan.realign(X, V_new, V_old, nr)                  # coefficients onto a new ALB basis
+    st = chefsi.SweepState(X, v0); chefsi.run_cycles(plan, H, st, 2, m)
+    st.save("run.npz", plan)                           # resumable run (bit-identical)
 """
 from ._binding import (  # noqa: F401
     ChefsiError, Plan, orthonormalize, orthonormalize_backward, occupations, library_path, lib, ChefsiLoss, ChebFilter,
@@ -21,3 +23,4 @@ from ._binding import (  # noqa: F401
     OP_FILTER_BACKWARD, OP_LOSS_BACKWARD, OP_DENSITY, OP_LOSS, OP_RAYLEIGH_RITZ_BACKWARD, ERR_NOT_PD, ERR_ARG, ERR_WORKSPACE, ERR_EIG, ERR_HIP,
     ERR_NONFINITE, ERR_UNSUPPORTED,
 )
+from .state import SweepState, run_cycles  # noqa: F401,E402
