@@ -570,12 +570,25 @@ unsigned grid1(int64_t total) {
 // operand rows can be read as aligned 16-byte pairs
 bool vec_ok(const double* X, int64_t ld) { return (ld % 2) == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0; }
 
+// Splits of the reduction for a launch of `tiles` output tiles: at least
+// enough work-groups to fill the chip, then more until the last round of
+// work-groups is nearly full (all work-groups carry equal work, so a round
+// that is 1/8 full costs as much as a full one).  kGemmSlots = 256 CUs x 2
+// resident work-groups of this kernel.
+constexpr int64_t kGemmSlots = 512;
 int choose_splits(int64_t tiles, int64_t k, int64_t kmin) {
-  int64_t s = ceil_div(2048, tiles > 0 ? tiles : 1);
-  const int64_t maxs = ceil_div(k, kmin);
+  if (tiles < 1) tiles = 1;
+  int64_t maxs = ceil_div(k, kmin);
+  if (maxs > 64) maxs = 64;
+  if (maxs < 1) maxs = 1;
+  int64_t s = ceil_div(2048, tiles);
   if (s > maxs) s = maxs;
-  if (s > 64) s = 64;
   if (s < 1) s = 1;
+  for (; s < maxs; ++s) {
+    const int64_t wgs = tiles * s;
+    const int64_t rounds = ceil_div(wgs, kGemmSlots);
+    if (wgs * 100 >= rounds * kGemmSlots * 97) break;   // last round at least ~3/4 full
+  }
   return static_cast<int>(s);
 }
 
