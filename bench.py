@@ -223,6 +223,27 @@ def filter_mode(args, w, P, plan, H, X0d, chefsi, torch):
     print(json.dumps(out), flush=True)
 
 
+def measured_peaks(torch, n=8192, copy_bytes=2 << 30, reps=5):
+    """What this machine reaches on plain vendor work: FP64 TFLOP/s of an n x n x n
+    torch.mm (rocBLAS / hipBLASLt) and GB/s of a device-to-device copy (bytes
+    read + written).  Context for the roofline fractions, which are quoted
+    against the published peaks."""
+    g = torch.Generator(device="cuda").manual_seed(7)
+    A = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    B = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    C = torch.empty_like(A)
+    ms = timed_ms(torch, lambda: torch.mm(A, B, out=C), reps)
+    dgemm = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    del A, B, C
+    x = torch.empty(copy_bytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    ms_c = timed_ms(torch, lambda: y.copy_(x), reps)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"dgemm_tflops": round(dgemm, 2), "dgemm_n": n, "copy_gbs": round(2.0 * copy_bytes / (ms_c * 1e-3) / 1e9, 1)}
+
+
 def timed_ms(torch, fn, reps):
     """Average stream time of fn() over reps back-to-back calls (HIP events on
     the current stream, one untimed call first)."""
@@ -392,6 +413,13 @@ def main():
                      "flops_per_launch": f_step, "avg_launch_ms": round(step_ms, 4)},
         "final_max_resid_wanted": float(resid.max().item()) if resid is not None else None,
     }
+
+    # measured peaks on this machine, outside the timed region: a square FP64
+    # matrix product of the vendor library (torch.mm) and a device copy
+    mp = measured_peaks(torch)
+    result["roofline"]["measured_peaks"] = mp
+    result["roofline"]["frac_of_measured_dgemm"] = round(achieved / mp["dgemm_tflops"], 4)
+    log(f"measured peaks: {mp}")
 
     if not args.no_post:
         log("steps around the cycle: occupations, density-matrix blocks, re-alignment")
