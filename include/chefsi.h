@@ -56,7 +56,7 @@ typedef enum {
   CHEFSI_ERR_ARG = 1,         /* invalid argument (checked on the host)          */
   CHEFSI_ERR_HIP = 2,         /* a HIP runtime / launch error                     */
   CHEFSI_ERR_WORKSPACE = 3,   /* ws is NULL, too small or misaligned              */
-  CHEFSI_ERR_NOT_PD = 4,      /* Cholesky met a pivot <= 0 or not finite          */
+  CHEFSI_ERR_NOT_PD = 4,      /* Cholesky met a pivot <= 0                        */
   CHEFSI_ERR_EIG = 5,         /* the dense eigensolver did not converge           */
   CHEFSI_ERR_NONFINITE = 6,   /* a non-finite value where a finite one is needed  */
   CHEFSI_ERR_UNSUPPORTED = 7  /* valid request the library does not implement     */
@@ -190,7 +190,9 @@ int chefsi_filter_noalloc(chefsi_plan plan, const double* d_H, int m, double a, 
  * (CholeskyQR2); passes = 0 repeats it only when the first factor's condition
  * bound asks for it (the rule of chefsi_sweep; one extra synchronisation).
  * d_U (ns x ns row-major, may be NULL) receives U_2 U_1 (or U_1).
- * Returns CHEFSI_ERR_NOT_PD if a pivot was <= 0 or not finite.  Synchronises
+ * Returns CHEFSI_ERR_NOT_PD if the first failing pivot was <= 0 and
+ * CHEFSI_ERR_NONFINITE if it was not finite (Y held NaN or Inf, or the
+ * factorisation overflowed).  Synchronises
  * the stream to read the pivot status. */
 int chefsi_orthonormalize(int64_t n, int ns, double* d_Y, int64_t ldy, int passes,
                           double* d_U, void* ws, size_t ws_bytes, void* stream);
@@ -236,8 +238,9 @@ int chefsi_rayleigh_ritz(chefsi_plan plan, const double* d_H, const double* d_Yh
  * then returns at once).
  * Errors found on the device: CHEFSI_ERR_NONFINITE (bounds not finite),
  * CHEFSI_ERR_ARG (bounds with a0 < a < b violated, e.g. warm Ritz values at or
- * above a reused upper bound), CHEFSI_ERR_NOT_PD, CHEFSI_ERR_EIG, reported in
- * that order of precedence.  On every error return d_X is unchanged (the final
+ * above a reused upper bound), CHEFSI_ERR_NOT_PD (the first failing Cholesky pivot
+ * <= 0) or CHEFSI_ERR_NONFINITE (it was not finite: X or H held NaN or Inf),
+ * CHEFSI_ERR_EIG, reported in that order of precedence.  On every error return d_X is unchanged (the final
  * rotation checks the status words on the device before writing); d_ritz,
  * d_resid and d_bounds_out are then undefined. */
 int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, int passes,

@@ -267,6 +267,13 @@ int auto_passes_from_bound(double B) {
   return (kAutoLossFactor * eps * B * B <= kAutoLossLimit) ? 1 : 2;
 }
 
+// Error of a Cholesky status word: 1 = a pivot not above zero (the block is
+// rank deficient), 2 = a pivot that is not finite (the block holds NaN or Inf).
+int chol_fail(int h) {
+  if (h == 2) return fail(CHEFSI_ERR_NONFINITE, "Cholesky factorisation met a non-finite pivot (input not finite)");
+  return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+}
+
 // Cholesky-QR, `passes` times: S = Y^T Y (upper triangle, mirrored),
 // U^T U = S, and Yhat = Y U^{-1} as one GEMM with the triangular inverse
 // (its zero part skipped).  The passes alternate between Y and o.B so that
@@ -299,7 +306,7 @@ int run_orth(int64_t n, int ns, double* Y, int64_t ldy, int passes, double* Uout
       CHEFSI_HIP(hipMemcpyAsync(&h, o.cond, sizeof(double), hipMemcpyDeviceToHost, st));
       CHEFSI_HIP(hipMemcpyAsync(&hs0, o.status, sizeof(int), hipMemcpyDeviceToHost, st));
       CHEFSI_HIP(hipStreamSynchronize(st));
-      if (hs0 != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+      if (hs0 != 0) return chol_fail(hs0);
       used = auto_passes_from_bound(h);
     }
   }
@@ -745,7 +752,7 @@ int read_loss_status(const BwdWs& w, double* h_loss, hipStream_t st) {
   CHEFSI_HIP(hipMemcpyAsync(hs, w.status, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   CHEFSI_HIP(hipStreamSynchronize(st));
   if (h_loss) *h_loss = hl;
-  if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+  if (hs[0] != 0) return chol_fail(hs[0]);
   if (hs[1] < 0) return fail(CHEFSI_ERR_NONFINITE, "the projected matrix is not finite");
   if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");
   return CHEFSI_OK;
@@ -1198,7 +1205,10 @@ int chefsi_orthonormalize(int64_t n, int ns, double* d_Y, int64_t ldy, int passe
     Carver c(ws, ws_bytes);
     carve_orth(c, n, ns, o);
     CHEFSI_TRY(run_orth(n, ns, d_Y, ldy, passes, d_U, o, st));
-    return read_status(o.status, CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot", st);
+    int h = 0;
+    CHEFSI_HIP(hipMemcpyAsync(&h, o.status, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHEFSI_HIP(hipStreamSynchronize(st));
+    return h != 0 ? chol_fail(h) : CHEFSI_OK;
   });
 }
 
@@ -1339,7 +1349,7 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
           if (hs0[2] == 1) return fail(CHEFSI_ERR_NONFINITE, "filter bounds are not finite");
           if (hs0[2] != 0)
             return fail(CHEFSI_ERR_ARG, "filter bounds violate a0 < a < b (previous Ritz values above the upper bound?)");
-          if (hs0[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+          if (hs0[0] != 0) return chol_fail(hs0[0]);
           used = auto_passes_from_bound(hcond);
         }
         if (used == 2) {
@@ -1388,7 +1398,7 @@ int chefsi_sweep(chefsi_plan plan, const double* d_H, int m, int filter_dtype, i
       if (hs[2] == 1) return fail(CHEFSI_ERR_NONFINITE, "filter bounds are not finite");
       if (hs[2] != 0)
         return fail(CHEFSI_ERR_ARG, "filter bounds violate a0 < a < b (previous Ritz values above the upper bound?)");
-      if (hs[0] != 0) return fail(CHEFSI_ERR_NOT_PD, "Cholesky factorisation met a non-positive pivot");
+      if (hs[0] != 0) return chol_fail(hs[0]);
       if (hs[1] < 0) return fail(CHEFSI_ERR_NONFINITE, "the projected matrix is not finite");
       if (hs[1] != 0) return fail(CHEFSI_ERR_EIG, "dense eigensolver did not converge");
       return CHEFSI_OK;

@@ -390,13 +390,17 @@ __global__ __launch_bounds__(64) void potf2_inv_kernel(double* S, int64_t lds, i
 #pragma unroll
   for (int r = 0; r < HB; ++r)
     a[r] = (t < w && r <= t) ? S[static_cast<int64_t>(b0 + r) * lds + b0 + t] : (r == t ? 1.0 : 0.0);
-  bool bad = false;
+  // status: 1 = a pivot not above zero, 2 = a pivot that is not finite.  A
+  // failed pivot becomes NaN, which every later pivot inherits, so only the
+  // first failure names the cause: within the block the first failing pivot,
+  // across blocks (launched in order) the first block to fail.
+  int bad = 0;
 #pragma unroll
   for (int j = 0; j < HB; ++j) {
     const double d = rdlane(a[j], j);
     double piv = sqrt(d);
     if (!(d > 0.0) || !isfinite(d)) {
-      bad = true;
+      if (bad == 0) bad = (d == d && !isinf(d)) ? 1 : 2;
       piv = __builtin_nan("");
     }
     a[j] = (t == j) ? piv : (t > j ? a[j] / piv : a[j]);
@@ -422,7 +426,7 @@ __global__ __launch_bounds__(64) void potf2_inv_kernel(double* S, int64_t lds, i
       T[r * w + t] = ti[r];
     }
   }
-  if (t == 0 && bad) atomicExch(status, 1);
+  if (t == 0 && bad) atomicCAS(status, 0, bad);
 }
 
 __global__ void zero_lower_kernel(double* A, int64_t lda, int n) {

@@ -233,6 +233,50 @@ def test_orthonormalize_not_pd(lib, passes):
 
 
 @pytest.mark.parametrize("passes", [0, 1, 2])
+def test_orthonormalize_nonfinite_input(lib, passes):
+    """A NaN or an Inf in Y reaches a Cholesky pivot as a non-finite value:
+    CHEFSI_ERR_NONFINITE, not NOT_PD."""
+    g = np.random.default_rng(2)
+    for bad in (float("nan"), float("inf")):
+        Y = g.standard_normal((300, 20))
+        Y[123, 4] = bad
+        with pytest.raises(lib.ChefsiError) as e:
+            lib.orthonormalize(dev(Y), passes=passes)
+        assert e.value.code == lib.ERR_NONFINITE, (bad, e.value)
+
+
+def test_orthonormalize_workspace_too_small(lib):
+    """A workspace one alignment unit short is refused before any work."""
+    import ctypes
+    n, ns = 300, 20
+    Y = dev(np.random.default_rng(3).standard_normal((n, ns)))
+    need = ctypes.c_size_t(0)
+    assert lib.lib.chefsi_orthonormalize_workspace_bytes(n, ns, 2, ctypes.byref(need)) == 0
+    ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    Y0 = host(Y).copy()
+    rc = lib.lib.chefsi_orthonormalize(n, ns, ctypes.c_void_p(Y.data_ptr()), ns, 2, None,
+                                       ctypes.c_void_p(ws.data_ptr()), need.value - 256, None)
+    assert rc == lib.ERR_WORKSPACE
+    assert b"workspace" in lib.lib.chefsi_last_error()
+    assert np.array_equal(host(Y), Y0)
+
+
+@pytest.mark.parametrize("passes", [0, 1, 2])
+def test_sweep_nonfinite_x_leaves_x_unchanged(lib, passes):
+    """A NaN in X propagates through the filter into the Gram matrix: the sweep
+    returns CHEFSI_ERR_NONFINITE and leaves X as it was."""
+    P = synth.make_problem(synth.TINY)
+    plan = mkplan(lib, P)
+    X0 = synth.make_start_block(P.J, 48)
+    X0[17, 5] = float("nan")
+    X = dev(X0)
+    with pytest.raises(lib.ChefsiError) as e:
+        plan.sweep(dev(P.packed()), X, 10, bounds=(0.5, 6.0, -1.5), passes=passes)
+    assert e.value.code == lib.ERR_NONFINITE
+    assert np.array_equal(host(X), X0, equal_nan=True)
+
+
+@pytest.mark.parametrize("passes", [0, 1, 2])
 def test_sweep_not_pd_leaves_x_unchanged(lib, passes):
     """A zero column makes the filtered block rank deficient: the sweep returns
     NOT_PD and X is untouched (the automatic pass count stops after the first
