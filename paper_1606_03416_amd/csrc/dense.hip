@@ -374,22 +374,36 @@ __device__ __forceinline__ double rdlane(double v, int l) {
 }
 
 // Unblocked Cholesky of one w x w diagonal block (upper, in place) and the
-// inverse of the factor, in registers of one wave: lane t holds column t of
-// the block (padded to 64 with the identity) and, afterwards, column t of the
-// inverse.  Entries of other columns are read with v_readlane.  The factor is
-// written back to S, its inverse to T (w x w, row stride w).
+// inverse of the factor, by one wave: lane t holds column t of the block
+// (padded to HB with the identity) and, afterwards, column t of the inverse.
+// Step j publishes row j of the factor in LDS, from where every lane reads
+// the multipliers of its column's update; the inverse reads the rows of U
+// back from LDS.  Only the upper triangle (a[r], r <= t) is meaningful: the
+// updates run unmasked, and what they leave below the diagonal never enters
+// an entry on or above it (entry (r, t) depends on entries (j, r) and (j, t)
+// with j < r <= t only) and is not written out.  The factor is written back
+// to S, its inverse to T (w x w, row stride w).
 constexpr int CB = 64;   // diagonal blocks of the row-wise triangular solves
 #ifndef CHEFSI_CHOL_CB
-#define CHEFSI_CHOL_CB 32
+#define CHEFSI_CHOL_CB 64
 #endif
 constexpr int HB = CHEFSI_CHOL_CB;   // diagonal block of the blocked Cholesky (<= 64: one lane per column)
+static_assert(HB >= 2 && HB <= 64 && HB % 2 == 0, "one lane per column, rows read in pairs");
 __global__ __launch_bounds__(64) void potf2_inv_kernel(double* S, int64_t lds, int b0, int w, double* T,
                                                        int* status) {
+  __shared__ __attribute__((aligned(16))) double sU[HB][HB];   // sU[j][t] = U[j][t] for t >= j
+  __shared__ double sT[HB][HB];                                // sT[i][t] = U^{-1}[i][t]
+  __shared__ double sR[HB];                                    // 1 / U[j][j]
   const int t = threadIdx.x;
+  const bool col = t < w;
+  const int tc = col ? t : w - 1;   // clamped column: every load is in bounds
   double a[HB];
 #pragma unroll
-  for (int r = 0; r < HB; ++r)
-    a[r] = (t < w && r <= t) ? S[static_cast<int64_t>(b0 + r) * lds + b0 + t] : (r == t ? 1.0 : 0.0);
+  for (int r = 0; r < HB; ++r) {
+    const int rc = r < w ? r : w - 1;
+    const double v = S[static_cast<int64_t>(b0 + rc) * lds + b0 + tc];
+    a[r] = (col && r < w) ? v : (r == t ? 1.0 : 0.0);
+  }
   // status: 1 = a pivot not above zero, 2 = a pivot that is not finite.  A
   // failed pivot becomes NaN, which every later pivot inherits, so only the
   // first failure names the cause: within the block the first failing pivot,
@@ -403,27 +417,48 @@ __global__ __launch_bounds__(64) void potf2_inv_kernel(double* S, int64_t lds, i
       if (bad == 0) bad = (d == d && !isinf(d)) ? 1 : 2;
       piv = __builtin_nan("");
     }
-    a[j] = (t == j) ? piv : (t > j ? a[j] / piv : a[j]);
+    const double rp = 1.0 / piv;
+    a[j] = (t == j) ? piv : a[j] * rp;
+    if (t < HB) sU[j][t] = a[j];
+    if (t == 0) sR[j] = rp;
+    __syncthreads();
+    // a[r] -= U[j][r] U[j][t] for r > j, the multipliers read in pairs
 #pragma unroll
-    for (int r = j + 1; r < HB; ++r) {
-      const double ajr = rdlane(a[j], r);
-      a[r] = (t >= r) ? a[r] - ajr * a[j] : a[r];
+    for (int r = (j + 1) & ~1; r < HB; r += 2) {
+      const double2 u = *reinterpret_cast<const double2*>(&sU[j][r]);
+      if (r > j) a[r] -= u.x * a[j];
+      a[r + 1] -= u.y * a[j];
     }
+    // the updates happen here: sunk to the steps that use them, they would
+    // keep every multiplier read so far alive
+#pragma unroll
+    for (int r = j + 1; r < HB; ++r) asm volatile("" : "+v"(a[r]));
   }
   // column t of U^{-1}: T[i][t] = (delta_it - sum_{k>i} U[i][k] T[k][t]) / U[i][i]
+  // (zero for i > t), the sum in four interleaved partial sums
   double ti[HB];
 #pragma unroll
   for (int i = HB - 1; i >= 0; --i) {
-    double acc = (t == i) ? 1.0 : 0.0;
+    double p[4] = {(t == i) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = i + 1; k < HB; ++k) acc -= rdlane(a[i], k) * ti[k];
-    ti[i] = acc / rdlane(a[i], i);
+    for (int k = (i + 1) & ~1; k < HB; k += 2) {
+      const double2 u = *reinterpret_cast<const double2*>(&sU[i][k]);
+      if (k > i) p[(k - i - 1) & 3] -= u.x * ti[k];
+      p[(k - i) & 3] -= u.y * ti[k + 1];
+    }
+    ti[i] = ((p[0] + p[1]) + (p[2] + p[3])) * sR[i];
+    if (t < HB) sT[i][t] = ti[i];
+    // keep each row's LDS reads in its own iteration (hoisted, they would
+    // hold every row of U in registers at once)
+    __builtin_amdgcn_sched_barrier(0);
   }
-#pragma unroll
-  for (int r = 0; r < HB; ++r) {
-    if (r < w && t < w) {
-      S[static_cast<int64_t>(b0 + r) * lds + b0 + t] = (r <= t) ? a[r] : 0.0;
-      T[r * w + t] = ti[r];
+  __syncthreads();
+  // both results leave through LDS, row by row (a rolled loop: per-row
+  // addresses are not held in registers)
+  for (int r = 0; r < w; ++r) {
+    if (col) {
+      S[static_cast<int64_t>(b0 + r) * lds + b0 + t] = (r <= t) ? sU[r][t] : 0.0;
+      T[r * w + t] = sT[r][t];
     }
   }
   if (t == 0 && bad) atomicCAS(status, 0, bad);
