@@ -47,6 +47,9 @@ struct GemmArgs {
   int tri_tiles;    // upper_only: number of upper-triangle tiles (1-D grid)
   int tn_tiles;     // upper_only: tiles per row of the square tile grid
   const int* skip;  // if set and any of skip[0..2] is nonzero, write nothing
+  // batched launch (bsc != 0): blockIdx.z is the batch index and problem z
+  // reads A + z bsa, B + z bsb and writes C + z bsc (no reduction splits)
+  int64_t bsa = 0, bsb = 0, bsc = 0;
 };
 
 // One GT x GK operand chunk, 16 bytes (two doubles) per thread per load, four
@@ -241,6 +244,15 @@ __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
   }
   if (g.upper_only && ti > tj) return;
   if (g.skip != nullptr && (g.skip[0] | g.skip[1] | g.skip[2]) != 0) return;
+  const double* gA = g.A;
+  const double* gB = g.B;
+  double* gC = g.C;
+  if (g.bsc != 0) {
+    gA += split * g.bsa;
+    gB += split * g.bsb;
+    gC += split * g.bsc;
+    split = 0;
+  }
   __shared__ __attribute__((aligned(16))) double sA[2 * GBUF];
   __shared__ __attribute__((aligned(16))) double sB[2 * GBUF];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -254,7 +266,7 @@ __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
-  tile_mma<A_KMAJOR, true, VEC>(g.A, g.lda, g.B, g.ldb, g.m, g.n, kbeg, kend, i0, j0, sA, sB, acc);
+  tile_mma<A_KMAJOR, true, VEC>(gA, g.lda, gB, g.ldb, g.m, g.n, kbeg, kend, i0, j0, sA, sB, acc);
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -268,8 +280,8 @@ __global__ __launch_bounds__(GNT, 2) void gemm_kernel(GemmArgs g) {
             g.part[(static_cast<int64_t>(split) * g.m + i) * g.n + j] = acc[p][q][v];
           } else {
             double val = g.alpha * acc[p][q][v];
-            if (g.beta != 0.0) val += g.beta * g.C[i * g.ldc + j];
-            g.C[i * g.ldc + j] = val;
+            if (g.beta != 0.0) val += g.beta * gC[i * g.ldc + j];
+            gC[i * g.ldc + j] = val;
           }
         }
       }
@@ -689,6 +701,32 @@ int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   return CHEFSI_OK;
 }
 
+// `count` products C_z = alpha A_z B_z + beta C_z of one shape, operand z at
+// A + z sa, B + z sb, C + z sc, in one launch.
+int gemm_nn_batched(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda, int64_t sa,
+                    const double* B, int64_t ldb, int64_t sb, double beta, double* C, int64_t ldc, int64_t sc,
+                    int64_t count, hipStream_t st, bool b_upper) {
+  if (m <= 0 || n <= 0 || count <= 0) return CHEFSI_OK;
+  if (count == 1) return gemm_nn(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, st, b_upper);
+  const int64_t tm = ceil_div(m, GT), tn = ceil_div(n, GT);
+  if (tm > 65535 || count > 65535) return fail(CHEFSI_ERR_ARG, "gemm_nn_batched: grid too large");
+  if (sc == 0) return fail(CHEFSI_ERR_ARG, "gemm_nn_batched: the outputs must not overlap");
+  GemmArgs g{A, lda, B, ldb, C, ldc, m, n, k, alpha, beta, round_up(k > 0 ? k : 1, GK), nullptr, false, b_upper,
+             0, 0, nullptr};
+  g.bsa = sa;
+  g.bsb = sb;
+  g.bsc = sc;
+  dim3 grid(static_cast<unsigned>(tn), static_cast<unsigned>(tm), static_cast<unsigned>(count));
+  // every operand pointer of the batch is aligned like the first when the strides are even
+  const bool vec = vec_ok(A, lda) && vec_ok(B, ldb) && sa % 2 == 0 && sb % 2 == 0;
+  if (vec)
+    gemm_kernel<false, true><<<grid, GNT, 0, st>>>(g);
+  else
+    gemm_kernel<false, false><<<grid, GNT, 0, st>>>(g);
+  CHEFSI_LAUNCHED("gemm_nn_batched");
+  return CHEFSI_OK;
+}
+
 int launch_symmetrize(double* A, int64_t lda, int n, int mode, hipStream_t st) {
   symmetrize_kernel<<<grid1(static_cast<int64_t>(n) * n), 256, 0, st>>>(A, lda, n, mode);
   CHEFSI_LAUNCHED("symmetrize");
@@ -788,17 +826,30 @@ __global__ __launch_bounds__(64) void trtri_diag_kernel(const double* U, int64_t
     if (j < w) T[static_cast<int64_t>(r0 + r) * ldt + r0 + j] = Ts[r][j];
 }
 
-// Off-diagonal blocks of T = U^{-1} by recursive halving:
-//   [U11 U12; 0 U22]^{-1} = [T11, -T11 U12 T22; 0, T22].
+// Off-diagonal blocks of T = U^{-1}, bottom up: once the diagonal blocks of
+// order b are inverted, each aligned pair of them, [r0, r0+b) and
+// [r0+b, r0+b+m2) with m2 <= b, is joined by
+//   [U11 U12; 0 U22]^{-1} = [T11, -T11 U12 T22; 0, T22]
+// (W = U12 T22, then T12 = -T11 W).  The full pairs of one order run as one
+// batched launch per product, a ragged last pair on its own; then b doubles.
+// W holds at most n^2/4 doubles: pairs * b^2 <= n b / 2 with 2b <= n, and
+// b * m2 <= b (n - b) for the ragged pair.
 int trtri_offdiag(const double* U, int64_t ldu, double* T, int64_t ldt, int n, double* W, hipStream_t st) {
-  if (n <= CB) return CHEFSI_OK;
-  const int h = CB * static_cast<int>(ceil_div(n, 2 * CB));
-  CHEFSI_TRY(trtri_offdiag(U, ldu, T, ldt, h, W, st));
-  CHEFSI_TRY(trtri_offdiag(U + static_cast<int64_t>(h) * ldu + h, ldu, T + static_cast<int64_t>(h) * ldt + h, ldt,
-                           n - h, W, st));
-  CHEFSI_TRY(gemm_nn(h, n - h, n - h, 1.0, U + h, ldu, T + static_cast<int64_t>(h) * ldt + h, ldt, 0.0, W, n - h, st,
-                     true));
-  CHEFSI_TRY(gemm_nn(h, n - h, h, -1.0, T, ldt, W, n - h, 0.0, T + h, ldt, st));
+  for (int64_t b = CB; b < n; b *= 2) {
+    const int64_t pairs = n / (2 * b);
+    if (pairs > 0) {
+      const int64_t su = 2 * b * ldu + 2 * b, stt = 2 * b * ldt + 2 * b;
+      CHEFSI_TRY(gemm_nn_batched(b, b, b, 1.0, U + b, ldu, su, T + b * ldt + b, ldt, stt, 0.0, W, b, b * b, pairs, st,
+                                 true));
+      CHEFSI_TRY(gemm_nn_batched(b, b, b, -1.0, T, ldt, stt, W, b, b * b, 0.0, T + b, ldt, stt, pairs, st, false));
+    }
+    const int64_t r0 = pairs * 2 * b, m2 = n - r0 - b;
+    if (m2 > 0) {
+      CHEFSI_TRY(gemm_nn(b, m2, m2, 1.0, U + r0 * ldu + r0 + b, ldu, T + (r0 + b) * ldt + r0 + b, ldt, 0.0, W, m2,
+                         st, true));
+      CHEFSI_TRY(gemm_nn(b, m2, b, -1.0, T + r0 * ldt + r0, ldt, W, m2, 0.0, T + r0 * ldt + r0 + b, ldt, st));
+    }
+  }
   return CHEFSI_OK;
 }
 
