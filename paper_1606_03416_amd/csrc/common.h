@@ -183,6 +183,11 @@ int gemm_tn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
 int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t st,
             bool b_upper = false, const int* skip_if = nullptr);
+// Upper triangle (j >= i) of a row-major n x n C += alpha (A1 B1^T + A2 B2^T),
+// the four operands n x k row-major with stride ld; entries below the
+// diagonal are not touched.
+int syr2k_upper(int64_t n, int64_t k, double alpha, const double* A1, const double* B1, const double* A2,
+                const double* B2, int64_t ld, double* C, int64_t ldc, hipStream_t st);
 // T = U^{-1} for an upper triangular n x n U (T upper triangular); W is
 // scratch of (n/2 + 64)^2 doubles.
 int upper_inverse(const double* U, int n, double* T, double* W, hipStream_t st);
@@ -226,8 +231,8 @@ int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, in
             void* d_ws, size_t ws_bytes, hipStream_t st, const int* skip = nullptr);
 // Householder tridiagonalisation (tridiag.hip), LAPACK lower format
 size_t tridiag_scratch_bytes(int n);
-int tridiag_lower(void* rocblas_h, double* A, int64_t lda, int n, double* D, double* E, double* tau,
-                  void* scratch, hipStream_t st);
+int tridiag_lower(double* A, int64_t lda, int n, double* D, double* E, double* tau, void* scratch,
+                  hipStream_t st);
 // Back-transformation (backtr.hip): out = Q C for the reflectors of
 // tridiag_lower in A and tau; C (n x n column-major, leading dimension n, the
 // eigenvectors of T) is overwritten; out is column-major with leading

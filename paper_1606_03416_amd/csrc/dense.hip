@@ -341,6 +341,59 @@ __global__ __launch_bounds__(GNT, 2) void sddmm_kernel(SddmmArgs g) {
     }
 }
 
+// Symmetric rank-2k update of the upper triangle of a row-major n x n C:
+//   C[i][j] += alpha * sum_l (A1[i][l] B1[j][l] + A2[i][l] B2[j][l]),  j >= i,
+// all four operands n x k row-major with stride ld.  One work-group per
+// upper-triangle tile; both products accumulate in the same registers, so C
+// is read and written once.
+struct Syr2kArgs {
+  const double* A1;
+  const double* B1;
+  const double* A2;
+  const double* B2;
+  int64_t ld;
+  double* C;
+  int64_t ldc;
+  int64_t n, k;
+  double alpha;
+  int tn_tiles;
+};
+
+template <bool VEC>
+__global__ __launch_bounds__(GNT, 2) void syr2k_upper_kernel(Syr2kArgs g) {
+  int t = blockIdx.x, ti = 0, rowlen = g.tn_tiles;
+  while (t >= rowlen) {
+    t -= rowlen;
+    ++ti;
+    --rowlen;
+  }
+  const int tj = ti + t;
+  __shared__ __attribute__((aligned(16))) double sA[2 * GBUF];
+  __shared__ __attribute__((aligned(16))) double sB[2 * GBUF];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = static_cast<int64_t>(ti) * GT, j0 = static_cast<int64_t>(tj) * GT;
+  d4 acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+  // every wave's last LDS read of the first product precedes its final
+  // barrier, so the second product may refill the buffers at once
+  tile_mma<false, false, VEC>(g.A1, g.ld, g.B1, g.ld, g.n, g.n, 0, g.k, i0, j0, sA, sB, acc);
+  tile_mma<false, false, VEC>(g.A2, g.ld, g.B2, g.ld, g.n, g.n, 0, g.k, i0, j0, sA, sB, acc);
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + out_row(wave, lane, p, v);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = j0 + out_col(wave, lane, q);
+        if (j >= i && j < g.n) g.C[i * g.ldc + j] += g.alpha * acc[p][q][v];
+      }
+    }
+}
+
 __global__ void split_reduce_kernel(const double* part, int splits, int64_t m, int64_t n,
                                     double alpha, double beta, double* C, int64_t ldc,
                                     bool upper_only) {
@@ -698,6 +751,21 @@ int gemm_nn(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int6
   else
     gemm_kernel<false, false><<<grid, GNT, 0, st>>>(g);
   CHEFSI_LAUNCHED("gemm_nn");
+  return CHEFSI_OK;
+}
+
+int syr2k_upper(int64_t n, int64_t k, double alpha, const double* A1, const double* B1, const double* A2,
+                const double* B2, int64_t ld, double* C, int64_t ldc, hipStream_t st) {
+  if (n <= 0 || k <= 0) return CHEFSI_OK;
+  const int64_t tn = ceil_div(n, GT);
+  if (tn * (tn + 1) / 2 > 0x7fffffff) return fail(CHEFSI_ERR_ARG, "syr2k_upper: too many tiles");
+  Syr2kArgs g{A1, B1, A2, B2, ld, C, ldc, n, k, alpha, static_cast<int>(tn)};
+  const unsigned grid = static_cast<unsigned>(tn * (tn + 1) / 2);
+  if (vec_ok(A1, ld) && vec_ok(B1, ld) && vec_ok(A2, ld) && vec_ok(B2, ld))
+    syr2k_upper_kernel<true><<<grid, GNT, 0, st>>>(g);
+  else
+    syr2k_upper_kernel<false><<<grid, GNT, 0, st>>>(g);
+  CHEFSI_LAUNCHED("syr2k_upper");
   return CHEFSI_OK;
 }
 

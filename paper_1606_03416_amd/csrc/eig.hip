@@ -118,7 +118,7 @@ int eig_sym(Plan& p, double* A, int64_t lda, int n, double* d_w, double* d_E, in
   nonfinite_scan_kernel<<<grid_for(nn), 256, 0, st>>>(A, lda, n, flag);
   identity_if_kernel<<<grid_for(nn), 256, 0, st>>>(A, lda, n, flag, skip);
   CHEFSI_LAUNCHED("eig input guard");
-  CHEFSI_TRY(tridiag_lower(h, A, lda, n, d_w, d_E, tau, scratch, st));
+  CHEFSI_TRY(tridiag_lower(A, lda, n, d_w, d_E, tau, scratch, st));
   rocblas_status s = rocsolver_dstedc(h, rocblas_evect_tridiagonal, n, d_w, d_E, Z, n, d_info);
   if (s != rocblas_status_success)
     return fail(CHEFSI_ERR_EIG, std::string("rocsolver_dstedc: ") + rocblas_status_to_string(s));

@@ -32,8 +32,6 @@
 // Every partial sum has a fixed owner and a fixed reduction order, so the
 // result does not depend on scheduling.  Column-major storage, A(r, c) at
 // A[r + c * lda]; only the lower triangle is read or written.
-#include <rocblas/rocblas.h>
-
 #include "common.h"
 
 namespace chefsi {
@@ -454,8 +452,8 @@ size_t tridiag_scratch_bytes(int n) {
   return static_cast<size_t>(elems) * sizeof(double);
 }
 
-int tridiag_lower(void* rocblas_h, double* A, int64_t lda, int n, double* D, double* E, double* tau,
-                  void* scratch, hipStream_t st) {
+int tridiag_lower(double* A, int64_t lda, int n, double* D, double* E, double* tau, void* scratch,
+                  hipStream_t st) {
   if (n <= 0) return CHEFSI_OK;
   TdArgs a{};
   a.A = A;
@@ -480,8 +478,6 @@ int tridiag_lower(void* rocblas_h, double* A, int64_t lda, int n, double* D, dou
   a.D = D;
   a.E = E;
   a.tau = tau;
-  rocblas_handle h = static_cast<rocblas_handle>(rocblas_h);
-  const double minus1 = -1.0, one = 1.0;
 
   td_start_kernel<<<static_cast<unsigned>(a.nT), 64, 0, st>>>(a, 0);
   CHEFSI_LAUNCHED("td_start");
@@ -497,12 +493,12 @@ int tridiag_lower(void* rocblas_h, double* A, int64_t lda, int n, double* D, dou
       CHEFSI_LAUNCHED("td_update");
     }
     const int n2 = n - p1;
-    rocblas_status rs = rocblas_dsyr2k(h, rocblas_fill_lower, rocblas_operation_transpose, n2, p1 - p0,
-                                       &minus1, a.Vp + static_cast<int64_t>(p1) * kNB, kNB,
-                                       a.Wp + static_cast<int64_t>(p1) * kNB, kNB, &one,
-                                       A + p1 + static_cast<int64_t>(p1) * lda, static_cast<rocblas_int>(lda));
-    if (rs != rocblas_status_success)
-      return fail(CHEFSI_ERR_EIG, std::string("rocblas_dsyr2k: ") + rocblas_status_to_string(rs));
+    // A22 -= V W^T + W V^T on the lower triangle of the trailing block: in
+    // the row-major view (A^T, row stride lda) that is the upper triangle
+    // updated with W V^T + V W^T
+    CHEFSI_TRY(syr2k_upper(n2, p1 - p0, -1.0, a.Wp + static_cast<int64_t>(p1) * kNB, a.Vp + static_cast<int64_t>(p1) * kNB,
+                           a.Vp + static_cast<int64_t>(p1) * kNB, a.Wp + static_cast<int64_t>(p1) * kNB, kNB,
+                           A + p1 + static_cast<int64_t>(p1) * lda, lda, st));
     td_start_kernel<<<static_cast<unsigned>(a.nT - p1 / kTB), 64, 0, st>>>(a, p1);
     CHEFSI_LAUNCHED("td_start");
     p0 = p1;
