@@ -22,7 +22,11 @@
 namespace chefsi {
 namespace {
 
-constexpr int kBB = 256;   // reflectors per block reflector
+#ifndef CHEFSI_BACKTR_BB
+#define CHEFSI_BACKTR_BB 512
+#endif
+constexpr int kBB = CHEFSI_BACKTR_BB;   // reflectors per block reflector (a multiple of 64)
+static_assert(kBB % 64 == 0, "whole transpose tiles per block");
 constexpr int kXT = 64;    // transpose tile edge
 constexpr int kSplitK = 256;   // fewest rows per split-K part of V^T C (its result has few tiles)
 

@@ -375,12 +375,12 @@ def test_rayleigh_ritz_matches_oracle(lib, name, ns):
     assert np.linalg.norm(Xn.T @ Xn - np.eye(ns), 2) <= 1e-12
 
 
-@pytest.mark.parametrize("ns", [1, 2, 3, 63, 64, 65, 127, 128, 129, 256, 257, 258])
+@pytest.mark.parametrize("ns", [1, 2, 3, 63, 64, 65, 127, 128, 129, 256, 257, 258, 512, 513, 514])
 def test_rayleigh_ritz_subspace_sizes(lib, ns):
-    """Projected matrices of order 1 to 258: one and several 64 x 64 tiles of
+    """Projected matrices of order 1 to 514: one and several 64 x 64 tiles of
     the tridiagonal reduction, panel boundaries at 64 and 128, ragged tails,
-    and one full, one full plus one single-reflector block of the
-    back-transformation (blocks of 256 reflectors)."""
+    and a ragged, a full, and a full plus a single-reflector block of the
+    back-transformation (blocks of 512 reflectors)."""
     P = PROBLEMS["odd_3x3x3_nb40"]()
     H = oracle.assemble_dense(P.grid, P.stencil, P.J, P.blocks)
     Yh, _ = np.linalg.qr(np.random.default_rng(ns).standard_normal((P.N, ns)))
