@@ -868,30 +868,39 @@ int sddmm_accumulate(const Plan& p, const double* A, int64_t lda, const double* 
 }
 
 // Inverse of the upper triangular diagonal 64 x 64 blocks of U, one block per
-// work-group: thread j forms column j of the block inverse by back
-// substitution.
+// work-group of one wave: the block's rows go to LDS (a short last block is
+// padded with the identity), lane t keeps column t of the inverse in
+// registers, T[i][t] = (delta_it - sum_{k>i} U[i][k] T[k][t]) / U[i][i] from
+// the last row up (four interleaved partial sums), and the result leaves
+// through LDS row by row.  Only the upper triangle of U is read.
 __global__ __launch_bounds__(64) void trtri_diag_kernel(const double* U, int64_t ldu, double* T, int64_t ldt,
                                                         int n) {
-  __shared__ double Us[CB][CB + 1];
+  __shared__ __attribute__((aligned(16))) double Us[CB][CB];
   __shared__ double Ts[CB][CB + 1];
   const int r0 = blockIdx.x * CB;
   const int w = (n - r0) < CB ? (n - r0) : CB;
-  const int j = threadIdx.x;
-  for (int r = 0; r < w; ++r)
-    if (j < w) Us[r][j] = U[static_cast<int64_t>(r0 + r) * ldu + r0 + j];
+  const int t = threadIdx.x;
+  for (int r = 0; r < CB; ++r)
+    Us[r][t] = (r < w && t < w) ? U[static_cast<int64_t>(r0 + r) * ldu + r0 + t] : (r == t ? 1.0 : 0.0);
   __syncthreads();
-  if (j < w) {
-    for (int r = 0; r < w; ++r) Ts[r][j] = 0.0;
-    Ts[j][j] = 1.0 / Us[j][j];
-    for (int i = j - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int k = i + 1; k <= j; ++k) acc += Us[i][k] * Ts[k][j];
-      Ts[i][j] = -acc / Us[i][i];
+  double ti[CB];
+#pragma unroll
+  for (int i = CB - 1; i >= 0; --i) {
+    double p[4] = {(t == i) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = (i + 1) & ~1; k < CB; k += 2) {
+      const double2 u = *reinterpret_cast<const double2*>(&Us[i][k]);
+      if (k > i) p[(k - i - 1) & 3] -= u.x * ti[k];
+      p[(k - i) & 3] -= u.y * ti[k + 1];
     }
+    ti[i] = ((p[0] + p[1]) + (p[2] + p[3])) / Us[i][i];
+    Ts[i][t] = ti[i];
+    // keep each row's LDS reads in its own iteration
+    __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
   for (int r = 0; r < w; ++r)
-    if (j < w) T[static_cast<int64_t>(r0 + r) * ldt + r0 + j] = Ts[r][j];
+    if (t < w) T[static_cast<int64_t>(r0 + r) * ldt + r0 + t] = Ts[r][t];
 }
 
 // Off-diagonal blocks of T = U^{-1}, bottom up: once the diagonal blocks of
