@@ -57,6 +57,9 @@ __global__ __launch_bounds__(LT) void lanczos_init_kernel(const double* v0, int6
 // interleaved), and the parts are added in a fixed order (HBM-bound; the
 // panel is read once).
 constexpr int kSpmvThreads = 256;
+// reduction rows of one element: at most 7 neighbours of up to kMaxJ ALBs
+// each, padded to the step kernels' chunk of 16
+constexpr int kMaxSpmvK = ((7 * kMaxJ + 15) / 16) * 16;
 
 __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(const double* panel, const int64_t* poff,
                                                             const int32_t* kpad, const int64_t* koff,
@@ -69,20 +72,29 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(const double* panel,
   const int splits = (JK <= 64) ? 4 : (JK <= 128 ? 2 : 1);
   const int rows = kSpmvThreads / splits;
   const int i = threadIdx.x % rows, sp = threadIdx.x / rows;
-  double a0 = 0.0, a1 = 0.0;
+  const int kp = kpad[K];
+  const int32_t* km = kmap + koff[K];
+  // the element's gathered x entries first (one pass over its reduction
+  // rows), so that the product loop reads only the panel from memory
+  __shared__ double xs[kMaxSpmvK];
+  for (int k = threadIdx.x; k < kp; k += kSpmvThreads) {
+    const int g = km[k];
+    xs[k] = g >= 0 ? x[g] : 0.0;
+  }
+  __syncthreads();
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (i < JK) {
     const int JP = rb[K] * 16;
     const double* pk = panel + poff[K] + i;
-    const int32_t* km = kmap + koff[K];
-    const int kp = kpad[K];
-#pragma unroll 4
-    for (int k = 2 * sp; k < kp; k += 2 * splits) {
-      const int g0 = km[k], g1 = km[k + 1];
-      a0 += pk[static_cast<int64_t>(k) * JP] * (g0 >= 0 ? x[g0] : 0.0);
-      a1 += pk[static_cast<int64_t>(k + 1) * JP] * (g1 >= 0 ? x[g1] : 0.0);
+#pragma unroll 2
+    for (int k = 4 * sp; k < kp; k += 4 * splits) {
+      a0 += pk[static_cast<int64_t>(k) * JP] * xs[k];
+      a1 += pk[static_cast<int64_t>(k + 1) * JP] * xs[k + 1];
+      a2 += pk[static_cast<int64_t>(k + 2) * JP] * xs[k + 2];
+      a3 += pk[static_cast<int64_t>(k + 3) * JP] * xs[k + 3];
     }
   }
-  red[threadIdx.x] = a0 + a1;
+  red[threadIdx.x] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   if (sp == 0 && i < JK) {
     double s = 0.0;
