@@ -214,11 +214,49 @@ __global__ void lz_check_stop(LanczosState* stt, int j) {
   }
 }
 
-// Eigenpairs of the tridiagonal T (order n <= 64) by parallel Jacobi: each
-// round rotates n/2 disjoint (p, q) pairs of a round-robin tournament, so a
-// sweep of n-1 rounds meets every pair once; thread t applies the rotations to
-// row / column t.  Then the bounds policy on thread 0.  ritz == nullptr
-// selects the first-cycle rule.
+// Largest eigenvalue of the symmetric tridiagonal T_k (diagonal al[0..n-1],
+// off-diagonal be[0..n-2]) by bisection on Sturm counts: count(x) = number of
+// eigenvalues below x = number of negative pivots of the LDL^T factorisation
+// of T_k - xI.  The bracket starts from the Gershgorin interval and halves
+// until it cannot shrink; the upper end is returned (at most one unit in the
+// last place above the eigenvalue).
+__device__ double tridiag_max_eig(const double* al, const double* be, int n) {
+  if (n == 1) return al[0];
+  double gl = al[0], gu = al[0], b2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < n ? fabs(be[i]) : 0.0);
+    gl = fmin(gl, al[i] - r);
+    gu = fmax(gu, al[i] + r);
+    if (i + 1 < n) b2 = fmax(b2, be[i] * be[i]);
+  }
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, b2);
+  double lo = gl, hi = gu + fmax(1e-3 * (gu - gl), 1e-12 * fmax(fabs(gu), 1.0));
+  for (int it = 0; it < 2200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    int c = 0;
+    double q = al[0] - mid;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+    for (int i = 1; i < n; ++i) {
+      q = al[i] - mid - be[i - 1] * be[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      c += q < 0.0;
+    }
+    if (c == n) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+// Bounds from the Lanczos tridiagonal T: b = (largest eigenvalue of T, by
+// bisection) + the last beta in every cycle.  The first-cycle rule (ritz ==
+// nullptr) also needs every eigenvalue and the first component of every
+// eigenvector: eigenpairs of T (order n <= 64) by parallel Jacobi, each round
+// rotating n/2 disjoint (p, q) pairs of a round-robin tournament (a sweep of
+// n-1 rounds meets every pair once), thread t applying the rotations to
+// row / column t.  Warm cycles take a and a0 from the previous Ritz values
+// and skip the Jacobi sweeps.
 __global__ __launch_bounds__(64) void lanczos_bounds_kernel(const LanczosState* stt, const double* ritz, int ns,
                                                             double frac, double* bounds) {
   __shared__ double T[kMaxLanczos][kMaxLanczos + 1];
@@ -226,6 +264,7 @@ __global__ __launch_bounds__(64) void lanczos_bounds_kernel(const LanczosState* 
   __shared__ double cs[kMaxLanczos / 2][2];
   __shared__ int pq[kMaxLanczos / 2][2];
   __shared__ int done;
+  __shared__ double sal[kMaxLanczos], sbe[kMaxLanczos];   // alpha, beta of T
   const int t = threadIdx.x;
   const int n = stt->steps;
   const int m = (n + 1) & ~1;   // players incl. an idle one when n is odd
@@ -235,6 +274,8 @@ __global__ __launch_bounds__(64) void lanczos_bounds_kernel(const LanczosState* 
   }
   __syncthreads();
   if (t < n) {
+    sal[t] = stt->alpha[t];
+    sbe[t] = stt->beta[t];
     T[t][t] = stt->alpha[t];
     if (t + 1 < n) {
       T[t][t + 1] = stt->beta[t];
@@ -246,7 +287,8 @@ __global__ __launch_bounds__(64) void lanczos_bounds_kernel(const LanczosState* 
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) fro += T[i][j] * T[i][j];
   fro = sqrt(fro);
-  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+  const bool cold = (ritz == nullptr);
+  for (int sweep = 0; sweep < 60 && n > 1 && cold; ++sweep) {
     if (t == 0) {
       double off = 0.0;
       for (int i = 0; i < n; ++i)
@@ -324,26 +366,24 @@ __global__ __launch_bounds__(64) void lanczos_bounds_kernel(const LanczosState* 
     }
   }
   if (t != 0) return;
-  // ascending order of the diagonal (stable selection)
-  int idx[kMaxLanczos];
-  for (int i = 0; i < n; ++i) idx[i] = i;
-  for (int i = 1; i < n; ++i) {
-    const int v = idx[i];
-    int j = i - 1;
-    while (j >= 0 && T[idx[j]][idx[j]] > T[v][v]) {
-      idx[j + 1] = idx[j];
-      --j;
-    }
-    idx[j + 1] = v;
-  }
-  const double theta_min = T[idx[0]][idx[0]];
-  const double theta_max = T[idx[n - 1]][idx[n - 1]];
-  const double b = theta_max + stt->beta[n - 1];
+  const double b = tridiag_max_eig(sal, sbe, n) + sbe[n - 1];
   double a, a0;
-  if (ritz != nullptr) {
+  if (!cold) {
     a = ritz[ns - 1];
     a0 = ritz[0];
   } else {
+    // ascending order of the diagonal (stable selection)
+    int idx[kMaxLanczos];
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    for (int i = 1; i < n; ++i) {
+      const int v = idx[i];
+      int j = i - 1;
+      while (j >= 0 && T[idx[j]][idx[j]] > T[v][v]) {
+        idx[j + 1] = idx[j];
+        --j;
+      }
+      idx[j + 1] = v;
+    }
     double cum = 0.0;
     int js = n - 1;
     for (int i = 0; i < n; ++i) {
@@ -355,7 +395,7 @@ __global__ __launch_bounds__(64) void lanczos_bounds_kernel(const LanczosState* 
       }
     }
     a = T[idx[js]][idx[js]];
-    a0 = theta_min;
+    a0 = T[idx[0]][idx[0]];
   }
   if (a0 >= a - 1e-12 * fabs(b)) a0 = a - 1e-3 * (b - a);
   bounds[0] = a;
